@@ -1,0 +1,174 @@
+"""Independent checkers used to pin the oracle.
+
+None of these call the oracle or share its code.  Each follows a different
+route to the same numbers:
+
+* ``brute_*``: the full 2^n x 2^n unitary built from Kronecker products of
+  ``scipy.linalg.expm(-i theta P / 2)`` factors (qubit 0 is the right-most
+  factor), entanglers built from projector sums; observables as Kronecker
+  products of Z and I.
+* ``bloch_*``: entangler-free circuits stay product states; each qubit's Bloch
+  vector is rotated by SO(3) matrices and <Z_S> is the product of z parts.
+* ``heisenberg_mask``: a CNOT conjugates a Z string into another Z string.
+* ``classical_*``: with every angle in {0, pi} the state is one basis vector
+  up to a phase.
+"""
+from __future__ import annotations
+
+import math
+from functools import reduce
+
+import numpy as np
+import scipy.linalg as sla
+
+import workloads as W
+
+PX = np.array([[0, 1], [1, 0]], dtype=complex)
+PY = np.array([[0, -1j], [1j, 0]], dtype=complex)
+PZ = np.array([[1, 0], [0, -1]], dtype=complex)
+I2 = np.eye(2, dtype=complex)
+P0 = np.array([[1, 0], [0, 0]], dtype=complex)
+P1 = np.array([[0, 0], [0, 1]], dtype=complex)
+PAULI = {W.RX: PX, W.RY: PY, W.RZ: PZ}
+
+
+def kron_on(n, ops: dict):
+    """Kronecker product over qubits n-1 ... 0 with ops[q] on qubit q."""
+    return reduce(np.kron, [ops.get(q, I2) for q in reversed(range(n))])
+
+
+def _angle(g, x_b, w):
+    return x_b[g[4]] if g[3] == W.SRC_INPUT else w[g[4]]
+
+
+def brute_unitary(circ, x_b, w):
+    n = circ.n
+    U = np.eye(1 << n, dtype=complex)
+    for g in circ.gates:
+        t, q0, q1 = int(g[0]), int(g[1]), int(g[2])
+        if t in W.PARAM_TYPES:
+            th = _angle(g, x_b, w)
+            G = kron_on(n, {q0: sla.expm(-0.5j * th * PAULI[t])})
+        elif t == W.CNOT:
+            G = kron_on(n, {q0: P0}) + kron_on(n, {q0: P1, q1: PX})
+        else:
+            G = np.eye(1 << n) - 2 * kron_on(n, {q0: P1, q1: P1})
+        U = G @ U
+    return U
+
+
+def brute_state(circ, x_b, w):
+    psi0 = np.zeros(1 << circ.n, dtype=complex)
+    psi0[0] = 1
+    return brute_unitary(circ, x_b, w) @ psi0
+
+
+def zstring(n, mask):
+    return kron_on(n, {q: PZ for q in range(n) if (int(mask) >> q) & 1})
+
+
+def brute_expvals(circ, x_b, w):
+    psi = brute_state(circ, x_b, w)
+    return np.array([np.real(np.vdot(psi, zstring(circ.n, m) @ psi)) for m in circ.masks])
+
+
+# --- Bloch-vector closed forms for product states -------------------------
+
+def so3(t, th):
+    c, s = math.cos(th), math.sin(th)
+    if t == W.RX:
+        return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+    if t == W.RY:
+        return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+
+
+def so3_deriv(t, th):
+    c, s = math.cos(th), math.sin(th)
+    if t == W.RX:
+        return np.array([[0, 0, 0], [0, -s, -c], [0, c, -s]])
+    if t == W.RY:
+        return np.array([[-s, 0, c], [0, 0, 0], [-c, 0, -s]])
+    return np.array([[-s, -c, 0], [c, -s, 0], [0, 0, 0]])
+
+
+def bloch_vectors(circ, x_b, w):
+    r = {q: np.array([0.0, 0.0, 1.0]) for q in range(circ.n)}
+    for g in circ.gates:
+        t = int(g[0])
+        assert t in W.PARAM_TYPES, "product-state closed form needs no entangler"
+        r[int(g[1])] = so3(t, _angle(g, x_b, w)) @ r[int(g[1])]
+    return r
+
+
+def bloch_expvals(circ, x_b, w, masks=None):
+    r = bloch_vectors(circ, x_b, w)
+    masks = circ.masks if masks is None else masks
+    return np.array([np.prod([r[q][2] for q in range(circ.n) if (int(m) >> q) & 1])
+                     for m in masks])
+
+
+def bloch_grad(circ, x_b, w, G):
+    """Analytic VJP of the product-state closed form (chain + product rule)."""
+    n = circ.n
+    per_q = {q: [] for q in range(n)}
+    for k, g in enumerate(circ.gates):
+        per_q[int(g[1])].append(k)
+    gw = np.zeros(circ.n_weights)
+    gx = np.zeros(circ.n_inputs)
+    r = bloch_vectors(circ, x_b, w)
+    for q in range(n):
+        ks = per_q[q]
+        mats = [so3(int(circ.gates[k][0]), _angle(circ.gates[k], x_b, w)) for k in ks]
+        for j, k in enumerate(ks):
+            v = np.array([0.0, 0.0, 1.0])
+            for i, M in enumerate(mats):
+                if i == j:
+                    v = so3_deriv(int(circ.gates[k][0]), _angle(circ.gates[k], x_b, w)) @ v
+                else:
+                    v = M @ v
+            dz = v[2]
+            tot = 0.0
+            for m, Gm in zip(circ.masks, G):
+                if not (int(m) >> q) & 1:
+                    continue
+                others = np.prod([r[p][2] for p in range(n) if p != q and (int(m) >> p) & 1])
+                tot += Gm * dz * others
+            g = circ.gates[k]
+            if g[3] == W.SRC_WEIGHT:
+                gw[g[4]] += tot
+            else:
+                gx[g[4]] += tot
+    return gw, gx
+
+
+# --- Heisenberg propagation of Z strings through CNOTs ---------------------
+
+def heisenberg_mask(mask: int, cnots) -> int:
+    """U^dag Z_S U for U = C_N ... C_1 (C_1 applied first): conjugate by the
+    last gate first.  CNOT(c, t): Z_t -> Z_c Z_t, Z_c -> Z_c."""
+    s = int(mask)
+    for c, t in reversed(list(cnots)):
+        if (s >> t) & 1:
+            s ^= 1 << c
+    return s
+
+
+# --- classical circuits ----------------------------------------------------
+
+def classical_bits(circ, x_b, w):
+    """Angles must be 0 or pi (mod 2 pi): RX(pi), RY(pi) flip a bit, RZ only
+    adds a phase, CNOT permutes, CZ adds a sign."""
+    bits = 0
+    for g in circ.gates:
+        t, q0, q1 = int(g[0]), int(g[1]), int(g[2])
+        if t in (W.RX, W.RY):
+            th = _angle(g, x_b, w)
+            k = round(th / math.pi)
+            assert abs(th - k * math.pi) < 1e-12
+            if k % 2:
+                bits ^= 1 << q0
+        elif t == W.CNOT:
+            if (bits >> q0) & 1:
+                bits ^= 1 << q1
+    return bits

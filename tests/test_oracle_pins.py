@@ -1,0 +1,332 @@
+"""Pins for the CPU oracle: it is checked against facts fixed by the paper and
+by the mathematics, never against itself.
+
+Every pin uses a route to the numbers that is independent of the oracle's
+code (see ``checkers.py``): closed forms, brute-force Kronecker unitaries,
+Heisenberg propagation of Z strings, classical bit circuits, the exact
+parameter-shift rule and finite differences (which use only the oracle's
+forward against its reverse sweep), and invariants.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st, HealthCheck
+
+import oracle
+import workloads as W
+import checkers as C
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def circ_from(d):
+    gates = np.array(d["gates"], dtype=np.int32).reshape(-1, 5)
+    return W.Circuit(n=d["n"], gates=gates, n_inputs=len(d["inputs"]),
+                     n_weights=len(d["weights"]),
+                     masks=np.array(d["masks"], dtype=np.uint64))
+
+
+# --- golden closed forms ---------------------------------------------------
+
+def test_golden_closed_forms():
+    cases = json.load(open(os.path.join(GOLDEN, "closed_forms.json")))["cases"]
+    for d in cases:
+        c = circ_from(d)
+        x = np.array(d["inputs"], dtype=float).reshape(1, -1)
+        w = np.array(d["weights"], dtype=float)
+        ev = oracle.forward(c, x, w)[0]
+        np.testing.assert_allclose(ev, d["expect"], atol=1e-13, err_msg=d["name"])
+        if "G" in d:
+            _, gw, gx = oracle.vjp(c, x, w, np.array(d["G"]).reshape(1, -1))
+            if "grad_w" in d:
+                np.testing.assert_allclose(gw, d["grad_w"], atol=1e-13, err_msg=d["name"])
+            if "grad_x" in d:
+                np.testing.assert_allclose(gx[0], d["grad_x"], atol=1e-13, err_msg=d["name"])
+
+
+def test_batch_split_rule():
+    facts = json.load(open(os.path.join(GOLDEN, "paper_facts.json")))["batch_split"]
+    for case in facts["cases"]:
+        ranges = oracle.split(case["B"], case["T"])
+        assert [hi - lo for lo, hi in ranges] == case["sizes"]
+        # contiguous cover of 0..B-1
+        assert ranges[0][0] == 0 and ranges[-1][1] == case["B"]
+        assert all(ranges[i][1] == ranges[i + 1][0] for i in range(len(ranges) - 1))
+
+
+@pytest.mark.parametrize("t", [W.RX, W.RY])
+def test_single_qubit_cos_and_sin(t):
+    th = np.linspace(-3.0, 3.0, 13)
+    c = W.Circuit(n=1, gates=np.array([[t, 0, 0, W.SRC_WEIGHT, 0]], np.int32),
+                  n_inputs=0, n_weights=1, masks=np.array([1], np.uint64))
+    for v in th:
+        ev = oracle.forward(c, np.zeros((1, 0)), np.array([v]))[0, 0]
+        assert abs(ev - math.cos(v)) < 1e-14
+        _, gw, _ = oracle.vjp(c, np.zeros((1, 0)), np.array([v]), np.ones((1, 1)))
+        assert abs(gw[0] + math.sin(v)) < 1e-14
+
+
+def test_rz_leaves_z_unchanged_and_has_zero_gradient():
+    g = np.array([[W.RY, 0, 0, W.SRC_WEIGHT, 0], [W.RZ, 0, 0, W.SRC_WEIGHT, 1]], np.int32)
+    c = W.Circuit(n=1, gates=g, n_inputs=0, n_weights=2, masks=np.array([1], np.uint64))
+    for a, b in [(0.3, 1.1), (-2.0, 0.7)]:
+        ev = oracle.forward(c, np.zeros((1, 0)), np.array([a, b]))[0, 0]
+        assert abs(ev - math.cos(a)) < 1e-14
+        _, gw, _ = oracle.vjp(c, np.zeros((1, 0)), np.array([a, b]), np.ones((1, 1)))
+        assert abs(gw[1]) < 1e-15
+
+
+# --- product states: Bloch closed form -------------------------------------
+
+@pytest.mark.parametrize("n,L", [(3, 1), (5, 3), (7, 2)])
+def test_product_states_match_bloch(n, L):
+    rng = np.random.default_rng(7 + n)
+    c = W.layered_circuit(n, L, "none")
+    extra = rng.integers(1, 1 << n, size=4, dtype=np.uint64)
+    c.masks = np.concatenate([c.masks, extra])
+    x = rng.uniform(-np.pi, np.pi, size=(3, n))
+    w = rng.uniform(-np.pi, np.pi, size=c.n_weights)
+    G = rng.uniform(-1, 1, size=(3, c.n_obs))
+    ev, gw, gx = oracle.vjp(c, x, w, G)
+    gw_ref = np.zeros_like(gw)
+    for b in range(3):
+        np.testing.assert_allclose(ev[b], C.bloch_expvals(c, x[b], w), atol=1e-13)
+        gwb, gxb = C.bloch_grad(c, x[b], w, G[b])
+        gw_ref += gwb
+        np.testing.assert_allclose(gx[b], gxb, atol=1e-12)
+    np.testing.assert_allclose(gw, gw_ref, atol=1e-12)
+
+
+def test_one_layer_products_of_cosines():
+    """One layer of RX(x) RY(w) (RZ adds only a phase): <Z_q> = cos x_q cos w_q."""
+    n = 6
+    rng = np.random.default_rng(3)
+    c = W.layered_circuit(n, 1, "none")
+    x = rng.uniform(-np.pi, np.pi, size=(2, n))
+    w = rng.uniform(-np.pi, np.pi, size=c.n_weights)
+    ev = oracle.forward(c, x, w)
+    np.testing.assert_allclose(ev, np.cos(x) * np.cos(w[:n])[None, :], atol=1e-13)
+
+
+# --- brute force (n <= 5) ----------------------------------------------------
+
+@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 2**31 - 1), n=st.integers(1, 5), ng=st.integers(0, 25))
+def test_brute_force_random_circuits(seed, n, ng):
+    rng = np.random.default_rng(seed)
+    c = W.random_circuit(rng, n, ng)
+    wl = W.random_workload(rng, c, 2)
+    for b in range(2):
+        psi = oracle.state(c, wl.inputs[b], wl.weights)
+        np.testing.assert_allclose(psi, C.brute_state(c, wl.inputs[b], wl.weights), atol=1e-12)
+    ev = oracle.forward(c, wl.inputs, wl.weights)
+    for b in range(2):
+        np.testing.assert_allclose(ev[b], C.brute_expvals(c, wl.inputs[b], wl.weights), atol=1e-12)
+
+
+def test_brute_force_config_c1():
+    wl = W.config_workload("c1")
+    ev = oracle.forward(wl.circuit, wl.inputs, wl.weights)
+    for b in range(wl.batch):
+        np.testing.assert_allclose(ev[b], C.brute_expvals(wl.circuit, wl.inputs[b], wl.weights),
+                                   atol=1e-12)
+
+
+# --- Heisenberg propagation: pins the CNOT ring order ----------------------
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+def test_ring_heisenberg(n):
+    rng = np.random.default_rng(100 + n)
+    c = W.layered_circuit(n, 1, "ring")
+    x = rng.uniform(-np.pi, np.pi, size=(2, n))
+    w = rng.uniform(-np.pi, np.pi, size=c.n_weights)
+    ev = oracle.forward(c, x, w)
+    rot = W.layered_circuit(n, 1, "none")
+    cnots = [(int(g[1]), int(g[2])) for g in c.gates if g[0] == W.CNOT]
+    assert cnots[-1] == (n - 1, 0)
+    for b in range(2):
+        masks = [C.heisenberg_mask(int(m), cnots) for m in c.masks]
+        ref = C.bloch_expvals(rot, x[b], w, masks=masks)
+        np.testing.assert_allclose(ev[b], ref, atol=1e-13)
+        # the reversed ring order gives different masks (n >= 2), so the pin bites
+        if n >= 3:
+            masks_rev = [C.heisenberg_mask(int(m), list(reversed(cnots))) for m in c.masks]
+            assert masks_rev != masks
+
+
+# --- classical circuits: angles in {0, pi} --------------------------------
+
+@pytest.mark.parametrize("n,L,ent", [(4, 3, "ring"), (9, 2, "ring"), (6, 2, "ladder")])
+def test_classical_circuits(n, L, ent):
+    rng = np.random.default_rng(n * 10 + L)
+    c = W.layered_circuit(n, L, ent)
+    x = rng.integers(0, 2, size=(3, n)) * np.pi
+    w = rng.integers(-1, 2, size=c.n_weights) * np.pi
+    ev = oracle.forward(c, x, w)
+    for b in range(3):
+        bits = C.classical_bits(c, x[b], w)
+        ref = [(-1.0) ** bin(bits & int(m)).count("1") for m in c.masks]
+        np.testing.assert_allclose(ev[b], ref, atol=1e-12)
+
+
+# --- norm, uncompute --------------------------------------------------------
+
+def test_norm_and_uncompute():
+    wl = W.config_workload("c2", batch=2)
+    for b in range(2):
+        psi = oracle.state(wl.circuit, wl.inputs[b], wl.weights)
+        assert abs(np.vdot(psi, psi).real - 1) < 1e-12
+        assert abs(oracle.uncompute_residual(wl.circuit, wl.inputs[b], wl.weights) - 1) < 1e-10
+
+
+# --- parameter shift (exact) on the untied circuit -------------------------
+
+def _param_shift_occ(c, x_b, w, G_b):
+    cu, vals, occ = W.untie(c, x_b, w)
+    xb = np.asarray(x_b).reshape(1, -1)
+    out = np.zeros(len(occ))
+    for k in range(len(occ)):
+        vp, vm = vals.copy(), vals.copy()
+        vp[k] += np.pi / 2
+        vm[k] -= np.pi / 2
+        fp = oracle.forward(cu, xb, vp)[0]
+        fm = oracle.forward(cu, xb, vm)[0]
+        out[k] = np.dot(G_b, (fp - fm) / 2)
+    return out, occ
+
+
+@pytest.mark.parametrize("name,n,L,ent", [("c1", 4, 2, "ring"), ("lad", 5, 2, "ladder")])
+def test_param_shift_per_occurrence(name, n, L, ent):
+    if name == "c1":
+        wl = W.config_workload("c1", batch=3)
+    else:
+        rng = np.random.default_rng(5)
+        wl = W.random_workload(rng, W.layered_circuit(n, L, ent), 3)
+    c = wl.circuit
+    _, gw, gx, gocc = oracle.vjp(c, wl.inputs, wl.weights, wl.grad_out, occurrences=True)
+    for b in range(wl.batch):
+        ps, occ = _param_shift_occ(c, wl.inputs[b], wl.weights, wl.grad_out[b])
+        np.testing.assert_allclose(gocc[b, occ], ps, atol=1e-10)
+
+
+def test_param_shift_random_gates():
+    rng = np.random.default_rng(11)
+    for n in (2, 3, 4):
+        c = W.random_circuit(rng, n, 18)
+        wl = W.random_workload(rng, c, 2)
+        _, _, _, gocc = oracle.vjp(c, wl.inputs, wl.weights, wl.grad_out, occurrences=True)
+        for b in range(2):
+            ps, occ = _param_shift_occ(c, wl.inputs[b], wl.weights, wl.grad_out[b])
+            np.testing.assert_allclose(gocc[b, occ], ps, atol=1e-10)
+
+
+def test_param_shift_c2_sample():
+    """Exactness at n = 12 on a sample of occurrences of the c2 circuit."""
+    wl = W.config_workload("c2", batch=1)
+    c = wl.circuit
+    _, _, _, gocc = oracle.vjp(c, wl.inputs, wl.weights, wl.grad_out, occurrences=True)
+    cu, vals, occ = W.untie(c, wl.inputs[0], wl.weights)
+    rng = np.random.default_rng(0)
+    for k in rng.choice(len(occ), size=8, replace=False):
+        vp, vm = vals.copy(), vals.copy()
+        vp[k] += np.pi / 2
+        vm[k] -= np.pi / 2
+        fp = oracle.forward(cu, wl.inputs[:1], vp)[0]
+        fm = oracle.forward(cu, wl.inputs[:1], vm)[0]
+        assert abs(gocc[0, occ[k]] - np.dot(wl.grad_out[0], (fp - fm) / 2)) < 1e-10
+
+
+# --- central finite differences on tied parameters --------------------------
+
+def test_finite_differences_tied():
+    wl = W.config_workload("c1", batch=4)
+    c, x, w, G = wl.circuit, wl.inputs, wl.weights, wl.grad_out
+    _, gw, gx = oracle.vjp(c, x, w, G)
+    h = 1e-6
+    L = lambda xx, ww: float(np.sum(G * oracle.forward(c, xx, ww)))
+    for j in range(c.n_weights):
+        wp, wm = w.copy(), w.copy()
+        wp[j] += h
+        wm[j] -= h
+        assert abs((L(x, wp) - L(x, wm)) / (2 * h) - gw[j]) < 1e-8
+    for b in range(2):
+        for i in range(c.n_inputs):
+            xp, xm = x.copy(), x.copy()
+            xp[b, i] += h
+            xm[b, i] -= h
+            assert abs((L(xp, w) - L(xm, w)) / (2 * h) - gx[b, i]) < 1e-8
+
+
+# --- Jacobian (paper's multi-observable extension) vs VJP -----------------
+
+def test_jacobian_rows_and_vjp_linearity():
+    wl = W.config_workload("c1", batch=3)
+    c = wl.circuit
+    ev_j, jw, jx = oracle.jacobian(c, wl.inputs, wl.weights)
+    ev_v, gw, gx = oracle.vjp(c, wl.inputs, wl.weights, wl.grad_out)
+    np.testing.assert_allclose(ev_j, ev_v, atol=1e-15)
+    np.testing.assert_allclose(np.einsum("bm,bmj->j", wl.grad_out, jw), gw, atol=1e-12)
+    np.testing.assert_allclose(np.einsum("bm,bmi->bi", wl.grad_out, jx), gx, atol=1e-12)
+    assert jw.shape == (3, c.n_obs, c.n_weights)     # (B, M, |Theta|), Sec. II-B
+    # one-hot G reproduces a Jacobian row (VJP linearity)
+    for m in range(c.n_obs):
+        G = np.zeros((3, c.n_obs))
+        G[:, m] = 1
+        _, gwm, gxm = oracle.vjp(c, wl.inputs, wl.weights, G)
+        np.testing.assert_allclose(gwm, jw[:, m, :].sum(0), atol=1e-12)
+        np.testing.assert_allclose(gxm, jx[:, m, :], atol=1e-12)
+
+
+# --- invariants ----------------------------------------------------------------
+
+@pytest.mark.parametrize("ent", ["ring", "ladder"])
+def test_last_layer_rz_gradient_is_zero(ent):
+    n, L = 5, 3
+    rng = np.random.default_rng(21)
+    wl = W.random_workload(rng, W.layered_circuit(n, L, ent), 2)
+    _, gw, _ = oracle.vjp(wl.circuit, wl.inputs, wl.weights, wl.grad_out)
+    last_rz = [(L - 1) * 2 * n + n + q for q in range(n)]
+    assert np.max(np.abs(gw[last_rz])) < 1e-13
+    assert np.max(np.abs(gw)) > 1e-3
+
+
+def test_appending_cz_layer_and_2pi_shift():
+    n, L = 5, 2
+    rng = np.random.default_rng(22)
+    wl = W.random_workload(rng, W.layered_circuit(n, L, "ring"), 2)
+    c = wl.circuit
+    ev = oracle.forward(c, wl.inputs, wl.weights)
+    extra = np.array([[W.CZ, i, (i + 2) % n, 0, 0] for i in range(n)], np.int32)
+    c2 = W.Circuit(n=n, gates=np.concatenate([c.gates, extra]), n_inputs=c.n_inputs,
+                   n_weights=c.n_weights, masks=c.masks)
+    np.testing.assert_allclose(oracle.forward(c2, wl.inputs, wl.weights), ev, atol=1e-13)
+    w2 = wl.weights.copy()
+    w2[3] += 2 * np.pi
+    np.testing.assert_allclose(oracle.forward(c, wl.inputs, w2), ev, atol=1e-12)
+
+
+def test_cz_ladder_reflection_symmetry():
+    n, L = 6, 2
+    rng = np.random.default_rng(23)
+    wl = W.random_workload(rng, W.layered_circuit(n, L, "ladder"), 2)
+    c, x, w, G = wl.circuit, wl.inputs, wl.weights, wl.grad_out
+    perm = np.arange(n)[::-1]
+    xr = x[:, perm]
+    wr = w.reshape(L, 2, n)[:, :, perm].reshape(-1)
+    Gr = G[:, perm]
+    ev, gw, gx = oracle.vjp(c, x, w, G)
+    evr, gwr, gxr = oracle.vjp(c, xr, wr, Gr)
+    np.testing.assert_allclose(evr, ev[:, perm], atol=1e-12)
+    np.testing.assert_allclose(gxr, gx[:, perm], atol=1e-12)
+    np.testing.assert_allclose(gwr, gw.reshape(L, 2, n)[:, :, perm].reshape(-1), atol=1e-12)
+
+
+def test_amplitude_parallel_mode_matches_batch_mode():
+    wl = W.config_workload("c2", batch=3)
+    a = oracle.vjp(wl.circuit, wl.inputs, wl.weights, wl.grad_out, threads=4, par_mode=0)
+    b = oracle.vjp(wl.circuit, wl.inputs, wl.weights, wl.grad_out, threads=4, par_mode=1)
+    for u, v in zip(a, b):
+        np.testing.assert_allclose(u, v, atol=1e-12)

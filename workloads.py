@@ -1,0 +1,202 @@
+"""Seeded synthetic inputs: circuits (gate lists), angles, upstream gradients.
+
+This module is the only code shared by the oracle side and the HIP side.  It
+holds none of the method's arithmetic: it emits gate *records* (which gate,
+on which qubits, reading which input or weight slot), observable bitmasks and
+random numbers, and nothing that simulates a state.
+
+Gate record format (int32 x 5): ``type, q0, q1, src, index``.
+
+* ``type``: 0 RX, 1 RY, 2 RZ, 3 CNOT (q0 = control, q1 = target), 4 CZ.
+* ``src``: 0 none (entanglers), 1 input vector, 2 weight vector.
+* ``index``: slot in that vector.  Parameters are indexed in construction
+  order, never alphabetically (paper Sec. II-C).
+
+Circuit family (paper Eq. (7), simplified to the layer used by every
+benchmark here): one *layer* is RX(x_q) angle encoding on each qubit
+(re-uploaded every layer, Sec. III-A "data re-uploading"), then trainable RY
+and RZ on each qubit, then an entangler: a CNOT ring i -> (i+1) mod n applied
+in increasing i (wrap gate last), or an open CZ ladder (i, i+1).  Weight slot
+``l*2n + q`` is the RY angle on qubit q in layer l, ``l*2n + n + q`` the RZ
+angle.  Observables are Pauli-Z strings given as bitmasks (bit q = qubit q,
+little-endian basis index).
+
+Random draws use ``numpy.random.default_rng(seed)`` in a fixed order:
+weights, then inputs (row-major), then the upstream gradient G.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+RX, RY, RZ, CNOT, CZ = 0, 1, 2, 3, 4
+SRC_NONE, SRC_INPUT, SRC_WEIGHT = 0, 1, 2
+PARAM_TYPES = (RX, RY, RZ)
+
+
+@dataclass
+class Circuit:
+    n: int
+    gates: np.ndarray          # int32 [G, 5]
+    n_inputs: int
+    n_weights: int
+    masks: np.ndarray          # uint64 [M]
+    name: str = ""
+
+    @property
+    def n_gates(self) -> int:
+        return int(self.gates.shape[0])
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.masks.shape[0])
+
+
+@dataclass
+class Workload:
+    circuit: Circuit
+    batch: int
+    inputs: np.ndarray         # float64 [B, n_inputs]
+    weights: np.ndarray        # float64 [n_weights]
+    grad_out: np.ndarray       # float64 [B, M]
+    meta: dict = field(default_factory=dict)
+
+
+def z_masks(n: int, extra=()) -> np.ndarray:
+    """Single-qubit Z_i on every qubit, then any extra masks."""
+    return np.array([1 << q for q in range(n)] + list(extra), dtype=np.uint64)
+
+
+def layered_circuit(n: int, layers: int, entangler: str = "ring",
+                    extra_masks=(), name: str = "") -> Circuit:
+    if entangler not in ("ring", "ladder", "none"):
+        raise ValueError(entangler)
+    g = []
+    for l in range(layers):
+        for q in range(n):
+            g.append((RX, q, 0, SRC_INPUT, q))
+        for q in range(n):
+            g.append((RY, q, 0, SRC_WEIGHT, l * 2 * n + q))
+        for q in range(n):
+            g.append((RZ, q, 0, SRC_WEIGHT, l * 2 * n + n + q))
+        if entangler == "ring" and n >= 2:
+            for i in range(n):
+                g.append((CNOT, i, (i + 1) % n, SRC_NONE, 0))
+        elif entangler == "ladder":
+            for i in range(n - 1):
+                g.append((CZ, i, i + 1, SRC_NONE, 0))
+    gates = np.array(g, dtype=np.int32).reshape(-1, 5)
+    return Circuit(n=n, gates=gates, n_inputs=n, n_weights=2 * n * layers,
+                   masks=z_masks(n, extra_masks), name=name)
+
+
+def _draw(rng, circ: Circuit, batch: int):
+    w = rng.uniform(-math.pi, math.pi, size=circ.n_weights)
+    x = rng.uniform(-math.pi, math.pi, size=(batch, circ.n_inputs))
+    G = rng.uniform(-1.0, 1.0, size=(batch, circ.n_obs))
+    return x, w, G
+
+
+# name -> (n, layers, entangler, batch, extra masks, seed, state precision)
+CONFIGS = {
+    "c1": dict(n=4, layers=2, entangler="ring", batch=8, extra=(), seed=1001,
+               precision="c128"),
+    "c2": dict(n=12, layers=4, entangler="ring", batch=256, extra=(0xFFF,),
+               seed=1002, precision="c64"),
+    "c3": dict(n=20, layers=8, entangler="ladder", batch=64, extra=(),
+               seed=1003, precision="c64"),
+    "c5": dict(n=26, layers=10, entangler="ring", batch=16, extra=(),
+               seed=1005, precision="c64"),
+}
+
+WORKLOAD_NAMES = {
+    "c1": "n4_L2_ring_B8_c128",
+    "c2": "n12_L4_ring_B256_c64",
+    "c3": "n20_L8_czladder_B64_c64",
+    "c4": "uneven1024_n8-16_L2-10_ring_c64",
+    "c5": "n26_L10_ring_B16_c64",
+}
+
+
+def config_workload(name: str, batch: int | None = None) -> Workload:
+    """Seeded inputs for a named configuration (c1, c2, c3, c5)."""
+    c = CONFIGS[name]
+    circ = layered_circuit(c["n"], c["layers"], c["entangler"], c["extra"],
+                           name=WORKLOAD_NAMES[name])
+    B = c["batch"]
+    rng = np.random.default_rng(c["seed"])
+    x, w, G = _draw(rng, circ, B)
+    if batch is not None:
+        x, G = x[:batch].copy(), G[:batch].copy()
+        B = batch
+    return Workload(circuit=circ, batch=B, inputs=x, weights=w, grad_out=G,
+                    meta=dict(config=name, precision=c["precision"]))
+
+
+def uneven_items(count: int = 1024, seed: int = 1004, n_range=(8, 16),
+                 l_range=(2, 10)) -> list[Workload]:
+    """Uneven batch: per item draw n, then L (inclusive ranges), then that
+    item's weights, inputs (batch 1) and G."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        L = int(rng.integers(l_range[0], l_range[1] + 1))
+        circ = layered_circuit(n, L, "ring", name=f"item{i}_n{n}_L{L}")
+        x, w, G = _draw(rng, circ, 1)
+        out.append(Workload(circuit=circ, batch=1, inputs=x, weights=w,
+                            grad_out=G, meta=dict(item=i)))
+    return out
+
+
+def random_circuit(rng, n: int, n_gates: int, n_inputs: int = 3,
+                   n_weights: int = 5, n_obs: int = 3) -> Circuit:
+    """Random gate list over all gate types and random qubit pairs, with
+    random parameter slots (parameters may be shared between gates)."""
+    g = []
+    for _ in range(n_gates):
+        t = int(rng.integers(0, 5)) if n >= 2 else int(rng.integers(0, 3))
+        if t in PARAM_TYPES:
+            q = int(rng.integers(0, n))
+            if rng.random() < 0.4:
+                g.append((t, q, 0, SRC_INPUT, int(rng.integers(0, n_inputs))))
+            else:
+                g.append((t, q, 0, SRC_WEIGHT, int(rng.integers(0, n_weights))))
+        else:
+            a, b = rng.choice(n, size=2, replace=False)
+            g.append((t, int(a), int(b), SRC_NONE, 0))
+    masks = rng.integers(1, 1 << n, size=n_obs, dtype=np.uint64)
+    return Circuit(n=n, gates=np.array(g, dtype=np.int32).reshape(-1, 5),
+                   n_inputs=n_inputs, n_weights=n_weights, masks=masks,
+                   name=f"random_n{n}_g{n_gates}")
+
+
+def random_workload(rng, circ: Circuit, batch: int) -> Workload:
+    x, w, G = _draw(rng, circ, batch)
+    return Workload(circuit=circ, batch=batch, inputs=x, weights=w, grad_out=G)
+
+
+def untie(circ: Circuit, x: np.ndarray, w: np.ndarray):
+    """Give every parameterised gate occurrence its own weight slot.
+
+    Returns (circuit, weights, occ) where the new circuit reads every rotation
+    angle from its own weight slot k (in gate order) and ``occ[k]`` is the gate
+    index.  Input-fed angles are copied from the single sample ``x``.
+    Used by parameter-shift checks: the shift rule is exact only for a
+    parameter that enters exactly one exp(-i theta P / 2).
+    """
+    g = circ.gates.copy()
+    vals, occ = [], []
+    for k in range(g.shape[0]):
+        t, q0, q1, src, idx = (int(v) for v in g[k])
+        if t in PARAM_TYPES:
+            vals.append(x[idx] if src == SRC_INPUT else w[idx])
+            g[k, 3] = SRC_WEIGHT
+            g[k, 4] = len(occ)
+            occ.append(k)
+    c = Circuit(n=circ.n, gates=g, n_inputs=max(circ.n_inputs, 1),
+                n_weights=len(occ), masks=circ.masks.copy(),
+                name=circ.name + "_untied")
+    return c, np.array(vals, dtype=np.float64), occ
