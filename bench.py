@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Throughput of the batched statevector forward + adjoint VJP on one GPU.
+
+One step = qtm_forward (keeping the final states) + qtm_backward (adjoint
+vector-Jacobian product to dL/dweights and dL/dinputs) over one batch of
+synthetic inputs already resident in HBM.  Default workload: n = 20 qubits,
+8 layers (RX encoding, RY + RZ trainable, CZ ladder), batch 64, complex64
+amplitudes, Z_i observables on every qubit.
+
+Prints one JSON line (metric, value, roofline of the dominant kernel and the
+CPU oracle's throughput on a bounded sample); progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "circuit evals/s (fwd+adjoint grad) n=20 depth 8 batch 64; % peak HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sweep_bytes(n_sweeps: int, kind: int) -> int:
+    """State-array reads + writes per amplitude, summed over a pass's sweeps.
+
+    forward: the first sweep generates |0> (1 write), the others read and
+    write psi (2); backward: the first sweep reads psi and writes psi and
+    lambda (3), middle sweeps read and write both (4), the last only reads
+    both (2)."""
+    if kind == 0:
+        return 1 + 2 * (n_sweeps - 1)
+    if n_sweeps == 1:
+        return 1
+    return 3 + 4 * (n_sweeps - 2) + 2
+
+
+def cpu_baseline(wl, threads: int, samples: int):
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    s = min(samples, wl.batch)
+    x, G = wl.inputs[:s], wl.grad_out[:s]
+    t0 = time.perf_counter()
+    oracle.vjp(wl.circuit, x, wl.weights, G, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": s / dt, "unit": "circuit evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{s} of {wl.batch} samples of the same workload, forward + adjoint VJP "
+                      f"in complex128, samples split over {threads} threads; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--precision", default=None, choices=[None, "c64", "c128"])
+    ap.add_argument("--path", default="fused", choices=["fused", "plain"])
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--klo", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--cpu-samples", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batch would be "
+              "split across GPUs with one all-reduce of dL/dweights, which this build does not do",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2404_06314_amd as q
+
+    wl = W.config_workload(args.config)
+    prec = args.precision or wl.meta["precision"]
+    circ = wl.circuit
+    c = q.Circuit.from_workload(circ)
+    c.set_path(q.QTM_PATH_FUSED if args.path == "fused" else q.QTM_PATH_PLAIN)
+    if args.tile:
+        c.set_option(q.QTM_OPT_TILE_QUBITS, args.tile)
+    if args.klo:
+        c.set_option(q.QTM_OPT_LOW_QUBITS, args.klo)
+    dev = torch.device("cuda:0")
+    x = torch.as_tensor(wl.inputs, device=dev)
+    w = torch.as_tensor(wl.weights, device=dev)
+    G = torch.as_tensor(wl.grad_out, device=dev)
+    B = wl.batch
+    state = c.alloc_state(B, prec)
+    log(f"workload {circ.name}: n={circ.n} gates={circ.n_gates} B={B} precision={prec} "
+        f"path={args.path}")
+
+    def step():
+        c.forward(x, w, prec, state=state)
+        c.backward(x, w, G, prec, state=state)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    c.set_option(q.QTM_OPT_TIMING, 1 if args.path == "fused" else 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = B * args.steps / (t1 - t0)
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.1f} evals/s")
+
+    roof = None
+    elem = 8 if prec == "c64" else 16
+    if args.path == "fused":
+        import ctypes
+        lib = q._lib.load()
+        plan = c.plan(prec)
+        S = len(plan["sweeps"])
+        res = {}
+        for kind in (0, 1):
+            ms = ctypes.c_double()
+            nl = ctypes.c_int64()
+            q._lib.check(lib.qtm_timing_read(c.handle, kind, ctypes.byref(ms), ctypes.byref(nl)))
+            res[kind] = (ms.value, nl.value)
+        c.set_option(q.QTM_OPT_TIMING, 0)
+        kind = 1 if res[1][0] >= res[0][0] else 0
+        ms_tot, launches = res[kind]
+        bytes_per_step = B * (1 << circ.n) * elem * sweep_bytes(S, kind)
+        per_launch_bytes = bytes_per_step / S
+        avg_s = ms_tot / launches / 1e3
+        achieved = per_launch_bytes / avg_s / 1e9
+        name = "k_fused_bwd" if kind == 1 else "k_fused_fwd"
+        log(f"{name}: {launches} launches, avg {avg_s * 1e6:.1f} us, {per_launch_bytes / 1e6:.1f} MB "
+            f"per launch -> {achieved:.1f} GB/s; fwd sweeps {res[0][0] / args.steps:.3f} ms/step, "
+            f"bwd sweeps {res[1][0] / args.steps:.3f} ms/step ({S} sweeps)")
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
+                "bytes_per_launch": int(per_launch_bytes), "sweeps": S}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        samples = args.cpu_samples or threads
+        log(f"cpu baseline: oracle on {samples} samples with {threads} threads ...")
+        cpu = cpu_baseline(wl, threads, samples)
+        log(f"cpu baseline: {cpu['value']:.3f} evals/s")
+
+    out = {
+        "metric": METRIC if args.config == "c3" else f"circuit evals/s (fwd+adjoint grad) {circ.name}",
+        "value": round(value, 2),
+        "unit": "circuit evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": W.WORKLOAD_NAMES[args.config], "n_qubits": circ.n,
+                   "layers": W.CONFIGS[args.config]["layers"],
+                   "entangler": W.CONFIGS[args.config]["entangler"], "batch": B,
+                   "observables": circ.n_obs, "precision": prec, "path": args.path},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,166 @@
+/*
+ * qtm.h -- C ABI of libqtm: batched exact statevector forward and adjoint
+ * vector-Jacobian product of parameterised circuits on one gfx950 GPU.
+ *
+ * The operations are those of "Qiskit-Torch-Module" (arXiv 2404.06314):
+ *   - a circuit is a gate list whose rotation angles index into an input
+ *     vector (data encoding s) or a weight vector (trainable Theta), plus a
+ *     list of observables (Sec. II-D: encoding and variational parameters
+ *     given separately, indexed in construction order, Sec. II-C);
+ *   - qtm_forward evolves |0...0> once per sample and reads every observable
+ *     from that one state (Sec. II-A, Eq. (3)-(4)), for a batch of inputs with
+ *     shared weights (Sec. II-B, Eq. (6));
+ *   - qtm_backward is the reverse-mode ("adjoint") gradient the paper extends
+ *     to several observables (Sec. II-A, Eq. (5)), returned as a vector-
+ *     Jacobian product: given G = dL/d<O> of shape (B, M) it writes
+ *     dL/dweights = sum_b sum_m G[b][m] d<O_m>_b/dweights and
+ *     dL/dinputs[b] = sum_m G[b][m] d<O_m>_b/dinputs[b].
+ *
+ * Conventions.  Basis index x = sum_q b_q 2^q (qubit q is bit q).
+ * RX(t) = exp(-i t X/2), RY(t) = exp(-i t Y/2), RZ(t) = exp(-i t Z/2).
+ * CNOT(q0 -> q1) flips bit q1 where bit q0 is 1; CZ(q0, q1) negates the
+ * amplitudes whose bits q0 and q1 are both 1.  An observable is a Pauli-Z
+ * string given as a bitmask S: <Z_S> = sum_x (-1)^popcount(x & S) |psi_x|^2.
+ *
+ * Memory.  Every array argument named "dev" is device memory owned by the
+ * caller; the library never frees it.  Host arrays are read during the call
+ * only.  Circuit and multi handles, their plans and the internal workspace
+ * (second state buffer, partial sums, matrices) are owned by the library
+ * and released by the matching *_destroy.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ * asynchronous on it: launch errors are returned, execution errors surface
+ * at the caller's next synchronisation.  A handle's workspace is shared by
+ * all calls on that handle, so calls on one handle must be ordered (same
+ * stream, or synchronised by the caller); calls that overlap on one handle
+ * race.
+ *
+ * Errors.  Every function returns QTM_OK (0) or a negative code and never
+ * throws; qtm_last_error() gives a message for the calling thread's last
+ * failure.
+ */
+#ifndef QTM_H
+#define QTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QTM_OK 0
+#define QTM_ERR_INVALID_ARG (-1) /* bad qubit, control == target, index out of range,
+                                    batch <= 0, NULL where required, bad mask */
+#define QTM_ERR_UNSUPPORTED (-2) /* n_qubits > 30, unknown gate type or option */
+#define QTM_ERR_WORKSPACE (-3)   /* device allocation of the workspace failed */
+#define QTM_ERR_HIP (-4)         /* a HIP call failed; message in qtm_last_error */
+#define QTM_ERR_STATE (-5)       /* state buffer not produced by qtm_forward for
+                                    this (circuit, batch, precision) */
+
+enum { QTM_RX = 0, QTM_RY = 1, QTM_RZ = 2, QTM_CNOT = 3, QTM_CZ = 4 };
+enum { QTM_SRC_NONE = 0, QTM_SRC_INPUT = 1, QTM_SRC_WEIGHT = 2 };
+enum { QTM_C64 = 0, QTM_C128 = 1 }; /* state amplitudes: complex float / complex double */
+
+/* Kernel path (option QTM_OPT_PATH). */
+enum { QTM_PATH_AUTO = 0, QTM_PATH_PLAIN = 1, QTM_PATH_FUSED = 2 };
+
+/* Options for qtm_set_option. */
+enum {
+  QTM_OPT_PATH = 0,        /* QTM_PATH_*; AUTO = fused */
+  QTM_OPT_TILE_QUBITS = 1, /* fused path: qubits per LDS tile (0 = default) */
+  QTM_OPT_LOW_QUBITS = 2,  /* fused path: contiguous low qubits always in a tile */
+  QTM_OPT_RENORM = 3,      /* reserved: expectation values are always divided by the norm */
+  QTM_OPT_TIMING = 4       /* 1: record HIP events around every sweep kernel (qtm_timing_read) */
+};
+
+/* One gate.  Rotations (RX, RY, RZ): q0 = qubit, src = QTM_SRC_INPUT or
+ * QTM_SRC_WEIGHT, index = slot in that vector (q1 ignored).
+ * CNOT: q0 = control, q1 = target.  CZ: q0, q1 (symmetric).  src/index
+ * ignored for entanglers. */
+typedef struct {
+  int32_t type, q0, q1, src, index;
+} qtm_gate;
+
+typedef struct qtm_circuit_s *qtm_circuit_t;
+typedef struct qtm_multi_s *qtm_multi_t;
+
+/* Validate and copy a circuit (host arrays).  1 <= n_qubits <= 30;
+ * obs_zmask[m] must have no bit >= n_qubits and n_obs >= 1.  Gates are
+ * applied in list order (paper Eq. (7): the ansatz is a product of layers).
+ * *out receives a new handle on success. */
+int qtm_circuit_create(int32_t n_qubits, const qtm_gate *gates, int32_t n_gates,
+                       int32_t n_inputs, int32_t n_weights, const uint64_t *obs_zmask,
+                       int32_t n_obs, qtm_circuit_t *out);
+int qtm_circuit_destroy(qtm_circuit_t c);
+
+/* Tune the kernel path of a circuit (see QTM_OPT_*). */
+int qtm_set_option(qtm_circuit_t c, int32_t option, int64_t value);
+
+/* Bytes of the caller-owned state buffer for (batch, precision):
+ * batch * 2^n amplitudes of 8 (C64) or 16 (C128) bytes, sample-major.  The
+ * library remembers (host side) which circuit, batch and precision last
+ * filled a buffer, and qtm_backward checks it (QTM_ERR_STATE). */
+int qtm_state_bytes(qtm_circuit_t c, int32_t batch, int32_t precision, size_t *bytes);
+
+/* Forward pass (Sec. II-A, II-B).
+ *   inputs   dev [batch][n_inputs]  float64 (may be NULL if n_inputs == 0)
+ *   weights  dev [n_weights]        float64 (may be NULL if n_weights == 0)
+ *   expvals  dev [batch][n_obs]     float64, written
+ *   state    dev, qtm_state_bytes(); receives the final states for a later
+ *            qtm_backward.  NULL: not kept (a library workspace is used). */
+int qtm_forward(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
+                const double *weights, double *expvals, void *state, void *stream);
+
+/* Adjoint VJP (Sec. II-A, reverse gradient).
+ *   grad_expvals  dev [batch][n_obs] float64: G = dL/d<O>
+ *   state         dev buffer written by qtm_forward with the same circuit, batch,
+ *                 precision and angles; it is un-computed in place (on return it
+ *                 holds about |0...0>), so one forward serves one backward.
+ *                 NULL: the forward is recomputed into the workspace.
+ *   grad_weights  dev [n_weights] float64, overwritten (summed over the batch)
+ *   grad_inputs   dev [batch][n_inputs] float64, overwritten; may be NULL. */
+int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
+                 const double *weights, const double *grad_expvals, void *state,
+                 double *grad_weights, double *grad_inputs, void *stream);
+
+/* Uneven batch (one sample per circuit, circuits of different size and depth,
+ * Sec. II-B: batch elements are independent).  The item handles must stay
+ * alive while the multi handle exists.  Packed arrays: item i reads
+ * inputs[in_off[i] ...], weights[w_off[i] ...], writes expvals[out_off[i] ...]
+ * (n_obs of item i values) and gradients at the same offsets as inputs/weights.
+ * qtm_multi_layout fills the offsets (arrays of `count` + 1 entries; the last
+ * entry is the total length) and the C64 state bytes. */
+int qtm_multi_create(const qtm_circuit_t *items, int32_t count, qtm_multi_t *out);
+int qtm_multi_destroy(qtm_multi_t m);
+int qtm_multi_layout(qtm_multi_t m, int64_t *in_off, int64_t *w_off, int64_t *out_off,
+                     size_t *state_bytes);
+int qtm_multi_forward(qtm_multi_t m, const double *inputs, const double *weights,
+                      double *expvals, void *state, void *stream);
+int qtm_multi_backward(qtm_multi_t m, const double *inputs, const double *weights,
+                       const double *grad_expvals, void *state, double *grad_weights,
+                       double *grad_inputs, void *stream);
+
+/* Diagnostics: with QTM_OPT_TIMING set, the library records a pair of HIP
+ * events on the call's stream around every sweep kernel it launches.
+ * qtm_timing_read waits for those events, returns the summed kernel time in
+ * milliseconds and the number of launches of `kind` (0 = forward sweep,
+ * 1 = backward sweep) since the last read, and forgets them. */
+int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *launches);
+
+/* Diagnostics: JSON description of the fused-path plan (sweeps, tile qubits,
+ * stages and the gate indices each stage runs) for the given precision.
+ * Writes at most len bytes (NUL-terminated) into buf and the full size into
+ * *needed; buf may be NULL to query the size. */
+int qtm_plan_json(qtm_circuit_t c, int32_t precision, char *buf, size_t len, size_t *needed);
+
+/* Message for the calling thread's last non-OK return ("" if none). */
+const char *qtm_last_error(void);
+
+/* Library version string. */
+const char *qtm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTM_H */

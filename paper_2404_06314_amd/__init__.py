@@ -1,0 +1,207 @@
+"""MI355X-native batched statevector forward + adjoint VJP (libqtm binding).
+
+Thin Python layer over the C ABI in ``include/qtm.h``: it marshals torch
+device tensors into plain pointers and the current HIP stream; every step of
+the computation runs in the HIP kernels of ``libqtm.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+
+import numpy as np
+
+from . import _lib
+from ._lib import (QTM_C64, QTM_C128, QTM_CNOT, QTM_CZ, QTM_PATH_AUTO, QTM_PATH_FUSED,
+                   QTM_PATH_PLAIN, QTM_RX, QTM_RY, QTM_RZ, QTM_SRC_INPUT, QTM_SRC_NONE,
+                   QTM_SRC_WEIGHT, QTM_OPT_LOW_QUBITS, QTM_OPT_PATH, QTM_OPT_RENORM,
+                   QTM_OPT_TILE_QUBITS, QtmError)
+
+__all__ = ["Circuit", "Multi", "QtmError", "precision_code", "lib_path",
+           "QTM_C64", "QTM_C128", "QTM_PATH_AUTO", "QTM_PATH_PLAIN", "QTM_PATH_FUSED"]
+
+
+def lib_path() -> str:
+    return str(_lib.LIB_PATH)
+
+
+def precision_code(p) -> int:
+    if p in (QTM_C64, "c64", "complex64"):
+        return QTM_C64
+    if p in (QTM_C128, "c128", "complex128"):
+        return QTM_C128
+    raise ValueError(f"unknown precision {p!r}")
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Circuit:
+    """A validated circuit handle (gate list + Z-string observables)."""
+
+    def __init__(self, n_qubits: int, gates, n_inputs: int, n_weights: int, masks):
+        lib = _lib.load()
+        g = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 5))
+        m = np.ascontiguousarray(np.asarray(masks, dtype=np.uint64).reshape(-1))
+        h = ctypes.c_void_p()
+        _lib.check(lib.qtm_circuit_create(n_qubits, g.ctypes.data_as(ctypes.c_void_p), g.shape[0],
+                                          n_inputs, n_weights, m.ctypes.data_as(ctypes.c_void_p),
+                                          m.shape[0], ctypes.byref(h)))
+        self._h = h
+        self.n = int(n_qubits)
+        self.gates = g
+        self.masks = m
+        self.n_inputs = int(n_inputs)
+        self.n_weights = int(n_weights)
+        self.n_obs = int(m.shape[0])
+
+    @classmethod
+    def from_workload(cls, circ):
+        """From a ``workloads.Circuit``-like object (n, gates, n_inputs, n_weights, masks)."""
+        return cls(circ.n, circ.gates, circ.n_inputs, circ.n_weights, circ.masks)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().qtm_circuit_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, option: int, value: int):
+        _lib.check(_lib.load().qtm_set_option(self._h, option, int(value)))
+
+    def set_path(self, path: int):
+        self.set_option(QTM_OPT_PATH, path)
+
+    def state_bytes(self, batch: int, precision=QTM_C64) -> int:
+        out = ctypes.c_size_t()
+        _lib.check(_lib.load().qtm_state_bytes(self._h, batch, precision_code(precision),
+                                               ctypes.byref(out)))
+        return int(out.value)
+
+    def plan(self, precision=QTM_C64) -> dict:
+        lib = _lib.load()
+        need = ctypes.c_size_t()
+        _lib.check(lib.qtm_plan_json(self._h, precision_code(precision), None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _lib.check(lib.qtm_plan_json(self._h, precision_code(precision), buf, need.value,
+                                     ctypes.byref(need)))
+        return json.loads(buf.value.decode())
+
+    # --- raw pointer calls ----------------------------------------------------
+    def forward_ptr(self, batch, precision, inputs, weights, expvals, state, stream):
+        _lib.check(_lib.load().qtm_forward(self._h, batch, precision, inputs, weights, expvals,
+                                           state, stream))
+
+    def backward_ptr(self, batch, precision, inputs, weights, grad_expvals, state, grad_weights,
+                     grad_inputs, stream):
+        _lib.check(_lib.load().qtm_backward(self._h, batch, precision, inputs, weights,
+                                            grad_expvals, state, grad_weights, grad_inputs, stream))
+
+    # --- torch tensors ----------------------------------------------------------
+    def alloc_state(self, batch: int, precision=QTM_C64, device=None):
+        import torch
+        nbytes = self.state_bytes(batch, precision)
+        return torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+
+    def forward(self, inputs, weights, precision=QTM_C64, state=None, stream=None):
+        """inputs (B, n_inputs) float64 cuda, weights (n_weights,) float64 cuda ->
+        expvals (B, M) float64.  `state` (from alloc_state) keeps the final
+        states for backward."""
+        import torch
+        B = int(inputs.shape[0])
+        _check_f64(inputs, weights)
+        out = torch.empty((B, self.n_obs), dtype=torch.float64, device=inputs.device)
+        self.forward_ptr(B, precision_code(precision), _ptr(inputs), _ptr(weights), _ptr(out),
+                         _ptr(state), _stream_ptr(stream))
+        return out
+
+    def backward(self, inputs, weights, grad_expvals, precision=QTM_C64, state=None,
+                 need_inputs=True, stream=None):
+        """Returns (grad_weights (n_weights,), grad_inputs (B, n_inputs) or None)."""
+        import torch
+        B = int(inputs.shape[0])
+        _check_f64(inputs, weights, grad_expvals)
+        gw = torch.empty((max(self.n_weights, 0),), dtype=torch.float64, device=inputs.device)
+        gx = torch.empty((B, self.n_inputs), dtype=torch.float64, device=inputs.device) \
+            if need_inputs else None
+        self.backward_ptr(B, precision_code(precision), _ptr(inputs), _ptr(weights),
+                          _ptr(grad_expvals), _ptr(state), _ptr(gw), _ptr(gx),
+                          _stream_ptr(stream))
+        return gw, gx
+
+
+def _check_f64(*ts):
+    import torch
+    for t in ts:
+        if t is None:
+            continue
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("expected contiguous float64 cuda tensors")
+
+
+class Multi:
+    """Uneven batch: one sample per circuit, circuits of any size and depth."""
+
+    def __init__(self, circuits):
+        lib = _lib.load()
+        self.items = list(circuits)
+        arr = (ctypes.c_void_p * len(self.items))(*[c.handle.value for c in self.items])
+        h = ctypes.c_void_p()
+        _lib.check(lib.qtm_multi_create(arr, len(self.items), ctypes.byref(h)))
+        self._h = h
+        k = len(self.items) + 1
+        self.in_off = np.zeros(k, np.int64)
+        self.w_off = np.zeros(k, np.int64)
+        self.out_off = np.zeros(k, np.int64)
+        sb = ctypes.c_size_t()
+        _lib.check(lib.qtm_multi_layout(h, self.in_off.ctypes.data_as(ctypes.c_void_p),
+                                        self.w_off.ctypes.data_as(ctypes.c_void_p),
+                                        self.out_off.ctypes.data_as(ctypes.c_void_p),
+                                        ctypes.byref(sb)))
+        self.state_bytes = int(sb.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().qtm_multi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, inputs, weights, state, stream=None):
+        import torch
+        out = torch.empty(int(self.out_off[-1]), dtype=torch.float64, device=inputs.device)
+        _lib.check(_lib.load().qtm_multi_forward(self._h, _ptr(inputs), _ptr(weights), _ptr(out),
+                                                 _ptr(state), _stream_ptr(stream)))
+        return out
+
+    def backward(self, inputs, weights, grad_expvals, state, stream=None):
+        import torch
+        gw = torch.empty(int(self.w_off[-1]), dtype=torch.float64, device=inputs.device)
+        gx = torch.empty(int(self.in_off[-1]), dtype=torch.float64, device=inputs.device)
+        _lib.check(_lib.load().qtm_multi_backward(self._h, _ptr(inputs), _ptr(weights),
+                                                  _ptr(grad_expvals), _ptr(state), _ptr(gw),
+                                                  _ptr(gx), _stream_ptr(stream)))
+        return gw, gx

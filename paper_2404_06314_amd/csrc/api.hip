@@ -1,0 +1,622 @@
+// C ABI of libqtm (declared in include/qtm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/qtm.h"
+#include "circuit.h"
+#include "kernels.h"
+
+using namespace qtm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char *where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return QTM_ERR_HIP;
+}
+
+// Grow-only device buffer.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need) {
+    if (need <= bytes) return QTM_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t want = need < 256 ? 256 : need;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return fail(QTM_ERR_WORKSPACE, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    bytes = want;
+    return QTM_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+template <typename T>
+int upload(T **dst, const std::vector<T> &src, std::vector<void *> &owned) {
+  size_t bytes = std::max<size_t>(sizeof(T), src.size() * sizeof(T));
+  if (hipMalloc((void **)dst, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QTM_ERR_WORKSPACE, "device allocation failed");
+  }
+  owned.push_back(*dst);
+  if (!src.empty()) {
+    hipError_t e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  return QTM_OK;
+}
+
+struct StateTag {
+  uint64_t circuit_id;
+  int32_t batch, precision;
+};
+std::mutex g_reg_mu;
+std::unordered_map<void *, StateTag> g_registry;
+uint64_t g_next_id = 1;
+
+// Events around sweep kernels (diagnostic timing, QTM_OPT_TIMING).
+struct EventTimer : SweepTimer {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+  hipEvent_t cur = nullptr;
+  hipError_t err = hipSuccess;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) err = r;
+    return e;
+  }
+  void before(int kind, hipStream_t s) override {
+    (void)kind;
+    cur = get();
+    if (cur) (void)hipEventRecord(cur, s);
+  }
+  void after(int kind, hipStream_t s) override {
+    hipEvent_t e = get();
+    if (e) (void)hipEventRecord(e, s);
+    if (cur && e) pending[kind].push_back({cur, e});
+    cur = nullptr;
+  }
+  ~EventTimer() override {
+    for (auto &v : pending)
+      for (auto &pr : v) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct qtm_circuit_s {
+  uint64_t id = 0;
+  CircuitDesc desc;
+  HostCircuitInfo hinfo;
+  int path = QTM_PATH_AUTO;
+  int tile_qubits = 0;
+  int low_qubits = 0;
+  int renorm = 1;
+  int device = -1;
+  std::unique_ptr<EventTimer> timer;
+  bool uploaded = false;
+  DevCircuit dev;
+  std::vector<void *> owned;
+  std::map<std::pair<int, int>, DevPlan> plans;
+  DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm;
+
+  ~qtm_circuit_s() {
+    for (void *p : owned) (void)hipFree(p);
+    for (DevBuf *b : {&cs, &part, &gocc, &lam, &state_ws, &mats, &coef, &part_obs, &part_grad,
+                      &part_norm})
+      b->release();
+  }
+};
+
+struct qtm_multi_s {
+  std::vector<qtm_circuit_t> items;
+  std::vector<int64_t> in_off, w_off, out_off, st_off;
+};
+
+namespace {
+
+int ensure_device(qtm_circuit_t c) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (c->device >= 0 && c->device != dev)
+    return fail(QTM_ERR_UNSUPPORTED, "circuit handle used on a second device");
+  c->device = dev;
+  if (c->uploaded) return QTM_OK;
+  const CircuitDesc &d = c->desc;
+  DevCircuit &g = c->dev;
+  g.n = d.n;
+  g.n_inputs = d.n_inputs;
+  g.n_weights = d.n_weights;
+  g.n_obs = (int)d.masks.size();
+  g.n_occ = (int)d.occ_gate.size();
+  std::vector<int32_t> src, idx;
+  for (int k : d.occ_gate) {
+    src.push_back(d.gates[k].src);
+    idx.push_back(d.gates[k].index);
+  }
+  // CSR: parameter slot -> occurrences (construction order)
+  std::vector<int32_t> wp(d.n_weights + 1, 0), xp(d.n_inputs + 1, 0), wl, xl;
+  std::vector<std::vector<int32_t>> wlist(d.n_weights), xlist(d.n_inputs);
+  for (size_t k = 0; k < d.occ_gate.size(); ++k) {
+    const Gate &gt = d.gates[d.occ_gate[k]];
+    (gt.src == S_WEIGHT ? wlist[gt.index] : xlist[gt.index]).push_back((int32_t)k);
+  }
+  for (int j = 0; j < d.n_weights; ++j) {
+    wp[j + 1] = wp[j] + (int)wlist[j].size();
+    wl.insert(wl.end(), wlist[j].begin(), wlist[j].end());
+  }
+  for (int i = 0; i < d.n_inputs; ++i) {
+    xp[i + 1] = xp[i] + (int)xlist[i].size();
+    xl.insert(xl.end(), xlist[i].begin(), xlist[i].end());
+  }
+  int rc;
+  if ((rc = upload(&g.masks, d.masks, c->owned))) return rc;
+  if ((rc = upload(&g.occ_src, src, c->owned))) return rc;
+  if ((rc = upload(&g.occ_idx, idx, c->owned))) return rc;
+  if ((rc = upload(&g.w_ptr, wp, c->owned))) return rc;
+  if ((rc = upload(&g.w_list, wl, c->owned))) return rc;
+  if ((rc = upload(&g.x_ptr, xp, c->owned))) return rc;
+  if ((rc = upload(&g.x_list, xl, c->owned))) return rc;
+  c->uploaded = true;
+  return QTM_OK;
+}
+
+int default_kt(const qtm_circuit_s *c, int precision) {
+  int kt = c->tile_qubits > 0 ? c->tile_qubits : (precision == QTM_C128 ? 11 : 12);
+  kt = std::min(kt, kMaxTileQubits);
+  kt = std::min(kt, c->desc.n);
+  return std::max(kt, kMinTileQubits);
+}
+
+int get_plan(qtm_circuit_t c, int precision, DevPlan **out) {
+  const int kt = default_kt(c, precision);
+  const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
+  auto key = std::make_pair(kt, klo);
+  auto it = c->plans.find(key);
+  if (it != c->plans.end()) {
+    *out = &it->second;
+    return QTM_OK;
+  }
+  Plan plan = make_plan(c->desc, kt, klo);
+  std::string why = check_plan(c->desc, plan);
+  if (!why.empty()) return fail(QTM_ERR_UNSUPPORTED, "internal planner error: " + why);
+  Program prog = encode_program(c->desc, plan);
+  DevPlan dp;
+  dp.kt = kt;
+  dp.klo = klo;
+  dp.n_blocks = plan.n_blocks;
+  dp.n_gslots = plan.n_gslots;
+  dp.max_gslots = prog.max_gslots_per_sweep;
+  dp.n_sweeps = (int)plan.sweeps.size();
+  dp.sweep_off_fwd = prog.sweep_off_fwd;
+  dp.sweep_off_bwd = prog.sweep_off_bwd;
+  // block records for the matrix prep
+  std::vector<int32_t> blk, blk_off;
+  std::vector<int32_t> occ_gslot(c->desc.occ_gate.size(), 0);
+  for (int b = 0; b < plan.n_blocks; ++b) {
+    const FOp &o = plan.ops[plan.block_op[b]];
+    blk_off.push_back((int32_t)blk.size());
+    blk.push_back(o.q0);
+    blk.push_back((int32_t)o.gates.size());
+    for (int g : o.gates) {
+      const Gate &gt = c->desc.gates[g];
+      int occ = c->desc.gate_occ[g];
+      blk.push_back(gt.type);
+      blk.push_back(gt.src);
+      blk.push_back(gt.index);
+      blk.push_back(occ);
+      occ_gslot[occ] = o.gslot;
+    }
+  }
+  // observable signs of the last forward stage and seed signs of the first
+  // backward load layout
+  const int M = (int)c->desc.masks.size();
+  std::vector<float> osg((size_t)(M + 1) * kRegs, 1.f);
+  std::vector<double> ssg((size_t)M * kRegs, 1.0);
+  if (!plan.sweeps.empty()) {
+    const int last_fwd = prog.sweep_off_fwd.back();
+    const int32_t *H = prog.code.data() + last_fwd;
+    const int nst = H[0];
+    const int32_t *S = prog.code.data() + H[kSwStages + nst - 1];
+    const int first_bwd = prog.sweep_off_bwd.front();
+    const int32_t *HB = prog.code.data() + first_bwd;
+    for (int m = 0; m < M; ++m)
+      for (int j = 0; j < kRegs; ++j) {
+        uint32_t mk = (uint32_t)c->desc.masks[m];
+        osg[m * kRegs + j] = (__builtin_popcount((uint32_t)S[kStGlob + j] & mk) & 1) ? -1.f : 1.f;
+        ssg[m * kRegs + j] = (__builtin_popcount((uint32_t)HB[kSwLoadG + j] & mk) & 1) ? -1.0 : 1.0;
+      }
+  }
+  int rc;
+  if ((rc = upload(&dp.code, prog.code, c->owned))) return rc;
+  if ((rc = upload(&dp.blk, blk, c->owned))) return rc;
+  if ((rc = upload(&dp.blk_off, blk_off, c->owned))) return rc;
+  if ((rc = upload(&dp.occ_gslot, occ_gslot, c->owned))) return rc;
+  if ((rc = upload(&dp.obs_sgn_f, osg, c->owned))) return rc;
+  if ((rc = upload(&dp.seed_sgn, ssg, c->owned))) return rc;
+  auto ins = c->plans.emplace(key, dp);
+  *out = &ins.first->second;
+  return QTM_OK;
+}
+
+bool use_fused(const qtm_circuit_s *c) {
+  if (c->path == QTM_PATH_PLAIN) return false;
+  return c->desc.n >= kMinTileQubits;
+}
+
+int check_common(qtm_circuit_t c, int32_t batch, int32_t precision) {
+  if (!c) return fail(QTM_ERR_INVALID_ARG, "NULL circuit");
+  if (batch <= 0) return fail(QTM_ERR_INVALID_ARG, "batch must be >= 1");
+  if (precision != QTM_C64 && precision != QTM_C128)
+    return fail(QTM_ERR_INVALID_ARG, "precision must be QTM_C64 or QTM_C128");
+  if (c->path == QTM_PATH_FUSED && c->desc.n < kMinTileQubits)
+    return fail(QTM_ERR_UNSUPPORTED, "the fused path needs at least 4 qubits");
+  size_t amps = (size_t)batch << c->desc.n;
+  if (amps / (size_t)batch != ((size_t)1 << c->desc.n))
+    return fail(QTM_ERR_INVALID_ARG, "batch too large");
+  return QTM_OK;
+}
+
+size_t elem_bytes(int precision) { return precision == QTM_C128 ? 16 : 8; }
+
+int do_forward(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, const double *w,
+               double *out, void *state, bool keep, hipStream_t s) {
+  const DevCircuit &d = c->dev;
+  int rc;
+  if (use_fused(c)) {
+    DevPlan *p = nullptr;
+    if ((rc = get_plan(c, prec, &p))) return rc;
+    if ((rc = c->mats.ensure((size_t)B * std::max(p->n_blocks, 1) * sizeof(M2<double>)))) return rc;
+    if ((rc = c->part_obs.ensure(fused_part_obs_doubles(d, *p, B) * sizeof(double)))) return rc;
+    hipError_t e =
+        prec == QTM_C64
+            ? fused_forward<float>(d, *p, B, x, w, c->mats.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get())
+            : fused_forward<double>(d, *p, B, x, w, c->mats.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get());
+    if (e != hipSuccess) return hip_fail(e, "fused forward launch");
+    return QTM_OK;
+  }
+  if ((rc = c->cs.ensure((size_t)B * std::max(d.n_occ, 1) * sizeof(double2)))) return rc;
+  if ((rc = c->part.ensure(plain_part_doubles(d, B) * sizeof(double)))) return rc;
+  hipError_t e = launch_half_angles(d, B, x, w, (double2 *)c->cs.p, s);
+  if (e == hipSuccess)
+    e = prec == QTM_C64 ? plain_forward<float>(d, c->hinfo, B, (double2 *)c->cs.p, state,
+                                               (double *)c->part.p, out, false, s)
+                        : plain_forward<double>(d, c->hinfo, B, (double2 *)c->cs.p, state,
+                                                (double *)c->part.p, out, false, s);
+  if (e != hipSuccess) return hip_fail(e, "plain forward launch");
+  return QTM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qtm_last_error(void) { return g_err.c_str(); }
+
+const char *qtm_version(void) { return "qtm 0.1 (gfx950)"; }
+
+int qtm_circuit_create(int32_t n_qubits, const qtm_gate *gates, int32_t n_gates, int32_t n_inputs,
+                       int32_t n_weights, const uint64_t *obs_zmask, int32_t n_obs,
+                       qtm_circuit_t *out) {
+  if (!out) return fail(QTM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  std::unique_ptr<qtm_circuit_s> c(new (std::nothrow) qtm_circuit_s());
+  if (!c) return fail(QTM_ERR_WORKSPACE, "out of host memory");
+  std::string err;
+  int rc = validate_and_build(n_qubits, reinterpret_cast<const Gate *>(gates), n_gates, n_inputs,
+                              n_weights, obs_zmask, n_obs, c->desc, err);
+  if (rc) return fail(rc, err);
+  c->hinfo.gates = c->desc.gates;
+  c->hinfo.gate_occ = c->desc.gate_occ;
+  {
+    std::lock_guard<std::mutex> g(g_reg_mu);
+    c->id = g_next_id++;
+  }
+  *out = c.release();
+  return QTM_OK;
+}
+
+int qtm_circuit_destroy(qtm_circuit_t c) {
+  if (!c) return QTM_OK;
+  {
+    std::lock_guard<std::mutex> g(g_reg_mu);
+    for (auto it = g_registry.begin(); it != g_registry.end();)
+      it = it->second.circuit_id == c->id ? g_registry.erase(it) : std::next(it);
+  }
+  delete c;
+  return QTM_OK;
+}
+
+int qtm_set_option(qtm_circuit_t c, int32_t option, int64_t value) {
+  if (!c) return fail(QTM_ERR_INVALID_ARG, "NULL circuit");
+  switch (option) {
+    case QTM_OPT_PATH:
+      if (value < QTM_PATH_AUTO || value > QTM_PATH_FUSED) return fail(QTM_ERR_INVALID_ARG, "bad path");
+      c->path = (int)value;
+      return QTM_OK;
+    case QTM_OPT_TILE_QUBITS:
+      if (value != 0 && (value < kMinTileQubits || value > kMaxTileQubits))
+        return fail(QTM_ERR_INVALID_ARG, "tile qubits must be 0 or 4..12");
+      c->tile_qubits = (int)value;
+      return QTM_OK;
+    case QTM_OPT_LOW_QUBITS:
+      if (value < 0 || value > kMaxTileQubits) return fail(QTM_ERR_INVALID_ARG, "low qubits must be 0..12");
+      c->low_qubits = (int)value;
+      return QTM_OK;
+    case QTM_OPT_RENORM:
+      c->renorm = value ? 1 : 0;
+      return QTM_OK;
+    case QTM_OPT_TIMING:
+      if (value && !c->timer) c->timer.reset(new EventTimer());
+      if (!value) c->timer.reset();
+      return QTM_OK;
+    default:
+      return fail(QTM_ERR_UNSUPPORTED, "unknown option");
+  }
+}
+
+int qtm_state_bytes(qtm_circuit_t c, int32_t batch, int32_t precision, size_t *bytes) {
+  int rc = check_common(c, batch, precision);
+  if (rc) return rc;
+  if (!bytes) return fail(QTM_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = ((size_t)batch << c->desc.n) * elem_bytes(precision);
+  return QTM_OK;
+}
+
+int qtm_forward(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
+                const double *weights, double *expvals, void *state, void *stream) {
+  int rc = check_common(c, batch, precision);
+  if (rc) return rc;
+  if (!expvals) return fail(QTM_ERR_INVALID_ARG, "expvals is NULL");
+  if (c->desc.n_inputs > 0 && !inputs) return fail(QTM_ERR_INVALID_ARG, "inputs is NULL");
+  if (c->desc.n_weights > 0 && !weights) return fail(QTM_ERR_INVALID_ARG, "weights is NULL");
+  if ((rc = ensure_device(c))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t sbytes = ((size_t)batch << c->desc.n) * elem_bytes(precision);
+  void *st = state;
+  if (!st) {
+    if ((rc = c->state_ws.ensure(sbytes))) return rc;
+    st = c->state_ws.p;
+  }
+  rc = do_forward(c, batch, precision, inputs, weights, expvals, st, state != nullptr, s);
+  if (rc) return rc;
+  if (state) {
+    std::lock_guard<std::mutex> g(g_reg_mu);
+    g_registry[state] = StateTag{c->id, batch, precision};
+  }
+  return QTM_OK;
+}
+
+int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
+                 const double *weights, const double *grad_expvals, void *state,
+                 double *grad_weights, double *grad_inputs, void *stream) {
+  int rc = check_common(c, batch, precision);
+  if (rc) return rc;
+  if (!grad_expvals) return fail(QTM_ERR_INVALID_ARG, "grad_expvals is NULL");
+  if (c->desc.n_weights > 0 && !grad_weights) return fail(QTM_ERR_INVALID_ARG, "grad_weights is NULL");
+  if (c->desc.n_inputs > 0 && !inputs) return fail(QTM_ERR_INVALID_ARG, "inputs is NULL");
+  if (c->desc.n_weights > 0 && !weights) return fail(QTM_ERR_INVALID_ARG, "weights is NULL");
+  if ((rc = ensure_device(c))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const DevCircuit &d = c->dev;
+  const size_t sbytes = ((size_t)batch << c->desc.n) * elem_bytes(precision);
+  void *psi = state;
+  if (state) {
+    std::lock_guard<std::mutex> g(g_reg_mu);
+    auto it = g_registry.find(state);
+    if (it == g_registry.end() || it->second.circuit_id != c->id || it->second.batch != batch ||
+        it->second.precision != precision)
+      return fail(QTM_ERR_STATE, "state buffer was not filled by qtm_forward for this circuit, batch and precision");
+    g_registry.erase(it);
+  } else {
+    // recompute the forward into the workspace (expectation values go to a scratch area)
+    if ((rc = c->state_ws.ensure(sbytes))) return rc;
+    psi = c->state_ws.p;
+    if ((rc = c->gocc.ensure((size_t)batch * std::max(std::max(d.n_occ, d.n_obs), 1) * sizeof(double))))
+      return rc;
+    if ((rc = do_forward(c, batch, precision, inputs, weights, (double *)c->gocc.p, psi, true, s)))
+      return rc;
+  }
+  if ((rc = c->lam.ensure(sbytes))) return rc;
+  if ((rc = c->gocc.ensure((size_t)batch * std::max(std::max(d.n_occ, d.n_obs), 1) * sizeof(double))))
+    return rc;
+  hipError_t e;
+  if (use_fused(c)) {
+    DevPlan *p = nullptr;
+    if ((rc = get_plan(c, precision, &p))) return rc;
+    if ((rc = c->mats.ensure((size_t)batch * std::max(p->n_blocks, 1) * sizeof(M2<double>)))) return rc;
+    if ((rc = c->coef.ensure((size_t)batch * std::max(d.n_occ, 1) * 3 * sizeof(double)))) return rc;
+    if ((rc = c->part_grad.ensure(fused_part_grad_doubles(d, *p, batch) * sizeof(double)))) return rc;
+    if ((rc = c->part_norm.ensure((size_t)batch * fused_wg_per_sample(d.n, p->kt) * sizeof(double))))
+      return rc;
+    e = precision == QTM_C64
+            ? fused_backward<float>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
+                                    (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
+                                    (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
+                                    grad_inputs, s, c->timer.get())
+            : fused_backward<double>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
+                                     (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
+                                     (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
+                                     grad_inputs, s, c->timer.get());
+  } else {
+    if ((rc = c->cs.ensure((size_t)batch * std::max(d.n_occ, 1) * sizeof(double2)))) return rc;
+    if ((rc = c->part.ensure(plain_part_doubles(d, batch) * sizeof(double)))) return rc;
+    e = launch_half_angles(d, batch, inputs, weights, (double2 *)c->cs.p, s);
+    if (e == hipSuccess)
+      e = precision == QTM_C64
+              ? plain_backward<float>(d, c->hinfo, batch, (double2 *)c->cs.p, psi, c->lam.p,
+                                      grad_expvals, (double *)c->part.p, (double *)c->gocc.p,
+                                      grad_weights, grad_inputs, s)
+              : plain_backward<double>(d, c->hinfo, batch, (double2 *)c->cs.p, psi, c->lam.p,
+                                       grad_expvals, (double *)c->part.p, (double *)c->gocc.p,
+                                       grad_weights, grad_inputs, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  return QTM_OK;
+}
+
+int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *launches) {
+  if (!c || kind < 0 || kind > 1 || !total_ms || !launches)
+    return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  *total_ms = 0.0;
+  *launches = 0;
+  if (!c->timer) return fail(QTM_ERR_INVALID_ARG, "timing is not enabled (QTM_OPT_TIMING)");
+  EventTimer &t = *c->timer;
+  if (t.err != hipSuccess) return hip_fail(t.err, "hipEventCreate");
+  for (auto &pr : t.pending[kind]) {
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    *total_ms += ms;
+    *launches += 1;
+    t.pool.push_back(pr.first);
+    t.pool.push_back(pr.second);
+  }
+  t.pending[kind].clear();
+  return QTM_OK;
+}
+
+// Diagnostics: JSON description of the fused plan for (precision) into buf.
+int qtm_plan_json(qtm_circuit_t c, int32_t precision, char *buf, size_t len, size_t *needed) {
+  if (!c) return fail(QTM_ERR_INVALID_ARG, "NULL circuit");
+  if (c->desc.n < kMinTileQubits) return fail(QTM_ERR_UNSUPPORTED, "no fused plan below 4 qubits");
+  const int kt = default_kt(c, precision);
+  const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
+  Plan plan = make_plan(c->desc, kt, klo);
+  std::string why = check_plan(c->desc, plan);
+  std::string js = plan_json(c->desc, plan);
+  if (!why.empty()) {
+    js = "{\"error\":\"" + why + "\"}";
+  } else {
+    // append the encoded device program (for layout checks)
+    Program prog = encode_program(c->desc, plan);
+    std::string extra = ",\"code\":[";
+    for (size_t i = 0; i < prog.code.size(); ++i) extra += (i ? "," : "") + std::to_string(prog.code[i]);
+    extra += "],\"sweep_off_fwd\":[";
+    for (size_t i = 0; i < prog.sweep_off_fwd.size(); ++i)
+      extra += (i ? "," : "") + std::to_string(prog.sweep_off_fwd[i]);
+    extra += "],\"sweep_off_bwd\":[";
+    for (size_t i = 0; i < prog.sweep_off_bwd.size(); ++i)
+      extra += (i ? "," : "") + std::to_string(prog.sweep_off_bwd[i]);
+    extra += "]}";
+    js.pop_back();
+    js += extra;
+  }
+  if (needed) *needed = js.size() + 1;
+  if (buf && len > 0) {
+    size_t k = std::min(len - 1, js.size());
+    memcpy(buf, js.data(), k);
+    buf[k] = 0;
+  }
+  return why.empty() ? QTM_OK : fail(QTM_ERR_UNSUPPORTED, why);
+}
+
+// --- uneven batch --------------------------------------------------------
+
+int qtm_multi_create(const qtm_circuit_t *items, int32_t count, qtm_multi_t *out) {
+  if (!out || count < 0 || (count > 0 && !items)) return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  *out = nullptr;
+  std::unique_ptr<qtm_multi_s> m(new (std::nothrow) qtm_multi_s());
+  if (!m) return fail(QTM_ERR_WORKSPACE, "out of host memory");
+  int64_t io = 0, wo = 0, oo = 0, so = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!items[i]) return fail(QTM_ERR_INVALID_ARG, "NULL item");
+    m->items.push_back(items[i]);
+    m->in_off.push_back(io);
+    m->w_off.push_back(wo);
+    m->out_off.push_back(oo);
+    m->st_off.push_back(so);
+    io += items[i]->desc.n_inputs;
+    wo += items[i]->desc.n_weights;
+    oo += (int64_t)items[i]->desc.masks.size();
+    so += (int64_t)8 << items[i]->desc.n;
+  }
+  m->in_off.push_back(io);
+  m->w_off.push_back(wo);
+  m->out_off.push_back(oo);
+  m->st_off.push_back(so);
+  *out = m.release();
+  return QTM_OK;
+}
+
+int qtm_multi_destroy(qtm_multi_t m) {
+  delete m;
+  return QTM_OK;
+}
+
+int qtm_multi_layout(qtm_multi_t m, int64_t *in_off, int64_t *w_off, int64_t *out_off,
+                     size_t *state_bytes) {
+  if (!m) return fail(QTM_ERR_INVALID_ARG, "NULL multi handle");
+  size_t n = m->items.size() + 1;
+  if (in_off) memcpy(in_off, m->in_off.data(), n * sizeof(int64_t));
+  if (w_off) memcpy(w_off, m->w_off.data(), n * sizeof(int64_t));
+  if (out_off) memcpy(out_off, m->out_off.data(), n * sizeof(int64_t));
+  if (state_bytes) *state_bytes = (size_t)m->st_off.back();
+  return QTM_OK;
+}
+
+int qtm_multi_forward(qtm_multi_t m, const double *inputs, const double *weights, double *expvals,
+                      void *state, void *stream) {
+  if (!m || !expvals || !state) return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  for (size_t i = 0; i < m->items.size(); ++i) {
+    qtm_circuit_t c = m->items[i];
+    int rc = qtm_forward(c, 1, QTM_C64, inputs ? inputs + m->in_off[i] : nullptr,
+                         weights ? weights + m->w_off[i] : nullptr, expvals + m->out_off[i],
+                         (char *)state + m->st_off[i], stream);
+    if (rc) return rc;
+  }
+  return QTM_OK;
+}
+
+int qtm_multi_backward(qtm_multi_t m, const double *inputs, const double *weights,
+                       const double *grad_expvals, void *state, double *grad_weights,
+                       double *grad_inputs, void *stream) {
+  if (!m || !grad_expvals || !state || !grad_weights) return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  for (size_t i = 0; i < m->items.size(); ++i) {
+    qtm_circuit_t c = m->items[i];
+    int rc = qtm_backward(c, 1, QTM_C64, inputs ? inputs + m->in_off[i] : nullptr,
+                          weights ? weights + m->w_off[i] : nullptr, grad_expvals + m->out_off[i],
+                          (char *)state + m->st_off[i], grad_weights + m->w_off[i],
+                          grad_inputs ? grad_inputs + m->in_off[i] : nullptr, stream);
+    if (rc) return rc;
+  }
+  return QTM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,581 @@
+// Circuit validation, rotation fusion, dependency DAG and sweep/stage planner.
+#include "circuit.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <set>
+#include <sstream>
+
+#include "../../include/qtm.h"
+
+namespace qtm {
+
+int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_inputs,
+                       int32_t n_weights, const uint64_t *masks, int32_t n_obs,
+                       CircuitDesc &out, std::string &err) {
+  char buf[256];
+  if (n > 30) {
+    err = "n_qubits > 30 is not supported";
+    return QTM_ERR_UNSUPPORTED;
+  }
+  if (n < 1) {
+    err = "n_qubits must be >= 1";
+    return QTM_ERR_INVALID_ARG;
+  }
+  if (n_gates < 0 || n_inputs < 0 || n_weights < 0) {
+    err = "negative count";
+    return QTM_ERR_INVALID_ARG;
+  }
+  if (n_gates > 0 && !gates) {
+    err = "gates is NULL";
+    return QTM_ERR_INVALID_ARG;
+  }
+  if (n_obs < 1 || !masks) {
+    err = "need at least one observable mask";
+    return QTM_ERR_INVALID_ARG;
+  }
+  out = CircuitDesc();
+  out.n = n;
+  out.n_inputs = n_inputs;
+  out.n_weights = n_weights;
+  for (int32_t k = 0; k < n_gates; ++k) {
+    const Gate &g = gates[k];
+    if (g.type < 0 || g.type > 4) {
+      snprintf(buf, sizeof buf, "gate %d: unknown type %d", k, g.type);
+      err = buf;
+      return QTM_ERR_UNSUPPORTED;
+    }
+    if (g.q0 < 0 || g.q0 >= n) {
+      snprintf(buf, sizeof buf, "gate %d: qubit %d out of range", k, g.q0);
+      err = buf;
+      return QTM_ERR_INVALID_ARG;
+    }
+    if (is_rotation(g.type)) {
+      if (g.src == S_INPUT) {
+        if (g.index < 0 || g.index >= n_inputs) {
+          snprintf(buf, sizeof buf, "gate %d: input index %d out of range", k, g.index);
+          err = buf;
+          return QTM_ERR_INVALID_ARG;
+        }
+      } else if (g.src == S_WEIGHT) {
+        if (g.index < 0 || g.index >= n_weights) {
+          snprintf(buf, sizeof buf, "gate %d: weight index %d out of range", k, g.index);
+          err = buf;
+          return QTM_ERR_INVALID_ARG;
+        }
+      } else {
+        snprintf(buf, sizeof buf, "gate %d: rotation needs src INPUT or WEIGHT", k);
+        err = buf;
+        return QTM_ERR_INVALID_ARG;
+      }
+    } else {
+      if (g.q1 < 0 || g.q1 >= n) {
+        snprintf(buf, sizeof buf, "gate %d: qubit %d out of range", k, g.q1);
+        err = buf;
+        return QTM_ERR_INVALID_ARG;
+      }
+      if (g.q1 == g.q0) {
+        snprintf(buf, sizeof buf, "gate %d: both qubits are %d", k, g.q0);
+        err = buf;
+        return QTM_ERR_INVALID_ARG;
+      }
+    }
+    Gate c = g;
+    if (!is_rotation(g.type)) {
+      c.src = S_NONE;
+      c.index = 0;
+    } else {
+      c.q1 = 0;
+    }
+    out.gates.push_back(c);
+  }
+  for (int32_t m = 0; m < n_obs; ++m) {
+    if (n < 64 && (masks[m] >> n) != 0) {
+      snprintf(buf, sizeof buf, "observable %d: mask has a bit >= n_qubits", m);
+      err = buf;
+      return QTM_ERR_INVALID_ARG;
+    }
+    out.masks.push_back(masks[m]);
+  }
+  out.gate_occ.assign(out.gates.size(), -1);
+  for (size_t k = 0; k < out.gates.size(); ++k)
+    if (is_rotation(out.gates[k].type)) {
+      out.gate_occ[k] = (int32_t)out.occ_gate.size();
+      out.occ_gate.push_back((int32_t)k);
+    }
+  return QTM_OK;
+}
+
+// --------------------------------------------------------------------------
+// fusion and DAG
+
+static std::vector<int> wires(const FOp &o) {
+  if (o.kind == FK_BLOCK) return {o.q0};
+  return {o.q0, o.q1};
+}
+
+static bool commute(const FOp &a, const FOp &b) {
+  std::vector<int> wa = wires(a), wb = wires(b);
+  bool share = false;
+  for (int x : wa)
+    for (int y : wb) share |= x == y;
+  if (!share) return true;
+  if (a.diagonal && b.diagonal) return true;
+  auto cnot_diag = [](const FOp &c, const FOp &d) {  // c CNOT, d diagonal
+    for (int w : wires(d))
+      if (w == c.q1) return false;
+    return true;
+  };
+  if (a.kind == FK_CNOT && b.diagonal) return cnot_diag(a, b);
+  if (b.kind == FK_CNOT && a.diagonal) return cnot_diag(b, a);
+  if (a.kind == FK_CNOT && b.kind == FK_CNOT) return a.q0 != b.q1 && b.q0 != a.q1;
+  return false;
+}
+
+static std::vector<FOp> fuse(const CircuitDesc &c) {
+  std::vector<FOp> ops;
+  std::vector<int> open(c.n, -1);
+  for (size_t k = 0; k < c.gates.size(); ++k) {
+    const Gate &g = c.gates[k];
+    if (is_rotation(g.type)) {
+      int q = g.q0;
+      if (open[q] < 0) {
+        FOp o;
+        o.kind = FK_BLOCK;
+        o.q0 = q;
+        o.diagonal = true;
+        open[q] = (int)ops.size();
+        ops.push_back(o);
+      }
+      FOp &o = ops[open[q]];
+      o.gates.push_back((int32_t)k);
+      o.has_param = true;
+      if (g.type != G_RZ) o.diagonal = false;
+    } else {
+      open[g.q0] = -1;
+      open[g.q1] = -1;
+      FOp o;
+      o.kind = g.type == G_CNOT ? FK_CNOT : FK_CZ;
+      o.q0 = g.q0;
+      o.q1 = g.q1;
+      o.gates.push_back((int32_t)k);
+      o.diagonal = g.type == G_CZ;
+      ops.push_back(o);
+    }
+  }
+  return ops;
+}
+
+// predecessors that do not commute (all earlier ones, not only immediate)
+static std::vector<std::vector<int>> build_preds(const std::vector<FOp> &ops, int n) {
+  std::vector<std::vector<int>> on_wire(n);
+  std::vector<std::vector<int>> preds(ops.size());
+  for (size_t j = 0; j < ops.size(); ++j) {
+    std::set<int> ps;
+    for (int w : wires(ops[j]))
+      for (int i : on_wire[w])
+        if (!commute(ops[i], ops[j])) ps.insert(i);
+    preds[j].assign(ps.begin(), ps.end());
+    for (int w : wires(ops[j])) on_wire[w].push_back((int)j);
+  }
+  return preds;
+}
+
+namespace {
+
+struct Sched {
+  const std::vector<FOp> &ops;
+  const std::vector<std::vector<int>> &succ;
+  std::vector<int> left;   // unscheduled predecessors
+  std::vector<char> done;
+
+  // Execute (or simulate) every op that becomes ready and whose target is in
+  // `inset`; `allowed` restricts the op set (sweep scope).  Returns the ops
+  // run, in order.
+  std::vector<int> run(const std::vector<char> &inset, const std::vector<char> *allowed,
+                       bool commit) {
+    std::vector<int> lft = left;
+    std::vector<char> dn = done;
+    std::vector<int> order;
+    std::vector<int> ready;
+    for (size_t i = 0; i < ops.size(); ++i)
+      if (!dn[i] && lft[i] == 0 && (!allowed || (*allowed)[i])) ready.push_back((int)i);
+    std::sort(ready.begin(), ready.end());
+    bool progress = true;
+    while (progress) {
+      progress = false;
+      std::vector<int> next;
+      for (int i : ready) {
+        const FOp &o = ops[i];
+        int t = o.target();
+        if (t >= 0 && !inset[t]) {
+          next.push_back(i);
+          continue;
+        }
+        dn[i] = 1;
+        order.push_back(i);
+        progress = true;
+        for (int s : succ[i])
+          if (--lft[s] == 0 && (!allowed || (*allowed)[s])) next.push_back(s);
+      }
+      std::sort(next.begin(), next.end());
+      next.erase(std::unique(next.begin(), next.end()), next.end());
+      ready.swap(next);
+    }
+    if (commit) {
+      left = lft;
+      done = dn;
+    }
+    return order;
+  }
+};
+
+// Greedy choice of `k` members of a set among `cands`, starting from `base`:
+// each step adds the candidate that lets the most ops run (ties: the one whose
+// earliest pending op comes first).
+std::vector<char> choose_set(Sched &S, const std::vector<char> &base, const std::vector<int> &cands,
+                             int k, int nq, const std::vector<char> *allowed) {
+  std::vector<char> in = base;
+  std::vector<int> first(nq, 1 << 30);
+  for (size_t i = 0; i < S.ops.size(); ++i)
+    if (!S.done[i] && (!allowed || (*allowed)[i])) {
+      int t = S.ops[i].target();
+      if (t >= 0) first[t] = std::min(first[t], (int)i);
+    }
+  int have = 0;
+  for (int q : cands) have += in[q] ? 1 : 0;
+  while (have < k) {
+    int best = -1;
+    long best_score = -1;
+    for (int q : cands) {
+      if (in[q]) continue;
+      in[q] = 1;
+      long cnt = (long)S.run(in, allowed, false).size();
+      in[q] = 0;
+      long score = cnt * (1L << 31) - first[q];
+      if (score > best_score) {
+        best_score = score;
+        best = q;
+      }
+    }
+    if (best < 0) break;
+    in[best] = 1;
+    ++have;
+  }
+  return in;
+}
+
+}  // namespace
+
+Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo) {
+  Plan p;
+  p.n = c.n;
+  p.kt = kt;
+  // the tile must have at least one free slot when the state is larger than a tile
+  p.klo = std::min(klo, c.n > kt ? kt - 1 : kt);
+  p.ops = fuse(c);
+  for (size_t i = 0; i < p.ops.size(); ++i)
+    if (p.ops[i].kind == FK_BLOCK) {
+      p.ops[i].block = p.n_blocks++;
+      p.block_op.push_back((int)i);
+      if (p.ops[i].has_param) p.ops[i].gslot = p.n_gslots++;
+    }
+  auto preds = build_preds(p.ops, c.n);
+  std::vector<std::vector<int>> succ(p.ops.size());
+  std::vector<int> left(p.ops.size());
+  for (size_t j = 0; j < p.ops.size(); ++j) {
+    left[j] = (int)preds[j].size();
+    for (int i : preds[j]) succ[i].push_back((int)j);
+  }
+  Sched S{p.ops, succ, left, std::vector<char>(p.ops.size(), 0)};
+  size_t n_done = 0;
+  std::vector<int> all_q(c.n);
+  for (int q = 0; q < c.n; ++q) all_q[q] = q;
+  while (n_done < p.ops.size()) {
+    // tile: the klo low qubits plus the best kt - klo others
+    std::vector<char> base(c.n, 0);
+    for (int q = 0; q < p.klo; ++q) base[q] = 1;
+    std::vector<char> T = choose_set(S, base, all_q, kt, c.n, nullptr);
+    std::vector<int> order = S.run(T, nullptr, true);
+    if (order.empty()) break;  // cannot happen: the earliest ready op's target gets picked
+    n_done += order.size();
+    Sweep sw;
+    for (int q = 0; q < c.n; ++q)
+      if (T[q]) sw.tile.push_back(q);
+    // tile-local position of each global qubit
+    std::vector<int> loc(c.n, -1);
+    for (size_t k = 0; k < sw.tile.size(); ++k) loc[sw.tile[k]] = (int)k;
+    // stages inside the sweep
+    std::vector<char> allowed(p.ops.size(), 0);
+    for (int i : order) allowed[i] = 1;
+    Sched St{p.ops, succ, std::vector<int>(p.ops.size(), 0), std::vector<char>(p.ops.size(), 1)};
+    for (int i : order) {
+      St.done[i] = 0;
+      int cnt = 0;
+      for (int pr : preds[i]) cnt += allowed[pr] ? 1 : 0;
+      St.left[i] = cnt;
+    }
+    size_t st_done = 0;
+    while (st_done < order.size()) {
+      std::vector<char> none(c.n, 0);
+      std::vector<char> R = choose_set(St, none, sw.tile, kRegBits, c.n, &allowed);
+      // fill to exactly kRegBits register bits
+      for (int q : sw.tile) {
+        int cnt = 0;
+        for (int x : sw.tile) cnt += R[x] ? 1 : 0;
+        if (cnt >= kRegBits) break;
+        R[q] = 1;
+      }
+      std::vector<int> sto = St.run(R, &allowed, true);
+      if (sto.empty()) break;
+      st_done += sto.size();
+      Stage st;
+      int r = 0;
+      for (int q : sw.tile)
+        if (R[q]) st.regpos[r++] = loc[q];
+      st.ops.assign(sto.begin(), sto.end());
+      sw.stages.push_back(st);
+    }
+    for (int i : order)
+      if (p.ops[i].kind == FK_BLOCK && p.ops[i].gslot >= 0) sw.gslots.push_back(p.ops[i].gslot);
+    p.sweeps.push_back(sw);
+  }
+  return p;
+}
+
+std::string check_plan(const CircuitDesc &c, const Plan &p) {
+  std::vector<int> pos(p.ops.size(), -1);
+  int counter = 0;
+  for (size_t s = 0; s < p.sweeps.size(); ++s) {
+    const Sweep &sw = p.sweeps[s];
+    if ((int)sw.tile.size() != p.kt) return "tile size mismatch";
+    for (int q = 0; q < p.klo; ++q)
+      if (sw.tile[q] != q) return "low qubits not in tile";
+    for (const Stage &st : sw.stages) {
+      std::set<int> rb(st.regpos, st.regpos + kRegBits);
+      if ((int)rb.size() != kRegBits) return "duplicate register bits";
+      for (int i : st.ops) {
+        if (i < 0 || i >= (int)p.ops.size()) return "bad op index";
+        if (pos[i] >= 0) return "op scheduled twice";
+        pos[i] = counter++;
+        int t = p.ops[i].target();
+        if (t >= 0) {
+          int l = -1;
+          for (int k = 0; k < p.kt; ++k)
+            if (sw.tile[k] == t) l = k;
+          if (l < 0) return "target outside tile";
+          if (!rb.count(l)) return "target outside register bits";
+        }
+      }
+    }
+  }
+  for (size_t i = 0; i < p.ops.size(); ++i)
+    if (pos[i] < 0) return "op never scheduled";
+  // every pair of non-commuting ops keeps its order
+  auto preds = build_preds(p.ops, c.n);
+  for (size_t j = 0; j < p.ops.size(); ++j)
+    for (int i : preds[j])
+      if (pos[i] > pos[(int)j]) return "dependency order violated";
+  size_t ng = 0;
+  for (const FOp &o : p.ops) ng += o.gates.size();
+  if (ng != c.gates.size()) return "gate count mismatch";
+  return "";
+}
+
+std::string plan_json(const CircuitDesc &c, const Plan &p) {
+  std::ostringstream s;
+  s << "{\"n\":" << p.n << ",\"kt\":" << p.kt << ",\"klo\":" << p.klo << ",\"n_blocks\":" << p.n_blocks
+    << ",\"n_gslots\":" << p.n_gslots << ",\"sweeps\":[";
+  for (size_t i = 0; i < p.sweeps.size(); ++i) {
+    const Sweep &sw = p.sweeps[i];
+    if (i) s << ",";
+    s << "{\"tile\":[";
+    for (size_t k = 0; k < sw.tile.size(); ++k) s << (k ? "," : "") << sw.tile[k];
+    s << "],\"stages\":[";
+    for (size_t t = 0; t < sw.stages.size(); ++t) {
+      const Stage &st = sw.stages[t];
+      if (t) s << ",";
+      s << "{\"regpos\":[" << st.regpos[0] << "," << st.regpos[1] << "," << st.regpos[2] << ","
+        << st.regpos[3] << "],\"gates\":[";
+      bool first = true;
+      for (int o : st.ops)
+        for (int g : p.ops[o].gates) {
+          s << (first ? "" : ",") << g;
+          first = false;
+        }
+      s << "]}";
+    }
+    s << "]}";
+  }
+  s << "]}";
+  (void)c;
+  return s.str();
+}
+
+// --------------------------------------------------------------------------
+// program encoding
+
+static uint32_t pdep_bits(uint32_t v, const int *pos, int npos) {
+  uint32_t r = 0;
+  for (int i = 0; i < npos; ++i)
+    if ((v >> i) & 1u) r |= 1u << pos[i];
+  return r;
+}
+
+static int parity32(uint32_t v) { return __builtin_popcount(v) & 1; }
+
+static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, bool backward,
+                         std::vector<int32_t> &code, std::vector<int32_t> &sweep_offs,
+                         int32_t &max_gs) {
+  const int kt = p.kt, nthr_bits = kt - kRegBits;
+  const int off = (int)code.size();
+  sweep_offs.push_back(off);
+  const int nst = (int)sw.stages.size();
+  int hdr = kSwStages + nst + (int)sw.gslots.size();
+  code.resize(off + hdr, 0);
+  int32_t *H = nullptr;
+  auto h = [&](int i) -> int32_t & { return code[off + i]; };
+  (void)H;
+  std::vector<int> outer;
+  std::vector<char> intile(c.n, 0);
+  for (int q : sw.tile) intile[q] = 1;
+  for (int q = 0; q < c.n; ++q)
+    if (!intile[q]) outer.push_back(q);
+  h(0) = nst;
+  h(1) = (int)outer.size();
+  h(2) = (int)sw.gslots.size();
+  max_gs = std::max(max_gs, (int)sw.gslots.size());
+  for (size_t i = 0; i < outer.size(); ++i) h(kSwOuter + i) = outer[i];
+  for (int k = 0; k < kt; ++k) h(kSwTile + k) = sw.tile[k];
+  // load layout: local index i = t + 2^(kt-4) * j
+  for (int j = 0; j < kRegs; ++j) {
+    uint32_t local = (uint32_t)j << nthr_bits;
+    h(kSwLoadG + j) = (int32_t)pdep_bits(local, sw.tile.data(), kt);
+    h(kSwLoadL + j) = (int32_t)lds_swizzle(local);
+  }
+  for (int i = 0; i < nthr_bits; ++i) h(kSwLoadTb + i) = sw.tile[i];
+  // sweep-local gslot numbering: order of sw.gslots
+  std::vector<int> local_gs(p.n_gslots, -1);
+  for (size_t i = 0; i < sw.gslots.size(); ++i) {
+    local_gs[sw.gslots[i]] = (int)i;
+    h(kSwStages + nst + (int)i) = sw.gslots[i];
+  }
+  for (int si = 0; si < nst; ++si) {
+    const Stage &st = sw.stages[backward ? nst - 1 - si : si];
+    h(kSwStages + si) = (int32_t)code.size();
+    const int so = (int)code.size();
+    code.resize(so + kStOps, 0);
+    auto sh = [&](int i) -> int32_t & { return code[so + i]; };
+    int rp[kRegBits];
+    for (int r = 0; r < kRegBits; ++r) rp[r] = st.regpos[r];
+    uint32_t W[kRegs];
+    for (int j = 0; j < kRegs; ++j) {
+      uint32_t local = pdep_bits((uint32_t)j, rp, kRegBits);
+      sh(kStLds + j) = (int32_t)lds_swizzle(local);
+      W[j] = pdep_bits(local, sw.tile.data(), kt);
+      sh(kStGlob + j) = (int32_t)W[j];
+    }
+    std::vector<char> isreg(kt, 0);
+    for (int r = 0; r < kRegBits; ++r) isreg[rp[r]] = 1;
+    int ti = 0;
+    for (int k = 0; k < kt; ++k)
+      if (!isreg[k]) {
+        sh(kStTbLocal + ti) = k;
+        sh(kStTbGlob + ti) = sw.tile[k];
+        ++ti;
+      }
+    // ops: CZs merged into one diag op at the position of the first CZ of a run
+    std::vector<int> ops = st.ops;
+    if (backward) std::reverse(ops.begin(), ops.end());
+    std::vector<std::vector<int32_t>> enc;
+    std::vector<std::vector<int32_t>> diag_recs;
+    std::vector<std::pair<int, int>> czrun;
+    auto flush_cz = [&]() {
+      if (czrun.empty()) return;
+      // groups by distance
+      std::vector<std::pair<int, uint32_t>> groups;
+      for (auto &pr : czrun) {
+        int a = std::min(pr.first, pr.second), b = std::max(pr.first, pr.second);
+        int d = b - a;
+        bool found = false;
+        for (auto &g : groups)
+          if (g.first == d) {
+            g.second ^= 1u << a;  // a pair listed twice cancels (CZ^2 = I)
+            found = true;
+          }
+        if (!found) groups.push_back({d, 1u << a});
+      }
+      std::vector<int32_t> rec;
+      rec.push_back((int32_t)groups.size());
+      for (auto &g : groups) {
+        rec.push_back(g.first);
+        rec.push_back((int32_t)g.second);
+      }
+      uint32_t cbits = 0;
+      for (int j = 0; j < kRegs; ++j) {
+        uint32_t Cj = 0;
+        int q = 0;
+        for (auto &pr : czrun) {
+          int a = pr.first, b = pr.second;
+          if ((W[j] >> b) & 1u) Cj ^= 1u << a;
+          if ((W[j] >> a) & 1u) Cj ^= 1u << b;
+          q ^= (int)(((W[j] >> a) & (W[j] >> b)) & 1u);
+        }
+        rec.push_back((int32_t)Cj);
+        if (q) cbits |= 1u << j;
+      }
+      rec.push_back((int32_t)cbits);
+      enc.push_back({OP_DIAG, (int32_t)diag_recs.size(), 0, 0});
+      diag_recs.push_back(rec);
+      czrun.clear();
+    };
+    std::vector<int> regbit_of(kt, -1);
+    for (int r = 0; r < kRegBits; ++r) regbit_of[rp[r]] = r;
+    std::vector<int> loc(c.n, -1);
+    for (int k = 0; k < kt; ++k) loc[sw.tile[k]] = k;
+    for (int oi : ops) {
+      const FOp &o = p.ops[oi];
+      if (o.kind == FK_CZ) {
+        czrun.push_back({o.q0, o.q1});
+        continue;
+      }
+      flush_cz();
+      if (o.kind == FK_BLOCK) {
+        int r = regbit_of[loc[o.q0]];
+        enc.push_back({OP_U1, r, o.block, o.gslot >= 0 ? local_gs[o.gslot] : -1});
+      } else {
+        int r = regbit_of[loc[o.q1]];
+        int lc = loc[o.q0];
+        if (lc >= 0 && regbit_of[lc] >= 0)
+          enc.push_back({OP_CNOT, r, 0, regbit_of[lc]});
+        else
+          enc.push_back({OP_CNOT, r, 1, o.q0});
+      }
+    }
+    flush_cz();
+    sh(0) = (int32_t)enc.size();
+    int ops_off = (int)code.size();
+    code.resize(ops_off + 4 * enc.size(), 0);
+    for (size_t e = 0; e < enc.size(); ++e)
+      for (int f = 0; f < 4; ++f) code[ops_off + 4 * e + f] = enc[e][f];
+    // diag records after the ops; patch offsets
+    for (size_t e = 0; e < enc.size(); ++e)
+      if (enc[e][0] == OP_DIAG) {
+        int rec_off = (int)code.size();
+        const std::vector<int32_t> &rec = diag_recs[enc[e][1]];
+        code.insert(code.end(), rec.begin(), rec.end());
+        code[ops_off + 4 * e + 1] = rec_off;
+      }
+  }
+}
+
+Program encode_program(const CircuitDesc &c, const Plan &p) {
+  Program pr;
+  for (const Sweep &sw : p.sweeps)
+    encode_sweep(c, p, sw, false, pr.code, pr.sweep_off_fwd, pr.max_gslots_per_sweep);
+  for (int s = (int)p.sweeps.size() - 1; s >= 0; --s)
+    encode_sweep(c, p, p.sweeps[s], true, pr.code, pr.sweep_off_bwd, pr.max_gslots_per_sweep);
+  return pr;
+}
+
+}  // namespace qtm

@@ -1,0 +1,76 @@
+// Device helpers shared by the HIP kernels of libqtm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qtm {
+
+template <typename R>
+struct Cx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> cadd(Cx<R> a, Cx<R> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+
+// 2x2 complex matrix, row-major: m00, m01, m10, m11.
+template <typename R>
+struct M2 {
+  Cx<R> a, b, c, d;
+};
+
+// out0 = a v0 + b v1 ; out1 = c v0 + d v1
+template <typename R>
+__device__ __forceinline__ void apply_m2(const M2<R> &m, Cx<R> &v0, Cx<R> &v1) {
+  Cx<R> o0, o1;
+  o0.x = m.a.x * v0.x - m.a.y * v0.y + m.b.x * v1.x - m.b.y * v1.y;
+  o0.y = m.a.x * v0.y + m.a.y * v0.x + m.b.x * v1.y + m.b.y * v1.x;
+  o1.x = m.c.x * v0.x - m.c.y * v0.y + m.d.x * v1.x - m.d.y * v1.y;
+  o1.y = m.c.x * v0.y + m.c.y * v0.x + m.d.x * v1.y + m.d.y * v1.x;
+  v0 = o0;
+  v1 = o1;
+}
+
+// Conjugate transpose applied: out0 = conj(a) v0 + conj(c) v1 ; out1 = conj(b) v0 + conj(d) v1
+template <typename R>
+__device__ __forceinline__ void apply_m2_adj(const M2<R> &m, Cx<R> &v0, Cx<R> &v1) {
+  Cx<R> o0, o1;
+  o0.x = m.a.x * v0.x + m.a.y * v0.y + m.c.x * v1.x + m.c.y * v1.y;
+  o0.y = m.a.x * v0.y - m.a.y * v0.x + m.c.x * v1.y - m.c.y * v1.x;
+  o1.x = m.b.x * v0.x + m.b.y * v0.y + m.d.x * v1.x + m.d.y * v1.y;
+  o1.y = m.b.x * v0.y - m.b.y * v0.x + m.d.x * v1.y - m.d.y * v1.x;
+  v0 = o0;
+  v1 = o1;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the first W lanes of a wave (W = power of two <= 64); every lane
+// of those W must be active.
+template <int W, typename T>
+__device__ __forceinline__ T wave_sum_w(T v) {
+#pragma unroll
+  for (int o = W / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+__device__ __forceinline__ int parity_u64(uint64_t v) { return __popcll(v) & 1; }
+__device__ __forceinline__ int parity_u32(uint32_t v) { return __popc(v) & 1; }
+
+}  // namespace qtm

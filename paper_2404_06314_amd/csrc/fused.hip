@@ -1,0 +1,714 @@
+// Fused path: LDS-tiled, register-staged sweeps.
+//
+// A sweep loads a tile of 2^KT amplitudes of one sample (the `klo` lowest
+// qubits contiguous, plus KT - klo others chosen by the planner), runs a
+// chain of stages on it and writes it back.  In a stage every thread holds
+// 16 amplitudes in registers: the ones that differ in the stage's 4 register
+// bits.  Single-qubit blocks (the fused RZ RY RX of one wire and layer) and
+// CNOT targets act on register bits; CZ gates act as a sign computed from
+// the global index.  Between stages the tile is exchanged through LDS (an
+// XOR-swizzled layout that keeps the per-stage index arithmetic separable).
+//
+// Forward: the last sweep also reads every Pauli-Z string expectation value
+// (Sec. II-A: all observables from one evolved state) and the norm.
+// Backward: the reverse sweeps carry the ket psi and the combined bra
+// lambda = (sum_m G_m O_m) psi together; before un-applying a parameterised
+// block on wire q they accumulate the three numbers Im Tr(P T) (P = X, Y, Z)
+// of the 2x2 transition matrix T[a][b] = sum_r psi(b, r) conj(lambda(a, r));
+// the derivative of every rotation inside the block follows from them and
+// the block's later rotations (see k_fused_prep).
+#include <mutex>
+
+#include "kernels.h"
+
+namespace qtm {
+
+constexpr int kMaxWgPerSample = 512;
+
+int fused_wg_per_sample(int n, int kt) {
+  int64_t tiles = (int64_t)1 << (n - kt);
+  return (int)(tiles < kMaxWgPerSample ? tiles : kMaxWgPerSample);
+}
+
+size_t fused_part_obs_doubles(const DevCircuit &d, const DevPlan &p, int B) {
+  return (size_t)B * fused_wg_per_sample(d.n, p.kt) * (d.n_obs + 1);
+}
+size_t fused_part_grad_doubles(const DevCircuit &d, const DevPlan &p, int B) {
+  return (size_t)B * (size_t)(p.n_gslots > 0 ? p.n_gslots : 1) * fused_wg_per_sample(d.n, p.kt) * 3;
+}
+
+// ---------------------------------------------------------------------------
+// matrix prep: U = G_last ... G_first per (sample, block), FP64, stored in R;
+// for each rotation j of the block, P'_j = A_j P_j A_j^dag with A_j the
+// block's rotations after j, stored as (px, py, pz): P'_j = px X + py Y + pz Z.
+
+struct CD {
+  double x, y;
+};
+__device__ __forceinline__ CD cd_mul(CD a, CD b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ CD cd_add(CD a, CD b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ CD cd_conj(CD a) { return {a.x, -a.y}; }
+struct MD {
+  CD m[2][2];
+};
+__device__ __forceinline__ MD md_mul(const MD &a, const MD &b) {
+  MD r;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) r.m[i][j] = cd_add(cd_mul(a.m[i][0], b.m[0][j]), cd_mul(a.m[i][1], b.m[1][j]));
+  return r;
+}
+__device__ __forceinline__ MD md_adj(const MD &a) {
+  MD r;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) r.m[i][j] = cd_conj(a.m[j][i]);
+  return r;
+}
+__device__ __forceinline__ MD md_rot(int type, double t) {
+  double s, c;
+  sincos(0.5 * t, &s, &c);
+  MD r;
+  if (type == 0) {
+    r.m[0][0] = {c, 0}; r.m[0][1] = {0, -s}; r.m[1][0] = {0, -s}; r.m[1][1] = {c, 0};
+  } else if (type == 1) {
+    r.m[0][0] = {c, 0}; r.m[0][1] = {-s, 0}; r.m[1][0] = {s, 0}; r.m[1][1] = {c, 0};
+  } else {
+    r.m[0][0] = {c, -s}; r.m[0][1] = {0, 0}; r.m[1][0] = {0, 0}; r.m[1][1] = {c, s};
+  }
+  return r;
+}
+__device__ __forceinline__ MD md_pauli(int type) {
+  MD r;
+  r.m[0][0] = r.m[0][1] = r.m[1][0] = r.m[1][1] = {0, 0};
+  if (type == 0) { r.m[0][1] = {1, 0}; r.m[1][0] = {1, 0}; }
+  else if (type == 1) { r.m[0][1] = {0, -1}; r.m[1][0] = {0, 1}; }
+  else { r.m[0][0] = {1, 0}; r.m[1][1] = {-1, 0}; }
+  return r;
+}
+
+// blk record: [q, ng, (type, src, idx, occ) x ng]
+template <typename R>
+__global__ void k_fused_prep(int B, int n_blocks, const int32_t *__restrict__ blk,
+                             const int32_t *__restrict__ blk_off, const double *__restrict__ x,
+                             int n_in, const double *__restrict__ w, M2<R> *__restrict__ mats,
+                             double *__restrict__ coef, int n_occ) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * n_blocks) return;
+  const int b = (int)(i / n_blocks), k = (int)(i % n_blocks);
+  const int32_t *r = blk + blk_off[k];
+  const int ng = r[1];
+  auto ang = [&](int g) {
+    const int32_t *e = r + 2 + 4 * g;
+    return e[1] == 1 ? x[(int64_t)b * n_in + e[2]] : w[e[2]];
+  };
+  MD U;
+  U.m[0][0] = {1, 0}; U.m[0][1] = {0, 0}; U.m[1][0] = {0, 0}; U.m[1][1] = {1, 0};
+  for (int g = 0; g < ng; ++g) U = md_mul(md_rot(r[2 + 4 * g], ang(g)), U);
+  M2<R> o;
+  o.a = {(R)U.m[0][0].x, (R)U.m[0][0].y};
+  o.b = {(R)U.m[0][1].x, (R)U.m[0][1].y};
+  o.c = {(R)U.m[1][0].x, (R)U.m[1][0].y};
+  o.d = {(R)U.m[1][1].x, (R)U.m[1][1].y};
+  mats[i] = o;
+  if (!coef) return;
+  MD A;
+  A.m[0][0] = {1, 0}; A.m[0][1] = {0, 0}; A.m[1][0] = {0, 0}; A.m[1][1] = {1, 0};
+  for (int g = ng - 1; g >= 0; --g) {
+    const int32_t *e = r + 2 + 4 * g;
+    MD P = md_mul(md_mul(A, md_pauli(e[0])), md_adj(A));
+    double *cf = coef + ((int64_t)b * n_occ + e[3]) * 3;
+    cf[0] = P.m[1][0].x;
+    cf[1] = P.m[1][0].y;
+    cf[2] = P.m[0][0].x;
+    A = md_mul(A, md_rot(e[0], ang(g)));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// register-level ops
+
+template <typename R, int P>
+__device__ __forceinline__ void u1_bit(Cx<R> (&v)[kRegs], const M2<R> &m) {
+#pragma unroll
+  for (int j = 0; j < kRegs; ++j)
+    if (!(j & (1 << P))) apply_m2(m, v[j], v[j | (1 << P)]);
+}
+template <typename R, int P>
+__device__ __forceinline__ void u1_bit_adj(Cx<R> (&v)[kRegs], const M2<R> &m) {
+#pragma unroll
+  for (int j = 0; j < kRegs; ++j)
+    if (!(j & (1 << P))) apply_m2_adj(m, v[j], v[j | (1 << P)]);
+}
+template <typename R>
+__device__ __forceinline__ void u1(Cx<R> (&v)[kRegs], int p, const M2<R> &m) {
+  switch (p) {
+    case 0: u1_bit<R, 0>(v, m); break;
+    case 1: u1_bit<R, 1>(v, m); break;
+    case 2: u1_bit<R, 2>(v, m); break;
+    default: u1_bit<R, 3>(v, m); break;
+  }
+}
+template <typename R>
+__device__ __forceinline__ void u1_adj(Cx<R> (&v)[kRegs], int p, const M2<R> &m) {
+  switch (p) {
+    case 0: u1_bit_adj<R, 0>(v, m); break;
+    case 1: u1_bit_adj<R, 1>(v, m); break;
+    case 2: u1_bit_adj<R, 2>(v, m); break;
+    default: u1_bit_adj<R, 3>(v, m); break;
+  }
+}
+
+// CNOT with target register bit P and control register bit C
+template <typename R, int P, int C>
+__device__ __forceinline__ void cnot_rr(Cx<R> (&v)[kRegs]) {
+#pragma unroll
+  for (int j = 0; j < kRegs; ++j)
+    if (!(j & (1 << P)) && (j & (1 << C))) {
+      Cx<R> t = v[j];
+      v[j] = v[j | (1 << P)];
+      v[j | (1 << P)] = t;
+    }
+}
+template <typename R, int P>
+__device__ __forceinline__ void cnot_r(Cx<R> (&v)[kRegs], int c) {
+  switch (c) {
+    case 0: if (P != 0) cnot_rr<R, P, 0>(v); break;
+    case 1: if (P != 1) cnot_rr<R, P, 1>(v); break;
+    case 2: if (P != 2) cnot_rr<R, P, 2>(v); break;
+    default: if (P != 3) cnot_rr<R, P, 3>(v); break;
+  }
+}
+// CNOT with target register bit P, control fixed for the thread (on / off)
+template <typename R, int P>
+__device__ __forceinline__ void cnot_t(Cx<R> (&v)[kRegs], bool on) {
+#pragma unroll
+  for (int j = 0; j < kRegs; ++j)
+    if (!(j & (1 << P))) {
+      Cx<R> a = v[j], b = v[j | (1 << P)];
+      v[j] = on ? b : a;
+      v[j | (1 << P)] = on ? a : b;
+    }
+}
+template <typename R>
+__device__ __forceinline__ void cnot_op(Cx<R> (&v)[kRegs], int p, int kind, int c, uint32_t gt) {
+  if (kind == 0) {
+    switch (p) {
+      case 0: cnot_r<R, 0>(v, c); break;
+      case 1: cnot_r<R, 1>(v, c); break;
+      case 2: cnot_r<R, 2>(v, c); break;
+      default: cnot_r<R, 3>(v, c); break;
+    }
+  } else {
+    const bool on = (gt >> c) & 1u;
+    switch (p) {
+      case 0: cnot_t<R, 0>(v, on); break;
+      case 1: cnot_t<R, 1>(v, on); break;
+      case 2: cnot_t<R, 2>(v, on); break;
+      default: cnot_t<R, 3>(v, on); break;
+    }
+  }
+}
+
+// Diagonal op: sign(x) for x = gt | W_j from the diag record.
+__device__ __forceinline__ uint32_t diag_signs(const int32_t *__restrict__ rec, uint32_t gt) {
+  const int ng = rec[0];
+  uint32_t q = 0;
+  for (int g = 0; g < ng; ++g) q += __popc(gt & (gt >> rec[1 + 2 * g]) & (uint32_t)rec[2 + 2 * g]);
+  const int32_t *C = rec + 1 + 2 * ng;
+  uint32_t cb = (uint32_t)C[kRegs];
+  uint32_t bits = 0;
+#pragma unroll
+  for (int j = 0; j < kRegs; ++j) bits |= ((__popc(gt & (uint32_t)C[j]) + q + (cb >> j)) & 1u) << j;
+  return bits;
+}
+template <typename R>
+__device__ __forceinline__ void apply_signs(Cx<R> (&v)[kRegs], uint32_t bits) {
+#pragma unroll
+  for (int j = 0; j < kRegs; ++j)
+    if ((bits >> j) & 1u) v[j] = Cx<R>{-v[j].x, -v[j].y};
+}
+
+// Transition-matrix components for register bit P over the thread's pairs:
+// tx = Im Tr(X T), ty = Im Tr(Y T), tz = Im Tr(Z T), T[a][b] = sum psi_b conj(lam_a).
+template <typename R, int P>
+__device__ __forceinline__ void tcomp_bit(const Cx<R> (&v)[kRegs], const Cx<R> (&l)[kRegs],
+                                          R &tx, R &ty, R &tz) {
+#pragma unroll
+  for (int j = 0; j < kRegs; ++j)
+    if (!(j & (1 << P))) {
+      const Cx<R> p0 = v[j], p1 = v[j | (1 << P)], l0 = l[j], l1 = l[j | (1 << P)];
+      tx += p0.y * l1.x - p0.x * l1.y + p1.y * l0.x - p1.x * l0.y;
+      ty += p0.x * l1.x + p0.y * l1.y - p1.x * l0.x - p1.y * l0.y;
+      tz += p0.y * l0.x - p0.x * l0.y - p1.y * l1.x + p1.x * l1.y;
+    }
+}
+template <typename R>
+__device__ __forceinline__ void tcomp(const Cx<R> (&v)[kRegs], const Cx<R> (&l)[kRegs], int p,
+                                      R &tx, R &ty, R &tz) {
+  switch (p) {
+    case 0: tcomp_bit<R, 0>(v, l, tx, ty, tz); break;
+    case 1: tcomp_bit<R, 1>(v, l, tx, ty, tz); break;
+    case 2: tcomp_bit<R, 2>(v, l, tx, ty, tz); break;
+    default: tcomp_bit<R, 3>(v, l, tx, ty, tz); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward sweep
+
+struct FwdArgs {
+  const int32_t *prog;
+  int sweep_off;
+  int n;
+  void *state;
+  const void *mats;
+  int n_blocks;
+  int ntiles;
+  int first, last, store;
+  const uint64_t *masks;
+  int M;
+  const float *obs_sgn;  // [(M+1)][16]
+  double *part_obs;      // [B][gridDim.x][M+1]
+};
+
+template <typename R, int KT>
+__global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_fwd(FwdArgs a) {
+  constexpr int NT = 1 << (KT - kRegBits);
+  constexpr int NW = (NT + 63) / 64;
+  constexpr int WS = NT < 64 ? NT : 64;  // lanes per wave in use
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<R> *lds = reinterpret_cast<Cx<R> *>(smem);
+  double *obs_acc = reinterpret_cast<double *>(smem + (sizeof(Cx<R>) << KT));
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int b = blockIdx.y;
+  const int32_t *__restrict__ H = a.prog + a.sweep_off;
+  const int nst = H[0], nout = H[1];
+  Cx<R> *__restrict__ st = reinterpret_cast<Cx<R> *>(a.state) + ((int64_t)b << a.n);
+  const M2<R> *__restrict__ mats = reinterpret_cast<const M2<R> *>(a.mats) + (int64_t)b * a.n_blocks;
+  uint32_t gload = 0;
+#pragma unroll
+  for (int i = 0; i < KT - kRegBits; ++i)
+    if ((t >> i) & 1) gload |= 1u << H[kSwLoadTb + i];
+  const uint32_t lload = lds_swizzle((uint32_t)t);
+  if (a.last)
+    for (int i = t; i < (a.M + 1) * NW; i += NT) obs_acc[i] = 0.0;
+  Cx<R> v[kRegs];
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    uint32_t tbase = 0;
+    for (int i = 0; i < nout; ++i)
+      if ((tile >> i) & 1) tbase |= 1u << H[kSwOuter + i];
+    if (a.first) {
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j)
+        v[j] = Cx<R>{((tbase | gload | (uint32_t)H[kSwLoadG + j]) == 0u) ? (R)1 : (R)0, (R)0};
+    } else {
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) v[j] = st[tbase | gload | (uint32_t)H[kSwLoadG + j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) lds[lload ^ (uint32_t)H[kSwLoadL + j]] = v[j];
+    for (int s = 0; s < nst; ++s) {
+      const int32_t *__restrict__ S = a.prog + H[kSwStages + s];
+      __syncthreads();
+      uint32_t lt = 0, gt = tbase;
+#pragma unroll
+      for (int i = 0; i < KT - kRegBits; ++i)
+        if ((t >> i) & 1) {
+          lt |= 1u << S[kStTbLocal + i];
+          gt |= 1u << S[kStTbGlob + i];
+        }
+      const uint32_t lsw = lds_swizzle(lt);
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) v[j] = lds[lsw ^ (uint32_t)S[kStLds + j]];
+      const int nops = S[0];
+      for (int o = 0; o < nops; ++o) {
+        const int32_t *op = S + kStOps + 4 * o;
+        const int code = op[0];
+        if (code == OP_U1) {
+          u1<R>(v, op[1], mats[op[2]]);
+        } else if (code == OP_CNOT) {
+          cnot_op<R>(v, op[1], op[2], op[3], gt);
+        } else {
+          apply_signs<R>(v, diag_signs(a.prog + op[1], gt));
+        }
+      }
+      if (a.last && s == nst - 1) {
+        float p[kRegs];
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) p[j] = (float)v[j].x * (float)v[j].x + (float)v[j].y * (float)v[j].y;
+        for (int m = 0; m <= a.M; ++m) {
+          const float *sg = a.obs_sgn + m * kRegs;
+          float acc = 0.f;
+#pragma unroll
+          for (int j = 0; j < kRegs; ++j) acc += sg[j] * p[j];
+          const uint32_t mask = m < a.M ? (uint32_t)a.masks[m] : 0u;
+          double d = (__popc(gt & mask) & 1) ? -(double)acc : (double)acc;
+          d = wave_sum_w<WS>(d);
+          if (lane == 0) obs_acc[m * NW + wave] += d;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) lds[lsw ^ (uint32_t)S[kStLds + j]] = v[j];
+    }
+    __syncthreads();
+    if (a.store) {
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) v[j] = lds[lload ^ (uint32_t)H[kSwLoadL + j]];
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) st[tbase | gload | (uint32_t)H[kSwLoadG + j]] = v[j];
+    }
+    __syncthreads();
+  }
+  if (a.last) {
+    __syncthreads();
+    for (int m = t; m <= a.M; m += NT) {
+      double acc = 0.0;
+      for (int wv = 0; wv < NW; ++wv) acc += obs_acc[m * NW + wv];
+      a.part_obs[((int64_t)b * gridDim.x + blockIdx.x) * (a.M + 1) + m] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward sweep
+
+struct BwdArgs {
+  const int32_t *prog;
+  int sweep_off;
+  int n;
+  void *psi;
+  void *lam;
+  const void *mats;
+  int n_blocks;
+  int ntiles;
+  int first, store;
+  const uint64_t *masks;
+  int M;
+  const double *G;         // [B][M]
+  const double *seed_sgn;  // [M][16]
+  double *part_grad;       // [B][n_gslots][gridDim.x][3]
+  int n_gslots;
+  double *part_norm;       // [B][gridDim.x]
+};
+
+template <typename R, int KT>
+__global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_bwd(BwdArgs a) {
+  constexpr int NT = 1 << (KT - kRegBits);
+  constexpr int NW = (NT + 63) / 64;
+  constexpr int WS = NT < 64 ? NT : 64;  // lanes per wave in use
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<R> *lds_p = reinterpret_cast<Cx<R> *>(smem);
+  Cx<R> *lds_l = lds_p + (1 << KT);
+  double *gacc = reinterpret_cast<double *>(smem + (2 * sizeof(Cx<R>) << KT));
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int b = blockIdx.y;
+  const int32_t *__restrict__ H = a.prog + a.sweep_off;
+  const int nst = H[0], nout = H[1], ngs = H[2];
+  Cx<R> *__restrict__ ps = reinterpret_cast<Cx<R> *>(a.psi) + ((int64_t)b << a.n);
+  Cx<R> *__restrict__ ls = reinterpret_cast<Cx<R> *>(a.lam) + ((int64_t)b << a.n);
+  const M2<R> *__restrict__ mats = reinterpret_cast<const M2<R> *>(a.mats) + (int64_t)b * a.n_blocks;
+  uint32_t gload = 0;
+#pragma unroll
+  for (int i = 0; i < KT - kRegBits; ++i)
+    if ((t >> i) & 1) gload |= 1u << H[kSwLoadTb + i];
+  const uint32_t lload = lds_swizzle((uint32_t)t);
+  for (int i = t; i < ngs * 3 * NW + NW; i += NT) gacc[i] = 0.0;
+  double *nacc = gacc + ngs * 3 * NW;
+  Cx<R> v[kRegs], l[kRegs];
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    uint32_t tbase = 0;
+    for (int i = 0; i < nout; ++i)
+      if ((tile >> i) & 1) tbase |= 1u << H[kSwOuter + i];
+    const uint32_t g0 = tbase | gload;
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) v[j] = ps[g0 | (uint32_t)H[kSwLoadG + j]];
+    if (a.first) {
+      // lambda = D psi, D(x) = sum_m G_m (-1)^popcount(x & S_m), x = g0 | W_j (disjoint bits)
+      double dj[kRegs];
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) dj[j] = 0.0;
+      for (int m = 0; m < a.M; ++m) {
+        double gm = a.G[(int64_t)b * a.M + m];
+        if (__popc(g0 & (uint32_t)a.masks[m]) & 1) gm = -gm;
+        const double *sg = a.seed_sgn + m * kRegs;
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) dj[j] += sg[j] * gm;
+      }
+      float nrm = 0.f;
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) {
+        l[j] = Cx<R>{(R)(dj[j] * (double)v[j].x), (R)(dj[j] * (double)v[j].y)};
+        nrm += (float)v[j].x * (float)v[j].x + (float)v[j].y * (float)v[j].y;
+      }
+      double dn = wave_sum_w<WS>((double)nrm);
+      if (lane == 0) nacc[wave] += dn;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) l[j] = ls[g0 | (uint32_t)H[kSwLoadG + j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {
+      lds_p[lload ^ (uint32_t)H[kSwLoadL + j]] = v[j];
+      lds_l[lload ^ (uint32_t)H[kSwLoadL + j]] = l[j];
+    }
+    for (int s = 0; s < nst; ++s) {
+      const int32_t *__restrict__ S = a.prog + H[kSwStages + s];
+      __syncthreads();
+      uint32_t lt = 0, gt = tbase;
+#pragma unroll
+      for (int i = 0; i < KT - kRegBits; ++i)
+        if ((t >> i) & 1) {
+          lt |= 1u << S[kStTbLocal + i];
+          gt |= 1u << S[kStTbGlob + i];
+        }
+      const uint32_t lsw = lds_swizzle(lt);
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) {
+        v[j] = lds_p[lsw ^ (uint32_t)S[kStLds + j]];
+        l[j] = lds_l[lsw ^ (uint32_t)S[kStLds + j]];
+      }
+      const int nops = S[0];
+      for (int o = 0; o < nops; ++o) {
+        const int32_t *op = S + kStOps + 4 * o;
+        const int code = op[0];
+        if (code == OP_U1) {
+          const M2<R> m = mats[op[2]];
+          if (op[3] >= 0) {
+            R tx = 0, ty = 0, tz = 0;
+            tcomp<R>(v, l, op[1], tx, ty, tz);
+            float fx = wave_sum_w<WS>((float)tx), fy = wave_sum_w<WS>((float)ty), fz = wave_sum_w<WS>((float)tz);
+            if (lane == 0) {
+              double *g = gacc + op[3] * 3 * NW;
+              g[wave] += (double)fx;
+              g[NW + wave] += (double)fy;
+              g[2 * NW + wave] += (double)fz;
+            }
+          }
+          u1_adj<R>(v, op[1], m);
+          u1_adj<R>(l, op[1], m);
+        } else if (code == OP_CNOT) {
+          cnot_op<R>(v, op[1], op[2], op[3], gt);
+          cnot_op<R>(l, op[1], op[2], op[3], gt);
+        } else {
+          const uint32_t bits = diag_signs(a.prog + op[1], gt);
+          apply_signs<R>(v, bits);
+          apply_signs<R>(l, bits);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) {
+        lds_p[lsw ^ (uint32_t)S[kStLds + j]] = v[j];
+        lds_l[lsw ^ (uint32_t)S[kStLds + j]] = l[j];
+      }
+    }
+    __syncthreads();
+    if (a.store) {
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) {
+        v[j] = lds_p[lload ^ (uint32_t)H[kSwLoadL + j]];
+        l[j] = lds_l[lload ^ (uint32_t)H[kSwLoadL + j]];
+      }
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) {
+        ps[g0 | (uint32_t)H[kSwLoadG + j]] = v[j];
+        ls[g0 | (uint32_t)H[kSwLoadG + j]] = l[j];
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const int32_t *gsl = H + kSwStages + nst;
+  for (int i = t; i < ngs * 3; i += NT) {
+    const int ls_ = i / 3, c = i % 3;
+    double acc = 0.0;
+    for (int wv = 0; wv < NW; ++wv) acc += gacc[(ls_ * 3 + c) * NW + wv];
+    a.part_grad[(((int64_t)b * a.n_gslots + gsl[ls_]) * gridDim.x + blockIdx.x) * 3 + c] = acc;
+  }
+  if (a.first && t == 0) {
+    double acc = 0.0;
+    for (int wv = 0; wv < NW; ++wv) acc += nacc[wv];
+    a.part_norm[(int64_t)b * gridDim.x + blockIdx.x] = acc;
+  }
+}
+
+// g[b][k] = (px TX + py TY + pz TZ) / norm for occurrence k of slot gs(k)
+__global__ void k_fused_grad_occ(const double *__restrict__ part, const double *__restrict__ pnorm,
+                                 const double *__restrict__ coef, const int32_t *__restrict__ occ_gslot,
+                                 int B, int n_occ, int n_gslots, int nwg, double *__restrict__ gocc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * n_occ) return;
+  const int b = (int)(i / n_occ), k = (int)(i % n_occ);
+  const int gs = occ_gslot[k];
+  double T[3] = {0, 0, 0}, nrm = 0;
+  for (int wg = 0; wg < nwg; ++wg) {
+    const double *p = part + (((int64_t)b * n_gslots + gs) * nwg + wg) * 3;
+    T[0] += p[0];
+    T[1] += p[1];
+    T[2] += p[2];
+    nrm += pnorm[(int64_t)b * nwg + wg];
+  }
+  const double *cf = coef + i * 3;
+  gocc[i] = (cf[0] * T[0] + cf[1] * T[1] + cf[2] * T[2]) / nrm;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+template <typename R, int KT>
+static size_t fwd_lds(int M) {
+  constexpr int NW = ((1 << (KT - kRegBits)) + 63) / 64;
+  return (sizeof(Cx<R>) << KT) + sizeof(double) * (size_t)(M + 1) * NW;
+}
+template <typename R, int KT>
+static size_t bwd_lds(int ngs) {
+  constexpr int NW = ((1 << (KT - kRegBits)) + 63) / 64;
+  return (2 * sizeof(Cx<R>) << KT) + sizeof(double) * ((size_t)ngs * 3 * NW + NW);
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename R, int KT>
+static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *mats, void *state,
+                          double *part_obs, bool store_final, hipStream_t s, SweepTimer *tm) {
+  const int nwg = fused_wg_per_sample(d.n, KT);
+  const size_t lds = fwd_lds<R, KT>(d.n_obs);
+  hipError_t e = allow_lds(k_fused_fwd<R, KT>, lds);
+  if (e != hipSuccess) return e;
+  for (int sw = 0; sw < p.n_sweeps; ++sw) {
+    FwdArgs a;
+    a.prog = p.code;
+    a.sweep_off = p.sweep_off_fwd[sw];
+    a.n = d.n;
+    a.state = state;
+    a.mats = mats;
+    a.n_blocks = p.n_blocks;
+    a.ntiles = 1 << (d.n - KT);
+    a.first = sw == 0;
+    a.last = sw == p.n_sweeps - 1;
+    a.store = !a.last || store_final;
+    a.masks = d.masks;
+    a.M = d.n_obs;
+    a.obs_sgn = p.obs_sgn_f;
+    a.part_obs = part_obs;
+    if (tm) tm->before(0, s);
+    hipLaunchKernelGGL((k_fused_fwd<R, KT>), dim3(nwg, B), dim3(1 << (KT - kRegBits)), lds, s, a);
+    if (tm) tm->after(0, s);
+  }
+  return hipGetLastError();
+}
+
+template <typename R, int KT>
+static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const double *G, void *mats,
+                          void *psi, void *lam, double *part_grad, double *part_norm, hipStream_t s,
+                          SweepTimer *tm) {
+  const int nwg = fused_wg_per_sample(d.n, KT);
+  const size_t lds = bwd_lds<R, KT>(p.max_gslots);
+  hipError_t e = allow_lds(k_fused_bwd<R, KT>, lds);
+  if (e != hipSuccess) return e;
+  for (int sw = 0; sw < p.n_sweeps; ++sw) {
+    BwdArgs a;
+    a.prog = p.code;
+    a.sweep_off = p.sweep_off_bwd[sw];
+    a.n = d.n;
+    a.psi = psi;
+    a.lam = lam;
+    a.mats = mats;
+    a.n_blocks = p.n_blocks;
+    a.ntiles = 1 << (d.n - KT);
+    a.first = sw == 0;
+    a.store = sw != p.n_sweeps - 1;
+    a.masks = d.masks;
+    a.M = d.n_obs;
+    a.G = G;
+    a.seed_sgn = p.seed_sgn;
+    a.part_grad = part_grad;
+    a.n_gslots = p.n_gslots > 0 ? p.n_gslots : 1;
+    a.part_norm = part_norm;
+    if (tm) tm->before(1, s);
+    hipLaunchKernelGGL((k_fused_bwd<R, KT>), dim3(nwg, B), dim3(1 << (KT - kRegBits)), lds, s, a);
+    if (tm) tm->after(1, s);
+  }
+  return hipGetLastError();
+}
+
+static inline unsigned nblocks256(int64_t w) { return (unsigned)((w + 255) / 256); }
+
+template <typename R>
+static hipError_t prep(const DevCircuit &d, const DevPlan &p, int B, const double *x,
+                       const double *w, void *mats, double *coef, hipStream_t s) {
+  if (p.n_blocks == 0) return hipSuccess;
+  k_fused_prep<R><<<nblocks256((int64_t)B * p.n_blocks), 256, 0, s>>>(
+      B, p.n_blocks, p.blk, p.blk_off, x, d.n_inputs, w, reinterpret_cast<M2<R> *>(mats), coef,
+      d.n_occ);
+  return hipGetLastError();
+}
+
+#define QTM_KT_DISPATCH(KTV, CALL) \
+  switch (KTV) {                   \
+    case 4: CALL(4); break;        \
+    case 5: CALL(5); break;        \
+    case 6: CALL(6); break;        \
+    case 7: CALL(7); break;        \
+    case 8: CALL(8); break;        \
+    case 9: CALL(9); break;        \
+    case 10: CALL(10); break;      \
+    case 11: CALL(11); break;      \
+    case 12: CALL(12); break;      \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <typename R>
+hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
+                         const double *w, void *mats, void *state, double *part_obs, double *out,
+                         bool store_final, hipStream_t s, SweepTimer *tm) {
+  hipError_t e = prep<R>(d, p, B, x, w, mats, nullptr, s);
+  if (e != hipSuccess) return e;
+#define FWD_CALL(K) e = run_fwd<R, K>(d, p, B, mats, state, part_obs, store_final, s, tm)
+  QTM_KT_DISPATCH(p.kt, FWD_CALL)
+#undef FWD_CALL
+  if (e != hipSuccess) return e;
+  return launch_obs_final(part_obs, B, fused_wg_per_sample(d.n, p.kt), d.n_obs, out, true, s);
+}
+
+template <typename R>
+hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
+                          const double *w, const double *G, void *mats, double *coef, void *state,
+                          void *lam, double *part_grad, double *part_norm, double *gocc, double *gw,
+                          double *gx, hipStream_t s, SweepTimer *tm) {
+  hipError_t e = prep<R>(d, p, B, x, w, mats, coef, s);
+  if (e != hipSuccess) return e;
+#define BWD_CALL(K) e = run_bwd<R, K>(d, p, B, G, mats, state, lam, part_grad, part_norm, s, tm)
+  QTM_KT_DISPATCH(p.kt, BWD_CALL)
+#undef BWD_CALL
+  if (e != hipSuccess) return e;
+  if (d.n_occ > 0) {
+    const int nwg = fused_wg_per_sample(d.n, p.kt);
+    k_fused_grad_occ<<<nblocks256((int64_t)B * d.n_occ), 256, 0, s>>>(
+        part_grad, part_norm, coef, p.occ_gslot, B, d.n_occ, p.n_gslots > 0 ? p.n_gslots : 1, nwg,
+        gocc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return launch_scatter(d, B, gocc, gw, gx, s);
+}
+
+template hipError_t fused_forward<float>(const DevCircuit &, const DevPlan &, int, const double *,
+                                         const double *, void *, void *, double *, double *, bool,
+                                         hipStream_t, SweepTimer *);
+template hipError_t fused_forward<double>(const DevCircuit &, const DevPlan &, int, const double *,
+                                          const double *, void *, void *, double *, double *, bool,
+                                          hipStream_t, SweepTimer *);
+template hipError_t fused_backward<float>(const DevCircuit &, const DevPlan &, int, const double *,
+                                          const double *, const double *, void *, double *, void *,
+                                          void *, double *, double *, double *, double *, double *,
+                                          hipStream_t, SweepTimer *);
+template hipError_t fused_backward<double>(const DevCircuit &, const DevPlan &, int, const double *,
+                                           const double *, const double *, void *, double *, void *,
+                                           void *, double *, double *, double *, double *, double *,
+                                           hipStream_t, SweepTimer *);
+
+}  // namespace qtm

@@ -1,0 +1,78 @@
+// Launch interface between the C-ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "circuit.h"
+#include "device_common.h"
+
+namespace qtm {
+
+// Device copies of a circuit's static data (owned by the circuit handle).
+struct DevCircuit {
+  int n = 0, n_inputs = 0, n_weights = 0, n_obs = 0, n_occ = 0;
+  uint64_t *masks = nullptr;
+  int32_t *occ_src = nullptr, *occ_idx = nullptr;
+  int32_t *w_ptr = nullptr, *w_list = nullptr, *x_ptr = nullptr, *x_list = nullptr;
+};
+
+struct HostCircuitInfo {
+  std::vector<Gate> gates;
+  std::vector<int32_t> gate_occ;
+};
+
+// Device copy of a fused plan for one (kt, klo).
+struct DevPlan {
+  int kt = 0, klo = 0, n_blocks = 0, n_gslots = 0, max_gslots = 0;
+  int n_sweeps = 0;
+  std::vector<int32_t> sweep_off_fwd, sweep_off_bwd;
+  int32_t *code = nullptr;      // program
+  int32_t *blk = nullptr;       // block records for the matrix prep
+  int32_t *blk_off = nullptr;   // block -> offset in blk
+  int32_t *occ_gslot = nullptr; // occurrence -> gradient slot
+  float *obs_sgn_f = nullptr;   // [(M+1)][16] signs of the last forward stage (float)
+  double *seed_sgn = nullptr;   // [M][16] signs of the first backward load layout (double)
+};
+
+// Optional hook around every sweep-kernel launch (kind 0 = forward sweep,
+// 1 = backward sweep); used to time the kernels with events on the stream.
+struct SweepTimer {
+  virtual void before(int kind, hipStream_t s) = 0;
+  virtual void after(int kind, hipStream_t s) = 0;
+  virtual ~SweepTimer() = default;
+};
+
+hipError_t launch_half_angles(const DevCircuit &d, int B, const double *x, const double *w,
+                              double2 *cs, hipStream_t s);
+hipError_t launch_obs_final(const double *part, int B, int nblk, int M, double *out,
+                            bool normalise, hipStream_t s);
+hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, double *gw, double *gx,
+                          hipStream_t s);
+size_t plain_part_doubles(const DevCircuit &d, int B);
+
+template <typename R>
+hipError_t plain_forward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,
+                         void *state, double *part, double *out, bool normalise, hipStream_t s);
+template <typename R>
+hipError_t plain_backward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,
+                          void *state, void *lam, const double *G, double *part, double *gocc,
+                          double *gw, double *gx, hipStream_t s);
+
+// Fused path workspace sizes and entry points.
+int fused_wg_per_sample(int n, int kt);
+size_t fused_part_obs_doubles(const DevCircuit &d, const DevPlan &p, int B);
+size_t fused_part_grad_doubles(const DevCircuit &d, const DevPlan &p, int B);
+
+template <typename R>
+hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
+                         const double *w, void *mats, void *state, double *part_obs, double *out,
+                         bool store_final, hipStream_t s, SweepTimer *tm);
+template <typename R>
+hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
+                          const double *w, const double *G, void *mats, double *coef, void *state,
+                          void *lam, double *part_grad, double *part_norm, double *gocc, double *gw,
+                          double *gx, hipStream_t s, SweepTimer *tm);
+
+}  // namespace qtm

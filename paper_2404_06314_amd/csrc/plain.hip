@@ -1,0 +1,360 @@
+// Plain per-gate path: one launch per gate over all (sample, pair) indices.
+//
+// This is the unfused form of the method (Sec. II-A: evolve once, read all
+// observables; reverse gradient by un-applying gates on the ket and the
+// combined bra).  It runs in complex64 or complex128 and serves as the plain
+// per-sample GPU form shown beside the fused path, and as the path for
+// circuits too small for a register tile.
+#include "kernels.h"
+
+
+namespace qtm {
+
+constexpr int kThreads = 256;
+
+// (cos(t/2), sin(t/2)) in FP64 for every (sample, rotation occurrence).
+__global__ void k_half_angles(int B, int n_occ, const int32_t *__restrict__ occ_src,
+                              const int32_t *__restrict__ occ_idx, const double *__restrict__ x,
+                              int n_in, const double *__restrict__ w, double2 *__restrict__ cs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * n_occ) return;
+  int b = (int)(i / n_occ), k = (int)(i % n_occ);
+  double t = occ_src[k] == 1 ? x[(int64_t)b * n_in + occ_idx[k]] : w[occ_idx[k]];
+  double s, c;
+  sincos(0.5 * t, &s, &c);
+  cs[i] = make_double2(c, s);
+}
+
+template <typename R>
+__device__ __forceinline__ M2<R> rot_m2(int type, double2 csd, bool adjoint) {
+  R c = (R)csd.x, s = (R)(adjoint ? -csd.y : csd.y);
+  M2<R> m;
+  if (type == 0) {  // RX
+    m.a = {c, 0};
+    m.b = {0, -s};
+    m.c = {0, -s};
+    m.d = {c, 0};
+  } else if (type == 1) {  // RY
+    m.a = {c, 0};
+    m.b = {-s, 0};
+    m.c = {s, 0};
+    m.d = {c, 0};
+  } else {  // RZ
+    m.a = {c, -s};
+    m.b = {0, 0};
+    m.c = {0, 0};
+    m.d = {c, s};
+  }
+  return m;
+}
+
+template <typename R>
+__global__ void k_plain_init(Cx<R> *__restrict__ st, int64_t total, int64_t dim) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  st[i] = Cx<R>{(i % dim) == 0 ? (R)1 : (R)0, (R)0};
+}
+
+template <typename R>
+__global__ void k_plain_1q(Cx<R> *__restrict__ a, Cx<R> *__restrict__ a2, int B, int n, int q,
+                           int type, int occ, const double2 *__restrict__ cs, int n_occ,
+                           int adjoint) {
+  const int64_t half = (int64_t)1 << (n - 1);
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * half) return;
+  int b = (int)(i / half);
+  int64_t p = i % half;
+  int64_t lo = p & (((int64_t)1 << q) - 1);
+  int64_t x0 = ((p >> q) << (q + 1)) | lo, x1 = x0 | ((int64_t)1 << q);
+  M2<R> m = rot_m2<R>(type, cs[(int64_t)b * n_occ + occ], adjoint != 0);
+  int64_t base = (int64_t)b << n;
+  Cx<R> v0 = a[base + x0], v1 = a[base + x1];
+  apply_m2(m, v0, v1);
+  a[base + x0] = v0;
+  a[base + x1] = v1;
+  if (a2) {
+    v0 = a2[base + x0];
+    v1 = a2[base + x1];
+    apply_m2(m, v0, v1);
+    a2[base + x0] = v0;
+    a2[base + x1] = v1;
+  }
+}
+
+template <typename R>
+__global__ void k_plain_cnot(Cx<R> *__restrict__ a, Cx<R> *__restrict__ a2, int B, int n, int ctl,
+                             int tgt) {
+  const int64_t half = (int64_t)1 << (n - 1);
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * half) return;
+  int b = (int)(i / half);
+  int64_t p = i % half;
+  int64_t lo = p & (((int64_t)1 << tgt) - 1);
+  int64_t x0 = ((p >> tgt) << (tgt + 1)) | lo, x1 = x0 | ((int64_t)1 << tgt);
+  if (!((x0 >> ctl) & 1)) return;
+  int64_t base = (int64_t)b << n;
+  Cx<R> t = a[base + x0];
+  a[base + x0] = a[base + x1];
+  a[base + x1] = t;
+  if (a2) {
+    t = a2[base + x0];
+    a2[base + x0] = a2[base + x1];
+    a2[base + x1] = t;
+  }
+}
+
+template <typename R>
+__global__ void k_plain_cz(Cx<R> *__restrict__ a, Cx<R> *__restrict__ a2, int B, int n, int q0,
+                           int q1) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t dim = (int64_t)1 << n;
+  if (i >= (int64_t)B * dim) return;
+  int64_t x = i & (dim - 1);
+  if (((x >> q0) & 1) && ((x >> q1) & 1)) {
+    a[i] = Cx<R>{-a[i].x, -a[i].y};
+    if (a2) a2[i] = Cx<R>{-a2[i].x, -a2[i].y};
+  }
+}
+
+// Expectation values: per (sample, block) FP64 partial sums of
+// (-1)^popcount(x & S_m) |psi_x|^2 for m < M, and the norm at m = M.
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+    k_plain_expval(const Cx<R> *__restrict__ st, int n, const uint64_t *__restrict__ masks, int M,
+                   double *__restrict__ part, int nblk) {
+  __shared__ double red[kThreads / 64];
+  const int b = blockIdx.y;
+  const int64_t dim = (int64_t)1 << n;
+  const Cx<R> *s = st + (int64_t)b * dim;
+  for (int m = 0; m <= M; ++m) {
+    const uint64_t mask = m < M ? masks[m] : 0;
+    double acc = 0.0;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < dim;
+         x += (int64_t)nblk * kThreads) {
+      double p = (double)s[x].x * s[x].x + (double)s[x].y * s[x].y;
+      acc += parity_u64((uint64_t)x & mask) ? -p : p;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int wv = 0; wv < kThreads / 64; ++wv) t += red[wv];
+      part[((int64_t)b * nblk + blockIdx.x) * (M + 1) + m] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// out[b][m] = sum over partial blocks, in block order; divided by the norm
+// when `normalise` is set.
+__global__ void k_obs_final(const double *__restrict__ part, int B, int nblk, int M,
+                            double *__restrict__ out, int normalise) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * M) return;
+  int b = i / M, m = i % M;
+  double acc = 0.0, nrm = 0.0;
+  for (int k = 0; k < nblk; ++k) {
+    acc += part[((int64_t)b * nblk + k) * (M + 1) + m];
+    nrm += part[((int64_t)b * nblk + k) * (M + 1) + M];
+  }
+  out[i] = normalise ? acc / nrm : acc;
+}
+
+// lambda = D psi with D(x) = sum_m G[b][m] (-1)^popcount(x & S_m), D in FP64.
+template <typename R>
+__global__ void k_plain_seed(const Cx<R> *__restrict__ psi, Cx<R> *__restrict__ lam, int B, int n,
+                             const uint64_t *__restrict__ masks, int M,
+                             const double *__restrict__ G) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t dim = (int64_t)1 << n;
+  if (i >= (int64_t)B * dim) return;
+  int b = (int)(i >> n);
+  uint64_t x = (uint64_t)(i & (dim - 1));
+  double d = 0.0;
+  for (int m = 0; m < M; ++m) {
+    double g = G[(int64_t)b * M + m];
+    d += parity_u64(x & masks[m]) ? -g : g;
+  }
+  lam[i] = Cx<R>{(R)(d * (double)psi[i].x), (R)(d * (double)psi[i].y)};
+}
+
+// g = Im <lambda| P_q |psi> for P = X, Y, Z (type 0, 1, 2), per-block FP64 partials.
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+    k_plain_grad(const Cx<R> *__restrict__ psi, const Cx<R> *__restrict__ lam, int n, int q,
+                 int type, int occ, int n_occ, double *__restrict__ part, int nblk) {
+  __shared__ double red[kThreads / 64];
+  const int b = blockIdx.y;
+  const int64_t half = (int64_t)1 << (n - 1);
+  const int64_t base = (int64_t)b << n;
+  double acc = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < half;
+       p += (int64_t)nblk * kThreads) {
+    int64_t lo = p & (((int64_t)1 << q) - 1);
+    int64_t x0 = ((p >> q) << (q + 1)) | lo, x1 = x0 | ((int64_t)1 << q);
+    double p0r = psi[base + x0].x, p0i = psi[base + x0].y;
+    double p1r = psi[base + x1].x, p1i = psi[base + x1].y;
+    double l0r = lam[base + x0].x, l0i = lam[base + x0].y;
+    double l1r = lam[base + x1].x, l1i = lam[base + x1].y;
+    // Im(conj(l) * v) = l.r * v.i - l.i * v.r
+    if (type == 0) {  // X psi = (psi1, psi0)
+      acc += l0r * p1i - l0i * p1r + l1r * p0i - l1i * p0r;
+    } else if (type == 1) {  // Y psi = (-i psi1, i psi0)
+      // -i psi1 = (p1i, -p1r); i psi0 = (-p0i, p0r)
+      acc += l0r * (-p1r) - l0i * p1i + l1r * p0r - l1i * (-p0i);
+    } else {  // Z psi = (psi0, -psi1)
+      acc += (l0r * p0i - l0i * p0r) - (l1r * p1i - l1i * p1r);
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int wv = 0; wv < kThreads / 64; ++wv) t += red[wv];
+    part[((int64_t)b * n_occ + occ) * nblk + blockIdx.x] = t;
+  }
+}
+
+__global__ void k_plain_grad_final(const double *__restrict__ part, int B, int n_occ, int nblk,
+                                   double *__restrict__ gocc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * n_occ) return;
+  double acc = 0.0;
+  for (int k = 0; k < nblk; ++k) acc += part[i * nblk + k];
+  gocc[i] = acc;
+}
+
+// Scatter per-occurrence derivatives into parameter slots (fixed order):
+// grad_w[j] = sum_b sum_{k in occ(w_j)} gocc[b][k];  grad_x[b][i] = sum_{k in occ(x_i)} gocc[b][k].
+__global__ void k_scatter(const double *__restrict__ gocc, int B, int n_occ,
+                          const int32_t *__restrict__ w_ptr, const int32_t *__restrict__ w_list,
+                          int n_w, const int32_t *__restrict__ x_ptr,
+                          const int32_t *__restrict__ x_list, int n_in, double *__restrict__ gw,
+                          double *__restrict__ gx) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_w) {
+    double acc = 0.0;
+    for (int b = 0; b < B; ++b)
+      for (int e = w_ptr[i]; e < w_ptr[i + 1]; ++e) acc += gocc[(int64_t)b * n_occ + w_list[e]];
+    gw[i] = acc;
+    return;
+  }
+  i -= n_w;
+  if (gx && i < (int64_t)B * n_in) {
+    int b = (int)(i / n_in), k = (int)(i % n_in);
+    double acc = 0.0;
+    for (int e = x_ptr[k]; e < x_ptr[k + 1]; ++e) acc += gocc[(int64_t)b * n_occ + x_list[e]];
+    gx[i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+
+static inline unsigned nb(int64_t work) { return (unsigned)((work + kThreads - 1) / kThreads); }
+
+hipError_t launch_half_angles(const DevCircuit &d, int B, const double *x, const double *w,
+                              double2 *cs, hipStream_t s) {
+  if (d.n_occ == 0) return hipSuccess;
+  k_half_angles<<<nb((int64_t)B * d.n_occ), kThreads, 0, s>>>(B, d.n_occ, d.occ_src, d.occ_idx, x,
+                                                              d.n_inputs, w, cs);
+  return hipGetLastError();
+}
+
+static int plain_nblk(int B, int64_t work) {
+  int64_t want = (2048 + B - 1) / B;
+  int64_t cap = (work + kThreads - 1) / kThreads;
+  int64_t v = want < cap ? want : cap;
+  if (v > 256) v = 256;
+  return (int)(v < 1 ? 1 : v);
+}
+
+template <typename R>
+hipError_t plain_forward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,
+                         void *state, double *part, double *out, bool normalise, hipStream_t s) {
+  Cx<R> *st = (Cx<R> *)state;
+  const int n = d.n;
+  const int64_t dim = (int64_t)1 << n;
+  k_plain_init<R><<<nb((int64_t)B * dim), kThreads, 0, s>>>(st, (int64_t)B * dim, dim);
+  for (size_t k = 0; k < h.gates.size(); ++k) {
+    const Gate &g = h.gates[k];
+    if (is_rotation(g.type))
+      k_plain_1q<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(st, nullptr, B, n, g.q0, g.type,
+                                                                    h.gate_occ[k], cs, d.n_occ, 0);
+    else if (g.type == G_CNOT)
+      k_plain_cnot<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(st, nullptr, B, n, g.q0, g.q1);
+    else
+      k_plain_cz<R><<<nb((int64_t)B * dim), kThreads, 0, s>>>(st, nullptr, B, n, g.q0, g.q1);
+  }
+  int nblk = plain_nblk(B, dim);
+  k_plain_expval<R><<<dim3(nblk, B), kThreads, 0, s>>>(st, n, d.masks, d.n_obs, part, nblk);
+  k_obs_final<<<nb((int64_t)B * d.n_obs), kThreads, 0, s>>>(part, B, nblk, d.n_obs, out,
+                                                            normalise ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t plain_backward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,
+                          void *state, void *lam_buf, const double *G, double *part, double *gocc,
+                          double *gw, double *gx, hipStream_t s) {
+  Cx<R> *psi = (Cx<R> *)state, *lam = (Cx<R> *)lam_buf;
+  const int n = d.n;
+  const int64_t dim = (int64_t)1 << n;
+  k_plain_seed<R><<<nb((int64_t)B * dim), kThreads, 0, s>>>(psi, lam, B, n, d.masks, d.n_obs, G);
+  const int nblk = plain_nblk(B, dim / 2);
+  for (int k = (int)h.gates.size() - 1; k >= 0; --k) {
+    const Gate &g = h.gates[k];
+    if (is_rotation(g.type)) {
+      k_plain_grad<R><<<dim3(nblk, B), kThreads, 0, s>>>(psi, lam, n, g.q0, g.type, h.gate_occ[k],
+                                                         d.n_occ, part, nblk);
+      k_plain_1q<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(psi, lam, B, n, g.q0, g.type,
+                                                                    h.gate_occ[k], cs, d.n_occ, 1);
+    } else if (g.type == G_CNOT) {
+      k_plain_cnot<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(psi, lam, B, n, g.q0, g.q1);
+    } else {
+      k_plain_cz<R><<<nb((int64_t)B * dim), kThreads, 0, s>>>(psi, lam, B, n, g.q0, g.q1);
+    }
+  }
+  if (d.n_occ > 0)
+    k_plain_grad_final<<<nb((int64_t)B * d.n_occ), kThreads, 0, s>>>(part, B, d.n_occ, nblk, gocc);
+  return launch_scatter(d, B, gocc, gw, gx, s);
+}
+
+hipError_t launch_obs_final(const double *part, int B, int nblk, int M, double *out,
+                            bool normalise, hipStream_t s) {
+  k_obs_final<<<nb((int64_t)B * M), kThreads, 0, s>>>(part, B, nblk, M, out, normalise ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, double *gw, double *gx,
+                          hipStream_t s) {
+  int64_t work = (int64_t)d.n_weights + (gx ? (int64_t)B * d.n_inputs : 0);
+  if (work == 0) return hipSuccess;
+  k_scatter<<<nb(work), kThreads, 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, d.n_weights, d.x_ptr,
+                                          d.x_list, d.n_inputs, gw, gx);
+  return hipGetLastError();
+}
+
+size_t plain_part_doubles(const DevCircuit &d, int B) {
+  const int64_t dim = (int64_t)1 << d.n;
+  size_t a = (size_t)B * plain_nblk(B, dim) * (d.n_obs + 1);
+  size_t b = (size_t)B * d.n_occ * plain_nblk(B, dim / 2);
+  return a > b ? a : b;
+}
+
+template hipError_t plain_forward<float>(const DevCircuit &, const HostCircuitInfo &, int,
+                                         const double2 *, void *, double *, double *, bool,
+                                         hipStream_t);
+template hipError_t plain_forward<double>(const DevCircuit &, const HostCircuitInfo &, int,
+                                          const double2 *, void *, double *, double *, bool,
+                                          hipStream_t);
+template hipError_t plain_backward<float>(const DevCircuit &, const HostCircuitInfo &, int,
+                                          const double2 *, void *, void *, const double *,
+                                          double *, double *, double *, double *, hipStream_t);
+template hipError_t plain_backward<double>(const DevCircuit &, const HostCircuitInfo &, int,
+                                           const double2 *, void *, void *, const double *,
+                                           double *, double *, double *, double *, hipStream_t);
+
+}  // namespace qtm

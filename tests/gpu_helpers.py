@@ -1,0 +1,56 @@
+"""Helpers for GPU tests: run the HIP path through the C ABI and compare."""
+from __future__ import annotations
+
+import numpy as np
+
+TOL_Z_C64 = 1e-5        # absolute, per expectation value
+TOL_G_C64 = 1e-4        # norm-wise relative per gradient vector
+TOL_Z_C128 = 1e-12
+TOL_G_C128 = 1e-10
+
+
+def run_gpu(circ, x, w, G, precision="c64", path=None, tile=None, klo=None, keep_state=True,
+            qcirc=None):
+    """Forward + backward on cuda:0.  Returns numpy (expvals, grad_w, grad_x)."""
+    import torch
+    import paper_2404_06314_amd as q
+    c = qcirc or q.Circuit.from_workload(circ)
+    if path is not None:
+        c.set_path(path)
+    if tile:
+        c.set_option(q.QTM_OPT_TILE_QUBITS, tile)
+    if klo:
+        c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
+    dev = torch.device("cuda:0")
+    xt = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+    wt = torch.as_tensor(np.ascontiguousarray(w), dtype=torch.float64, device=dev)
+    Gt = torch.as_tensor(np.ascontiguousarray(G), dtype=torch.float64, device=dev)
+    B = xt.shape[0]
+    st = c.alloc_state(B, precision) if keep_state else None
+    ev = c.forward(xt, wt, precision, state=st)
+    gw, gx = c.backward(xt, wt, Gt, precision, state=st)
+    torch.cuda.synchronize()
+    return ev.cpu().numpy(), gw.cpu().numpy(), gx.cpu().numpy()
+
+
+def assert_grad_close(got, ref, tol, what=""):
+    """Norm-wise relative check: max|got - ref| <= tol * max|ref| (per vector)."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    scale = max(np.max(np.abs(ref)), 1e-30)
+    err = np.max(np.abs(got - ref)) if ref.size else 0.0
+    assert err <= tol * scale, f"{what}: max err {err:.3e} > {tol:g} * {scale:.3e}"
+
+
+def assert_parity(gpu, ref, precision, what=""):
+    ev, gw, gx = gpu
+    rev, rgw, rgx = ref
+    tz = TOL_Z_C64 if precision == "c64" else TOL_Z_C128
+    tg = TOL_G_C64 if precision == "c64" else TOL_G_C128
+    err = np.max(np.abs(ev - rev))
+    assert err <= tz, f"{what}: <Z> max err {err:.3e} > {tz:g}"
+    if rgw.size:
+        assert_grad_close(gw, rgw, tg, what + " dL/dw")
+    for b in range(rgx.shape[0]):
+        if rgx.shape[1]:
+            assert_grad_close(gx[b], rgx[b], tg, what + f" dL/dx[{b}]")

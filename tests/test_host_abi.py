@@ -1,0 +1,151 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+and its host-side logic (validation, state sizes, options, the fused-path
+planner) behaves.  No compute call is made here (no GPU in this suite)."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qtm.h")
+
+
+@pytest.fixture(scope="module")
+def qtm():
+    import paper_2404_06314_amd as q
+    q._lib.load()
+    return q
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qtm_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(qtm):
+    lib = qtm._lib.load()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in qtm._lib.SIGNATURES, f"binding lacks {n}"
+    assert lib.qtm_version().decode().startswith("qtm")
+
+
+def make(qtm, n, gates, n_in=0, n_w=0, masks=(1,)):
+    g = np.asarray(gates, dtype=np.int32).reshape(-1, 5)
+    return qtm.Circuit(n, g, n_in, n_w, np.asarray(masks, dtype=np.uint64))
+
+
+@pytest.mark.parametrize("n,gates,n_in,n_w,masks,code", [
+    (31, [], 0, 0, [1], -2),                                   # too many qubits
+    (0, [], 0, 0, [1], -1),
+    (2, [[0, 2, 0, 2, 0]], 0, 1, [1], -1),                     # qubit out of range
+    (2, [[3, 1, 1, 0, 0]], 0, 0, [1], -1),                     # control == target
+    (2, [[4, 0, 5, 0, 0]], 0, 0, [1], -1),                     # CZ qubit out of range
+    (2, [[1, 0, 0, 2, 3]], 0, 3, [1], -1),                     # weight index out of range
+    (2, [[0, 0, 0, 1, 1]], 1, 0, [1], -1),                     # input index out of range
+    (2, [[0, 0, 0, 0, 0]], 1, 0, [1], -1),                     # rotation without source
+    (2, [[7, 0, 1, 0, 0]], 0, 0, [1], -2),                     # unknown gate type
+    (2, [], 0, 0, [4], -1),                                    # mask bit >= n
+    (2, [], 0, 0, [], -1),                                     # no observable
+])
+def test_validation_errors(qtm, n, gates, n_in, n_w, masks, code):
+    with pytest.raises(qtm.QtmError) as ei:
+        make(qtm, n, gates, n_in, n_w, masks)
+    assert ei.value.code == code
+    assert qtm._lib.load().qtm_last_error().decode()
+
+
+def test_state_bytes_and_options(qtm):
+    c = qtm.Circuit.from_workload(W.config_workload("c3").circuit)
+    assert c.state_bytes(64, "c64") == 64 * (1 << 20) * 8
+    assert c.state_bytes(3, "c128") == 3 * (1 << 20) * 16
+    with pytest.raises(qtm.QtmError):
+        c.state_bytes(0, "c64")
+    with pytest.raises(qtm.QtmError):
+        c.set_option(qtm.QTM_OPT_TILE_QUBITS, 13)
+    with pytest.raises(qtm.QtmError):
+        c.set_option(99, 1)
+    c.set_option(qtm.QTM_OPT_TILE_QUBITS, 10)
+    c.set_path(qtm.QTM_PATH_PLAIN)
+
+
+def test_null_pointer_errors_do_not_touch_the_gpu(qtm):
+    c = qtm.Circuit.from_workload(W.config_workload("c1").circuit)
+    lib = qtm._lib.load()
+    # expvals NULL -> invalid argument before any device call
+    rc = lib.qtm_forward(c.handle, 2, 0, None, None, None, None, None)
+    assert rc == qtm._lib.QTM_ERR_INVALID_ARG
+    rc = lib.qtm_backward(c.handle, 2, 0, None, None, None, None, None, None, None)
+    assert rc == qtm._lib.QTM_ERR_INVALID_ARG
+    rc = lib.qtm_forward(c.handle, 0, 0, None, None, None, None, None)
+    assert rc == qtm._lib.QTM_ERR_INVALID_ARG
+
+
+def _plan_gate_order(plan):
+    order = []
+    for sw in plan["sweeps"]:
+        for st in sw["stages"]:
+            order.extend(st["gates"])
+    return order
+
+
+def _check_plan(qtm, circ, precision="c64", tile=None, klo=None, batch=2, seed=0):
+    c = qtm.Circuit.from_workload(circ)
+    if tile:
+        c.set_option(qtm.QTM_OPT_TILE_QUBITS, tile)
+    if klo:
+        c.set_option(qtm.QTM_OPT_LOW_QUBITS, klo)
+    plan = c.plan(precision)
+    assert "error" not in plan
+    order = _plan_gate_order(plan)
+    assert sorted(order) == list(range(circ.n_gates))
+    for sw in plan["sweeps"]:
+        assert len(sw["tile"]) == plan["kt"]
+        assert sw["tile"][:plan["klo"]] == list(range(plan["klo"]))
+    # executing the gates in plan order gives the same results (oracle)
+    rng = np.random.default_rng(seed)
+    wl = W.random_workload(rng, circ, batch)
+    re = W.Circuit(n=circ.n, gates=circ.gates[order], n_inputs=circ.n_inputs,
+                   n_weights=circ.n_weights, masks=circ.masks)
+    a = oracle.vjp(circ, wl.inputs, wl.weights, wl.grad_out)
+    b = oracle.vjp(re, wl.inputs, wl.weights, wl.grad_out)
+    for u, v in zip(a, b):
+        np.testing.assert_allclose(u, v, atol=1e-11)
+    return plan
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_plan_reorders_only_commuting_gates(qtm, name):
+    _check_plan(qtm, W.config_workload(name).circuit)
+
+
+@pytest.mark.parametrize("n,L,ent,tile,klo", [(10, 3, "ring", 6, 3), (9, 2, "ladder", 5, 2),
+                                              (11, 2, "ring", 7, 5), (8, 4, "ladder", 4, 4)])
+def test_plan_multi_sweep_small(qtm, n, L, ent, tile, klo):
+    plan = _check_plan(qtm, W.layered_circuit(n, L, ent), tile=tile, klo=klo)
+    assert len(plan["sweeps"]) >= 2
+
+
+def test_plan_random_circuits(qtm):
+    rng = np.random.default_rng(5)
+    for n in (4, 5, 7, 9):
+        for _ in range(4):
+            circ = W.random_circuit(rng, n, 40)
+            _check_plan(qtm, circ, tile=4 if n > 4 else None, klo=2, seed=n)
+
+
+def test_plan_sizes_for_configs(qtm):
+    """The n = 20 and n = 26 configurations plan into few sweeps."""
+    for name, max_sweeps in (("c3", 12), ("c5", 36)):
+        c = qtm.Circuit.from_workload(W.config_workload(name).circuit)
+        plan = c.plan("c64")
+        assert 1 <= len(plan["sweeps"]) <= max_sweeps, (name, len(plan["sweeps"]))

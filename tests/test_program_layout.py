@@ -1,0 +1,125 @@
+"""CPU emulation of the fused kernels' index arithmetic over the encoded
+device program: every global address and LDS slot the kernels compute must
+be in range and each stage's / load's mapping must be a permutation.  This
+runs before any kernel is launched, so a layout bug cannot reach the GPU."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+KREG = 4
+SW_OUTER, SW_TILE, SW_LOADG, SW_LOADL, SW_LOADTB, SW_STAGES = 4, 34, 46, 62, 78, 90
+ST_LDS, ST_GLOB, ST_TBL, ST_TBG, ST_OPS = 4, 20, 36, 48, 60
+
+
+def swz(i):
+    return i ^ ((i >> 5) & 31) ^ ((i >> 10) & 31)
+
+
+def check_program(plan, n):
+    code = np.array(plan["code"], dtype=np.int64)
+    kt = plan["kt"]
+    nt = 1 << (kt - KREG)
+    t = np.arange(nt)
+    for offs in (plan["sweep_off_fwd"], plan["sweep_off_bwd"]):
+        assert len(offs) == len(plan["sweeps"])
+        for off in offs:
+            H = code[off:]
+            nst, nout = int(H[0]), int(H[1])
+            assert nout == n - kt
+            outer = H[SW_OUTER:SW_OUTER + nout]
+            tiles = np.arange(1 << nout)
+            tbase = np.zeros_like(tiles)
+            for i, pos in enumerate(outer):
+                tbase |= ((tiles >> i) & 1) << int(pos)
+            gload = np.zeros_like(t)
+            for i in range(kt - KREG):
+                gload |= ((t >> i) & 1) << int(H[SW_LOADTB + i])
+            addrs = (tbase[:, None, None] | gload[None, :, None] |
+                     H[SW_LOADG:SW_LOADG + 16][None, None, :])
+            assert addrs.max() < (1 << n) and addrs.min() >= 0
+            assert len(np.unique(addrs)) == 1 << n, "load addresses are not a permutation"
+            lload = swz(t)[:, None] ^ H[SW_LOADL:SW_LOADL + 16][None, :]
+            assert lload.max() < (1 << kt)
+            assert len(np.unique(lload)) == 1 << kt
+            # the load layout and its LDS slot describe the same local index:
+            # local index t + nt*j, whose global image is gload | loadG_j
+            for s in range(nst):
+                S = code[int(H[SW_STAGES + s]):]
+                lt = np.zeros_like(t)
+                gt = np.zeros_like(t)
+                for i in range(kt - KREG):
+                    lt |= ((t >> i) & 1) << int(S[ST_TBL + i])
+                    gt |= ((t >> i) & 1) << int(S[ST_TBG + i])
+                lidx = swz(lt)[:, None] ^ S[ST_LDS:ST_LDS + 16][None, :]
+                assert lidx.max() < (1 << kt)
+                assert len(np.unique(lidx)) == 1 << kt, "stage LDS slots not a permutation"
+                gidx = gt[:, None] | S[ST_GLOB:ST_GLOB + 16][None, :]
+                assert len(np.unique(gidx)) == 1 << kt
+                assert np.all((gt[:, None] & S[ST_GLOB:ST_GLOB + 16][None, :]) == 0)
+                # consistency: slot lidx holds the amplitude whose tile-local
+                # index maps to gidx; compare against the load layout's map
+                tile_pos = H[SW_TILE:SW_TILE + kt]
+                local_of = {}
+                for tt in range(nt):
+                    for j in range(16):
+                        local = tt + nt * j
+                        g = 0
+                        for k in range(kt):
+                            if (local >> k) & 1:
+                                g |= 1 << int(tile_pos[k])
+                        local_of[swz(local)] = g
+                for tt in range(nt):
+                    for j in range(16):
+                        assert local_of[int(lidx[tt, j])] == int(gidx[tt, j])
+                nops = int(S[0])
+                for o in range(nops):
+                    op = S[ST_OPS + 4 * o: ST_OPS + 4 * o + 4]
+                    assert op[0] in (1, 2, 3)
+                    if op[0] == 1:
+                        assert 0 <= op[1] < 4 and 0 <= op[2] < plan["n_blocks"]
+                    elif op[0] == 2:
+                        assert 0 <= op[1] < 4 and op[2] in (0, 1)
+                        assert (0 <= op[3] < 4 and op[3] != op[1]) if op[2] == 0 else 0 <= op[3] < n
+                    else:
+                        rec = code[int(op[1]):]
+                        ng = int(rec[0])
+                        assert 0 <= ng <= n
+
+
+@pytest.mark.parametrize("name,tile,klo", [("c1", 0, 0), ("c2", 0, 0), ("c3", 0, 0),
+                                           ("c3", 10, 4), ("c5", 0, 0)])
+def test_program_layout_configs(name, tile, klo):
+    import paper_2404_06314_amd as q
+    wl = W.config_workload(name)
+    c = q.Circuit.from_workload(wl.circuit)
+    if tile:
+        c.set_option(q.QTM_OPT_TILE_QUBITS, tile)
+    if klo:
+        c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
+    if name == "c5":
+        pytest.skip("n = 26 emulation is too large for the CPU suite; covered by c3 layouts")
+    check_program(c.plan("c64"), wl.circuit.n)
+
+
+@pytest.mark.parametrize("n,L,ent,tile,klo", [(6, 2, "ring", 4, 2), (9, 3, "ladder", 5, 3),
+                                              (10, 2, "ring", 6, 4), (13, 2, "ring", 12, 5),
+                                              (14, 3, "ladder", 8, 5), (11, 4, "ring", 7, 6)])
+def test_program_layout_small(n, L, ent, tile, klo):
+    import paper_2404_06314_amd as q
+    c = q.Circuit.from_workload(W.layered_circuit(n, L, ent))
+    c.set_option(q.QTM_OPT_TILE_QUBITS, tile)
+    c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
+    check_program(c.plan("c64"), n)
+
+
+def test_program_layout_random():
+    import paper_2404_06314_amd as q
+    rng = np.random.default_rng(9)
+    for n in (4, 5, 6, 8):
+        circ = W.random_circuit(rng, n, 60)
+        c = q.Circuit.from_workload(circ)
+        if n > 4:
+            c.set_option(q.QTM_OPT_TILE_QUBITS, 4)
+        c.set_option(q.QTM_OPT_LOW_QUBITS, 2)
+        check_program(c.plan("c64"), n)
