@@ -16,6 +16,10 @@ HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 (v_pk_*_f32) instructions in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep SimplifyCFG from merging the per-register-bit switch cases into
+    # pointer phis, which would force the 16-amplitude register arrays into
+    # scratch memory
+    "-mllvm", "-simplifycfg-sink-common=false",
     "-I" + str(ROOT / "include"),
 ]
 

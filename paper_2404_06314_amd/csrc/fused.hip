@@ -332,14 +332,15 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_fwd(FwdArgs a) {
         }
       }
       if (a.last && s == nst - 1) {
-        float p[kRegs];
+        // per-thread partials in the state's precision, FP64 across lanes
+        R p[kRegs];
 #pragma unroll
-        for (int j = 0; j < kRegs; ++j) p[j] = (float)v[j].x * (float)v[j].x + (float)v[j].y * (float)v[j].y;
+        for (int j = 0; j < kRegs; ++j) p[j] = v[j].x * v[j].x + v[j].y * v[j].y;
         for (int m = 0; m <= a.M; ++m) {
           const float *sg = a.obs_sgn + m * kRegs;
-          float acc = 0.f;
+          R acc = 0;
 #pragma unroll
-          for (int j = 0; j < kRegs; ++j) acc += sg[j] * p[j];
+          for (int j = 0; j < kRegs; ++j) acc += (R)sg[j] * p[j];
           const uint32_t mask = m < a.M ? (uint32_t)a.masks[m] : 0u;
           double d = (__popc(gt & mask) & 1) ? -(double)acc : (double)acc;
           d = wave_sum_w<WS>(d);
@@ -433,11 +434,11 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_bwd(BwdArgs a) {
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) dj[j] += sg[j] * gm;
       }
-      float nrm = 0.f;
+      R nrm = 0;
 #pragma unroll
       for (int j = 0; j < kRegs; ++j) {
         l[j] = Cx<R>{(R)(dj[j] * (double)v[j].x), (R)(dj[j] * (double)v[j].y)};
-        nrm += (float)v[j].x * (float)v[j].x + (float)v[j].y * (float)v[j].y;
+        nrm += v[j].x * v[j].x + v[j].y * v[j].y;
       }
       double dn = wave_sum_w<WS>((double)nrm);
       if (lane == 0) nacc[wave] += dn;
@@ -475,7 +476,7 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_bwd(BwdArgs a) {
           if (op[3] >= 0) {
             R tx = 0, ty = 0, tz = 0;
             tcomp<R>(v, l, op[1], tx, ty, tz);
-            float fx = wave_sum_w<WS>((float)tx), fy = wave_sum_w<WS>((float)ty), fz = wave_sum_w<WS>((float)tz);
+            const R fx = wave_sum_w<WS>(tx), fy = wave_sum_w<WS>(ty), fz = wave_sum_w<WS>(tz);
             if (lane == 0) {
               double *g = gacc + op[3] * 3 * NW;
               g[wave] += (double)fx;
