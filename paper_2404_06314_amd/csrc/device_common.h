@@ -6,6 +6,17 @@
 
 namespace qtm {
 
+// Read-only tables that all lanes of a wave read at the same address (sweep
+// program, gate matrices, sign tables) are addressed through the constant
+// address space, so the compiler issues scalar loads instead of vector loads
+// that would wait behind the kernel's own state traffic.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+  return (cptr<T>)(uintptr_t)p;
+}
+
 template <typename R>
 struct Cx {
   R x, y;
@@ -25,6 +36,12 @@ template <typename R>
 struct M2 {
   Cx<R> a, b, c, d;
 };
+
+template <typename R>
+__device__ __forceinline__ M2<R> load_m2(cptr<M2<R>> p) {
+  const cptr<R> f = reinterpret_cast<cptr<R>>(p);
+  return M2<R>{{f[0], f[1]}, {f[2], f[3]}, {f[4], f[5]}, {f[6], f[7]}};
+}
 
 // out0 = a v0 + b v1 ; out1 = c v0 + d v1
 template <typename R>
@@ -67,6 +84,25 @@ template <int W, typename T>
 __device__ __forceinline__ T wave_sum_w(T v) {
 #pragma unroll
   for (int o = W / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+// One DPP reduction step: x + x[lane permuted by CTRL] (rows outside ROW_MASK add 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+  int o = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW_MASK, 0xf, false);
+  return x + __builtin_bit_cast(float, o);
+}
+
+// Sum of a float over all 64 lanes with DPP row operations (no LDS traffic);
+// the total ends up in lane 63.  Every lane must be active.
+__device__ __forceinline__ float dpp_sum_to_lane63(float v) {
+  v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror: every lane of a row holds the row sum
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 

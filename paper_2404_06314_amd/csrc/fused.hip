@@ -18,6 +18,7 @@
 // the derivative of every rotation inside the block follows from them and
 // the block's later rotations (see k_fused_prep).
 #include <mutex>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -157,6 +158,85 @@ __device__ __forceinline__ void u1_adj(Cx<R> (&v)[kRegs], int p, const M2<R> &m)
   }
 }
 
+// --- complex64 gates on the matrix cores -----------------------------------
+//
+// A 2x2 complex gate [[a, b], [c, d]] acting on one pair (v0, v1) is the 4x4
+// real matrix M on (re0, im0, re1, im1):
+//   row 0: ( a.x, -a.y,  b.x, -b.y)    row 1: ( a.y,  a.x,  b.y,  b.x)
+//   row 2: ( c.x, -c.y,  d.x, -d.y)    row 3: ( c.y,  c.x,  d.y,  d.x)
+// v_mfma_f32_4x4x1_16b_f32 computes, for every 4-lane block, the outer product
+// D[i][j] += A(lane 4b + i) * B(lane 4b + j) with D[i] held in register i of
+// lane 4b + j.  With A = column k of M in "row = lane & 3" order and B = the
+// k-th component of each lane's own pair, four instructions (k = 0..3) give
+// every lane M times its pair: each lane's 8 pairs are 8 independent
+// matrix-vector products, with no data moved between lanes.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+struct MCols {
+  float k0, k1, k2, k3;
+};
+
+__device__ __forceinline__ MCols mfma_cols(Cx<float> a, Cx<float> b, Cx<float> c, Cx<float> d,
+                                           int row) {
+  const Cx<float> p = row < 2 ? a : c;
+  const Cx<float> q = row < 2 ? b : d;
+  const bool odd = row & 1;
+  return {odd ? p.y : p.x, odd ? p.x : -p.y, odd ? q.y : q.x, odd ? q.x : -q.y};
+}
+
+template <int P>
+__device__ __forceinline__ constexpr int pair_lo(int p) {
+  return ((p >> P) << (P + 1)) | (p & ((1 << P) - 1));
+}
+
+template <int P, int NS>
+__device__ __forceinline__ void u1_mfma_bit(Cx<float> (*const *vs)[kRegs], const MCols &A) {
+  constexpr int NP = kRegs / 2, CH = 4;  // 4 independent accumulation chains at a time
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int c0 = 0; c0 < NP; c0 += CH) {
+      Cx<float>(&v)[kRegs] = *vs[s];
+      floatx4 acc[CH];
+#pragma unroll
+      for (int p = 0; p < CH; ++p)
+        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(A.k0, v[pair_lo<P>(c0 + p)].x, zero, 0, 0, 0);
+#pragma unroll
+      for (int p = 0; p < CH; ++p)
+        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(A.k1, v[pair_lo<P>(c0 + p)].y, acc[p], 0, 0, 0);
+#pragma unroll
+      for (int p = 0; p < CH; ++p)
+        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(A.k2, v[pair_lo<P>(c0 + p) | (1 << P)].x,
+                                                    acc[p], 0, 0, 0);
+#pragma unroll
+      for (int p = 0; p < CH; ++p)
+        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(A.k3, v[pair_lo<P>(c0 + p) | (1 << P)].y,
+                                                    acc[p], 0, 0, 0);
+#pragma unroll
+      for (int p = 0; p < CH; ++p) {
+        v[pair_lo<P>(c0 + p)] = Cx<float>{acc[p][0], acc[p][1]};
+        v[pair_lo<P>(c0 + p) | (1 << P)] = Cx<float>{acc[p][2], acc[p][3]};
+      }
+    }
+}
+
+// Apply m (adjoint = false) or m^dag (adjoint = true) to register bit p of
+// NS register tiles.
+template <int NS>
+__device__ __forceinline__ void u1_mfma(Cx<float> (*const *vs)[kRegs], int p, const M2<float> &m,
+                                        bool adjoint, int row) {
+  const MCols A = adjoint ? mfma_cols(Cx<float>{m.a.x, -m.a.y}, Cx<float>{m.c.x, -m.c.y},
+                                      Cx<float>{m.b.x, -m.b.y}, Cx<float>{m.d.x, -m.d.y}, row)
+                          : mfma_cols(m.a, m.b, m.c, m.d, row);
+  switch (p) {
+    case 0: u1_mfma_bit<0, NS>(vs, A); break;
+    case 1: u1_mfma_bit<1, NS>(vs, A); break;
+    case 2: u1_mfma_bit<2, NS>(vs, A); break;
+    default: u1_mfma_bit<3, NS>(vs, A); break;
+  }
+}
+
 // CNOT with target register bit P and control register bit C
 template <typename R, int P, int C>
 __device__ __forceinline__ void cnot_rr(Cx<R> (&v)[kRegs]) {
@@ -209,11 +289,11 @@ __device__ __forceinline__ void cnot_op(Cx<R> (&v)[kRegs], int p, int kind, int 
 }
 
 // Diagonal op: sign(x) for x = gt | W_j from the diag record.
-__device__ __forceinline__ uint32_t diag_signs(const int32_t *__restrict__ rec, uint32_t gt) {
+__device__ __forceinline__ uint32_t diag_signs(cptr<int32_t> rec, uint32_t gt) {
   const int ng = rec[0];
   uint32_t q = 0;
   for (int g = 0; g < ng; ++g) q += __popc(gt & (gt >> rec[1 + 2 * g]) & (uint32_t)rec[2 + 2 * g]);
-  const int32_t *C = rec + 1 + 2 * ng;
+  cptr<int32_t> C = rec + 1 + 2 * ng;
   uint32_t cb = (uint32_t)C[kRegs];
   uint32_t bits = 0;
 #pragma unroll
@@ -271,19 +351,22 @@ struct FwdArgs {
 };
 
 template <typename R, int KT>
-__global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_fwd(FwdArgs a) {
+__global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) k_fused_fwd(FwdArgs a) {
   constexpr int NT = 1 << (KT - kRegBits);
   constexpr int NW = (NT + 63) / 64;
   constexpr int WS = NT < 64 ? NT : 64;  // lanes per wave in use
+  // complex64 gates run on the matrix cores (needs full 64-lane waves)
+  constexpr bool kMfma = std::is_same<R, float>::value && NT >= 64;
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<R> *lds = reinterpret_cast<Cx<R> *>(smem);
   double *obs_acc = reinterpret_cast<double *>(smem + (sizeof(Cx<R>) << KT));
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int b = blockIdx.y;
-  const int32_t *__restrict__ H = a.prog + a.sweep_off;
+  const cptr<int32_t> prog = as_const(a.prog);
+  const cptr<int32_t> H = prog + a.sweep_off;
   const int nst = H[0], nout = H[1];
   Cx<R> *__restrict__ st = reinterpret_cast<Cx<R> *>(a.state) + ((int64_t)b << a.n);
-  const M2<R> *__restrict__ mats = reinterpret_cast<const M2<R> *>(a.mats) + (int64_t)b * a.n_blocks;
+  const cptr<M2<R>> mats = as_const(reinterpret_cast<const M2<R> *>(a.mats)) + (int64_t)b * a.n_blocks;
   uint32_t gload = 0;
 #pragma unroll
   for (int i = 0; i < KT - kRegBits; ++i)
@@ -307,7 +390,7 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_fwd(FwdArgs a) {
 #pragma unroll
     for (int j = 0; j < kRegs; ++j) lds[lload ^ (uint32_t)H[kSwLoadL + j]] = v[j];
     for (int s = 0; s < nst; ++s) {
-      const int32_t *__restrict__ S = a.prog + H[kSwStages + s];
+      const cptr<int32_t> S = prog + H[kSwStages + s];
       __syncthreads();
       uint32_t lt = 0, gt = tbase;
 #pragma unroll
@@ -321,14 +404,20 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_fwd(FwdArgs a) {
       for (int j = 0; j < kRegs; ++j) v[j] = lds[lsw ^ (uint32_t)S[kStLds + j]];
       const int nops = S[0];
       for (int o = 0; o < nops; ++o) {
-        const int32_t *op = S + kStOps + 4 * o;
+        const cptr<int32_t> op = S + kStOps + 4 * o;
         const int code = op[0];
         if (code == OP_U1) {
-          u1<R>(v, op[1], mats[op[2]]);
+          const M2<R> m = load_m2<R>(mats + op[2]);
+          if constexpr (kMfma) {
+            Cx<float>(*const vs[1])[kRegs] = {&v};
+            u1_mfma<1>(vs, op[1], m, false, lane & 3);
+          } else {
+            u1<R>(v, op[1], m);
+          }
         } else if (code == OP_CNOT) {
           cnot_op<R>(v, op[1], op[2], op[3], gt);
         } else {
-          apply_signs<R>(v, diag_signs(a.prog + op[1], gt));
+          apply_signs<R>(v, diag_signs(prog + op[1], gt));
         }
       }
       if (a.last && s == nst - 1) {
@@ -337,11 +426,11 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_fwd(FwdArgs a) {
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) p[j] = v[j].x * v[j].x + v[j].y * v[j].y;
         for (int m = 0; m <= a.M; ++m) {
-          const float *sg = a.obs_sgn + m * kRegs;
+          const cptr<float> sg = as_const(a.obs_sgn) + m * kRegs;
           R acc = 0;
 #pragma unroll
           for (int j = 0; j < kRegs; ++j) acc += (R)sg[j] * p[j];
-          const uint32_t mask = m < a.M ? (uint32_t)a.masks[m] : 0u;
+          const uint32_t mask = m < a.M ? (uint32_t)as_const(a.masks)[m] : 0u;
           double d = (__popc(gt & mask) & 1) ? -(double)acc : (double)acc;
           d = wave_sum_w<WS>(d);
           if (lane == 0) obs_acc[m * NW + wave] += d;
@@ -392,21 +481,23 @@ struct BwdArgs {
 };
 
 template <typename R, int KT>
-__global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_bwd(BwdArgs a) {
+__global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) k_fused_bwd(BwdArgs a) {
   constexpr int NT = 1 << (KT - kRegBits);
   constexpr int NW = (NT + 63) / 64;
   constexpr int WS = NT < 64 ? NT : 64;  // lanes per wave in use
+  constexpr bool kMfma = std::is_same<R, float>::value && NT >= 64;
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<R> *lds_p = reinterpret_cast<Cx<R> *>(smem);
   Cx<R> *lds_l = lds_p + (1 << KT);
   double *gacc = reinterpret_cast<double *>(smem + (2 * sizeof(Cx<R>) << KT));
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int b = blockIdx.y;
-  const int32_t *__restrict__ H = a.prog + a.sweep_off;
+  const cptr<int32_t> prog = as_const(a.prog);
+  const cptr<int32_t> H = prog + a.sweep_off;
   const int nst = H[0], nout = H[1], ngs = H[2];
   Cx<R> *__restrict__ ps = reinterpret_cast<Cx<R> *>(a.psi) + ((int64_t)b << a.n);
   Cx<R> *__restrict__ ls = reinterpret_cast<Cx<R> *>(a.lam) + ((int64_t)b << a.n);
-  const M2<R> *__restrict__ mats = reinterpret_cast<const M2<R> *>(a.mats) + (int64_t)b * a.n_blocks;
+  const cptr<M2<R>> mats = as_const(reinterpret_cast<const M2<R> *>(a.mats)) + (int64_t)b * a.n_blocks;
   uint32_t gload = 0;
 #pragma unroll
   for (int i = 0; i < KT - kRegBits; ++i)
@@ -428,9 +519,9 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_bwd(BwdArgs a) {
 #pragma unroll
       for (int j = 0; j < kRegs; ++j) dj[j] = 0.0;
       for (int m = 0; m < a.M; ++m) {
-        double gm = a.G[(int64_t)b * a.M + m];
-        if (__popc(g0 & (uint32_t)a.masks[m]) & 1) gm = -gm;
-        const double *sg = a.seed_sgn + m * kRegs;
+        double gm = as_const(a.G)[(int64_t)b * a.M + m];
+        if (__popc(g0 & (uint32_t)as_const(a.masks)[m]) & 1) gm = -gm;
+        const cptr<double> sg = as_const(a.seed_sgn) + m * kRegs;
 #pragma unroll
         for (int j = 0; j < kRegs; ++j) dj[j] += sg[j] * gm;
       }
@@ -452,7 +543,7 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_bwd(BwdArgs a) {
       lds_l[lload ^ (uint32_t)H[kSwLoadL + j]] = l[j];
     }
     for (int s = 0; s < nst; ++s) {
-      const int32_t *__restrict__ S = a.prog + H[kSwStages + s];
+      const cptr<int32_t> S = prog + H[kSwStages + s];
       __syncthreads();
       uint32_t lt = 0, gt = tbase;
 #pragma unroll
@@ -469,14 +560,23 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_bwd(BwdArgs a) {
       }
       const int nops = S[0];
       for (int o = 0; o < nops; ++o) {
-        const int32_t *op = S + kStOps + 4 * o;
+        const cptr<int32_t> op = S + kStOps + 4 * o;
         const int code = op[0];
         if (code == OP_U1) {
-          const M2<R> m = mats[op[2]];
+          const M2<R> m = load_m2<R>(mats + op[2]);
           if (op[3] >= 0) {
             R tx = 0, ty = 0, tz = 0;
             tcomp<R>(v, l, op[1], tx, ty, tz);
-            const R fx = wave_sum_w<WS>(tx), fy = wave_sum_w<WS>(ty), fz = wave_sum_w<WS>(tz);
+            R fx, fy, fz;
+            if constexpr (kMfma) {
+              fx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(tx)), 63));
+              fy = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(ty)), 63));
+              fz = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(tz)), 63));
+            } else {
+              fx = wave_sum_w<WS>(tx);
+              fy = wave_sum_w<WS>(ty);
+              fz = wave_sum_w<WS>(tz);
+            }
             if (lane == 0) {
               double *g = gacc + op[3] * 3 * NW;
               g[wave] += (double)fx;
@@ -484,13 +584,18 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_bwd(BwdArgs a) {
               g[2 * NW + wave] += (double)fz;
             }
           }
-          u1_adj<R>(v, op[1], m);
-          u1_adj<R>(l, op[1], m);
+          if constexpr (kMfma) {
+            Cx<float>(*const vs[2])[kRegs] = {&v, &l};
+            u1_mfma<2>(vs, op[1], m, true, lane & 3);
+          } else {
+            u1_adj<R>(v, op[1], m);
+            u1_adj<R>(l, op[1], m);
+          }
         } else if (code == OP_CNOT) {
           cnot_op<R>(v, op[1], op[2], op[3], gt);
           cnot_op<R>(l, op[1], op[2], op[3], gt);
         } else {
-          const uint32_t bits = diag_signs(a.prog + op[1], gt);
+          const uint32_t bits = diag_signs(prog + op[1], gt);
           apply_signs<R>(v, bits);
           apply_signs<R>(l, bits);
         }
@@ -517,7 +622,7 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits)) k_fused_bwd(BwdArgs a) {
     __syncthreads();
   }
   __syncthreads();
-  const int32_t *gsl = H + kSwStages + nst;
+  const cptr<int32_t> gsl = H + kSwStages + nst;
   for (int i = t; i < ngs * 3; i += NT) {
     const int ls_ = i / 3, c = i % 3;
     double acc = 0.0;
