@@ -10,7 +10,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/qtm.h"
+#include "qtm.h"
 #include "circuit.h"
 #include "kernels.h"
 
@@ -263,6 +263,7 @@ int get_plan(qtm_circuit_t c, int precision, DevPlan **out) {
   }
   int rc;
   if ((rc = upload(&dp.code, prog.code, c->owned))) return rc;
+  if ((rc = upload(&dp.thr, prog.thr, c->owned))) return rc;
   if ((rc = upload(&dp.blk, blk, c->owned))) return rc;
   if ((rc = upload(&dp.blk_off, blk_off, c->owned))) return rc;
   if ((rc = upload(&dp.occ_gslot, occ_gslot, c->owned))) return rc;
@@ -528,6 +529,8 @@ int qtm_plan_json(qtm_circuit_t c, int32_t precision, char *buf, size_t len, siz
     Program prog = encode_program(c->desc, plan);
     std::string extra = ",\"code\":[";
     for (size_t i = 0; i < prog.code.size(); ++i) extra += (i ? "," : "") + std::to_string(prog.code[i]);
+    extra += "],\"thr\":[";
+    for (size_t i = 0; i < prog.thr.size(); ++i) extra += (i ? "," : "") + std::to_string(prog.thr[i]);
     extra += "],\"sweep_off_fwd\":[";
     for (size_t i = 0; i < prog.sweep_off_fwd.size(); ++i)
       extra += (i ? "," : "") + std::to_string(prog.sweep_off_fwd[i]);

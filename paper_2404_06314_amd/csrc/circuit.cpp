@@ -6,7 +6,7 @@
 #include <set>
 #include <sstream>
 
-#include "../../include/qtm.h"
+#include "qtm.h"
 
 namespace qtm {
 
@@ -193,11 +193,12 @@ struct Sched {
   // `inset`; `allowed` restricts the op set (sweep scope).  Returns the ops
   // run, in order.
   std::vector<int> run(const std::vector<char> &inset, const std::vector<char> *allowed,
-                       bool commit) {
+                       bool commit, int max_blocks = 1 << 30) {
     std::vector<int> lft = left;
     std::vector<char> dn = done;
     std::vector<int> order;
     std::vector<int> ready;
+    int blocks = 0;
     for (size_t i = 0; i < ops.size(); ++i)
       if (!dn[i] && lft[i] == 0 && (!allowed || (*allowed)[i])) ready.push_back((int)i);
     std::sort(ready.begin(), ready.end());
@@ -208,10 +209,11 @@ struct Sched {
       for (int i : ready) {
         const FOp &o = ops[i];
         int t = o.target();
-        if (t >= 0 && !inset[t]) {
+        if ((t >= 0 && !inset[t]) || (o.kind == FK_BLOCK && blocks >= max_blocks)) {
           next.push_back(i);
           continue;
         }
+        if (o.kind == FK_BLOCK) ++blocks;
         dn[i] = 1;
         order.push_back(i);
         progress = true;
@@ -296,7 +298,7 @@ Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo) {
     std::vector<char> base(c.n, 0);
     for (int q = 0; q < p.klo; ++q) base[q] = 1;
     std::vector<char> T = choose_set(S, base, all_q, kt, c.n, nullptr);
-    std::vector<int> order = S.run(T, nullptr, true);
+    std::vector<int> order = S.run(T, nullptr, true, kMaxSweepBlocks);
     if (order.empty()) break;  // cannot happen: the earliest ready op's target gets picked
     n_done += order.size();
     Sweep sw;
@@ -340,6 +342,19 @@ Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo) {
       if (p.ops[i].kind == FK_BLOCK && p.ops[i].gslot >= 0) sw.gslots.push_back(p.ops[i].gslot);
     p.sweeps.push_back(sw);
   }
+  if (p.sweeps.empty()) {
+    // a circuit without gates still needs one sweep: it writes |0...0> and
+    // reads the observables
+    Sweep sw;
+    for (int q = 0; q < kt; ++q) sw.tile.push_back(q);
+    p.sweeps.push_back(sw);
+  }
+  for (Sweep &sw : p.sweeps)
+    if (sw.stages.empty()) {
+      Stage st;
+      for (int r = 0; r < kRegBits; ++r) st.regpos[r] = r;
+      sw.stages.push_back(st);
+    }
   return p;
 }
 
@@ -425,13 +440,21 @@ static uint32_t pdep_bits(uint32_t v, const int *pos, int npos) {
 static int parity32(uint32_t v) { return __builtin_popcount(v) & 1; }
 
 static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, bool backward,
-                         std::vector<int32_t> &code, std::vector<int32_t> &sweep_offs,
-                         int32_t &max_gs) {
+                         std::vector<int32_t> &code, std::vector<int32_t> &thr,
+                         std::vector<int32_t> &sweep_offs, int32_t &max_gs) {
   const int kt = p.kt, nthr_bits = kt - kRegBits;
   const int off = (int)code.size();
   sweep_offs.push_back(off);
   const int nst = (int)sw.stages.size();
-  int hdr = kSwStages + nst + (int)sw.gslots.size();
+  // sweep-local matrix slots: blocks in order of first use
+  std::vector<int> mslots, mslot_of(p.n_blocks, -1);
+  for (const Stage &st : sw.stages)
+    for (int oi : st.ops)
+      if (p.ops[oi].kind == FK_BLOCK && mslot_of[p.ops[oi].block] < 0) {
+        mslot_of[p.ops[oi].block] = (int)mslots.size();
+        mslots.push_back(p.ops[oi].block);
+      }
+  int hdr = kSwStages + nst + (int)sw.gslots.size() + (int)mslots.size();
   code.resize(off + hdr, 0);
   int32_t *H = nullptr;
   auto h = [&](int i) -> int32_t & { return code[off + i]; };
@@ -444,6 +467,7 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
   h(0) = nst;
   h(1) = (int)outer.size();
   h(2) = (int)sw.gslots.size();
+  h(3) = (int)mslots.size();
   max_gs = std::max(max_gs, (int)sw.gslots.size());
   for (size_t i = 0; i < outer.size(); ++i) h(kSwOuter + i) = outer[i];
   for (int k = 0; k < kt; ++k) h(kSwTile + k) = sw.tile[k];
@@ -460,6 +484,8 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
     local_gs[sw.gslots[i]] = (int)i;
     h(kSwStages + nst + (int)i) = sw.gslots[i];
   }
+  for (size_t i = 0; i < mslots.size(); ++i)
+    h(kSwStages + nst + (int)sw.gslots.size() + (int)i) = mslots[i];
   for (int si = 0; si < nst; ++si) {
     const Stage &st = sw.stages[backward ? nst - 1 - si : si];
     h(kSwStages + si) = (int32_t)code.size();
@@ -476,19 +502,24 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
       sh(kStGlob + j) = (int32_t)W[j];
     }
     std::vector<char> isreg(kt, 0);
-    for (int r = 0; r < kRegBits; ++r) isreg[rp[r]] = 1;
-    int ti = 0;
+    for (int r = 0; r < kRegBits; ++r) {
+      isreg[rp[r]] = 1;
+      sh(kStRegPos + r) = rp[r];
+    }
+    std::vector<int> tpos;  // local positions of the thread bits, ascending
     for (int k = 0; k < kt; ++k)
-      if (!isreg[k]) {
-        sh(kStTbLocal + ti) = k;
-        sh(kStTbGlob + ti) = sw.tile[k];
-        ++ti;
-      }
+      if (!isreg[k]) tpos.push_back(k);
+    sh(kStThr) = (int32_t)thr.size();
+    for (uint32_t t = 0; t < (1u << nthr_bits); ++t) {
+      uint32_t lt = pdep_bits(t, tpos.data(), nthr_bits);
+      thr.push_back((int32_t)pdep_bits(lt, sw.tile.data(), kt));
+    }
     // ops: CZs merged into one diag op at the position of the first CZ of a run
     std::vector<int> ops = st.ops;
     if (backward) std::reverse(ops.begin(), ops.end());
     std::vector<std::vector<int32_t>> enc;
     std::vector<std::vector<int32_t>> diag_recs;
+    int32_t stage_flags = 0;
     std::vector<std::pair<int, int>> czrun;
     auto flush_cz = [&]() {
       if (czrun.empty()) return;
@@ -511,20 +542,26 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
         rec.push_back(g.first);
         rec.push_back((int32_t)g.second);
       }
-      uint32_t cbits = 0;
-      for (int j = 0; j < kRegs; ++j) {
-        uint32_t Cj = 0;
-        int q = 0;
+      if (!groups.empty()) stage_flags |= 1;
+      // linear term of register bit b: C(W_{e_b}) restricted to non-register bits
+      uint32_t regmask = W[kRegs - 1];
+      for (int b = 0; b < kRegBits; ++b) {
+        const uint32_t Wb = W[1 << b];
+        uint32_t Cb = 0;
         for (auto &pr : czrun) {
-          int a = pr.first, b = pr.second;
-          if ((W[j] >> b) & 1u) Cj ^= 1u << a;
-          if ((W[j] >> a) & 1u) Cj ^= 1u << b;
-          q ^= (int)(((W[j] >> a) & (W[j] >> b)) & 1u);
+          int a = pr.first, d = pr.second;
+          if ((Wb >> d) & 1u) Cb ^= 1u << a;
+          if ((Wb >> a) & 1u) Cb ^= 1u << d;
         }
-        rec.push_back((int32_t)Cj);
-        if (q) cbits |= 1u << j;
+        rec.push_back((int32_t)(Cb & ~regmask));
       }
-      rec.push_back((int32_t)cbits);
+      uint32_t qmask = 0;
+      for (int j = 0; j < kRegs; ++j) {
+        int q = 0;
+        for (auto &pr : czrun) q ^= (int)(((W[j] >> pr.first) & (W[j] >> pr.second)) & 1u);
+        if (q) qmask |= 1u << j;
+      }
+      rec.push_back((int32_t)qmask);
       enc.push_back({OP_DIAG, (int32_t)diag_recs.size(), 0, 0});
       diag_recs.push_back(rec);
       czrun.clear();
@@ -542,7 +579,7 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
       flush_cz();
       if (o.kind == FK_BLOCK) {
         int r = regbit_of[loc[o.q0]];
-        enc.push_back({OP_U1, r, o.block, o.gslot >= 0 ? local_gs[o.gslot] : -1});
+        enc.push_back({OP_U1, r, mslot_of[o.block], o.gslot >= 0 ? local_gs[o.gslot] : -1});
       } else {
         int r = regbit_of[loc[o.q1]];
         int lc = loc[o.q0];
@@ -554,6 +591,7 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
     }
     flush_cz();
     sh(0) = (int32_t)enc.size();
+    sh(kStFlags) = stage_flags;
     int ops_off = (int)code.size();
     code.resize(ops_off + 4 * enc.size(), 0);
     for (size_t e = 0; e < enc.size(); ++e)
@@ -572,9 +610,9 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
 Program encode_program(const CircuitDesc &c, const Plan &p) {
   Program pr;
   for (const Sweep &sw : p.sweeps)
-    encode_sweep(c, p, sw, false, pr.code, pr.sweep_off_fwd, pr.max_gslots_per_sweep);
+    encode_sweep(c, p, sw, false, pr.code, pr.thr, pr.sweep_off_fwd, pr.max_gslots_per_sweep);
   for (int s = (int)p.sweeps.size() - 1; s >= 0; --s)
-    encode_sweep(c, p, p.sweeps[s], true, pr.code, pr.sweep_off_bwd, pr.max_gslots_per_sweep);
+    encode_sweep(c, p, p.sweeps[s], true, pr.code, pr.thr, pr.sweep_off_bwd, pr.max_gslots_per_sweep);
   return pr;
 }
 

@@ -237,6 +237,37 @@ __device__ __forceinline__ void u1_mfma(Cx<float> (*const *vs)[kRegs], int p, co
   }
 }
 
+// Backward block on register bit P: transition-matrix components of the
+// states after the block, then the adjoint applied to psi and lambda.
+template <int P>
+__device__ __forceinline__ void bwd_u1_mfma_bit(Cx<float> (&v)[kRegs], Cx<float> (&l)[kRegs],
+                                                const MCols &A, float &tx, float &ty, float &tz) {
+  tx = ty = tz = 0.f;
+#pragma unroll
+  for (int j = 0; j < kRegs; ++j)
+    if (!(j & (1 << P))) {
+      const Cx<float> p0 = v[j], p1 = v[j | (1 << P)], l0 = l[j], l1 = l[j | (1 << P)];
+      tx += p0.y * l1.x - p0.x * l1.y + p1.y * l0.x - p1.x * l0.y;
+      ty += p0.x * l1.x + p0.y * l1.y - p1.x * l0.x - p1.y * l0.y;
+      tz += p0.y * l0.x - p0.x * l0.y - p1.y * l1.x + p1.x * l1.y;
+    }
+  Cx<float>(*const vs[2])[kRegs] = {&v, &l};
+  u1_mfma_bit<P, 2>(vs, A);
+}
+
+__device__ __forceinline__ void bwd_u1_mfma(Cx<float> (&v)[kRegs], Cx<float> (&l)[kRegs], int p,
+                                            const M2<float> &m, int row, float &tx, float &ty,
+                                            float &tz) {
+  const MCols A = mfma_cols(Cx<float>{m.a.x, -m.a.y}, Cx<float>{m.c.x, -m.c.y},
+                            Cx<float>{m.b.x, -m.b.y}, Cx<float>{m.d.x, -m.d.y}, row);
+  switch (p) {
+    case 0: bwd_u1_mfma_bit<0>(v, l, A, tx, ty, tz); break;
+    case 1: bwd_u1_mfma_bit<1>(v, l, A, tx, ty, tz); break;
+    case 2: bwd_u1_mfma_bit<2>(v, l, A, tx, ty, tz); break;
+    default: bwd_u1_mfma_bit<3>(v, l, A, tx, ty, tz); break;
+  }
+}
+
 // CNOT with target register bit P and control register bit C
 template <typename R, int P, int C>
 __device__ __forceinline__ void cnot_rr(Cx<R> (&v)[kRegs]) {
@@ -288,23 +319,75 @@ __device__ __forceinline__ void cnot_op(Cx<R> (&v)[kRegs], int p, int kind, int 
   }
 }
 
-// Diagonal op: sign(x) for x = gt | W_j from the diag record.
-__device__ __forceinline__ uint32_t diag_signs(cptr<int32_t> rec, uint32_t gt) {
-  const int ng = rec[0];
-  uint32_t q = 0;
-  for (int g = 0; g < ng; ++g) q += __popc(gt & (gt >> rec[1 + 2 * g]) & (uint32_t)rec[2 + 2 * g]);
-  cptr<int32_t> C = rec + 1 + 2 * ng;
-  uint32_t cb = (uint32_t)C[kRegs];
-  uint32_t bits = 0;
-#pragma unroll
-  for (int j = 0; j < kRegs; ++j) bits |= ((__popc(gt & (uint32_t)C[j]) + q + (cb >> j)) & 1u) << j;
-  return bits;
+// Sign flips: xor of the IEEE sign bit with `sgn` (0 or 0x80000000).
+__device__ __forceinline__ float flip(float x, uint32_t sgn) {
+  return __uint_as_float(__float_as_uint(x) ^ sgn);
 }
-template <typename R>
-__device__ __forceinline__ void apply_signs(Cx<R> (&v)[kRegs], uint32_t bits) {
+__device__ __forceinline__ double flip(double x, uint32_t sgn) {
+  return __longlong_as_double(__double_as_longlong(x) ^ ((unsigned long long)sgn << 32));
+}
+
+// Tile-local index of a thread's register-0 amplitude in a stage: the thread
+// id with a zero bit inserted at each of the 4 register positions.
+__device__ __forceinline__ uint32_t stage_local_index(uint32_t t, cptr<int32_t> S) {
+  uint32_t x = t;
+#pragma unroll
+  for (int r = 0; r < kRegBits; ++r) {
+    const uint32_t low = (1u << S[kStRegPos + r]) - 1u;
+    x = ((x & ~low) << 1) | (x & low);
+  }
+  return x;
+}
+
+// Diagonal op (a run of CZ gates): sign (-1)^Q(x) with x = gt | W_j.  The
+// per-thread part Q(gt) is the same for all 16 registers, so it commutes with
+// every op of the stage: it is accumulated in `tsg` and applied once when the
+// stage ends.  The part linear in the register bits flips the registers with
+// bit b set when parity(gt & C_b) = 1; the part depending only on j is a
+// uniform mask.
+template <typename R, int NS>
+__device__ __forceinline__ void diag_apply(Cx<R> (*const *vs)[kRegs], cptr<int32_t> rec,
+                                           uint32_t gt, uint32_t &tsg) {
+  const int ng = rec[0];
+  for (int g = 0; g < ng; ++g)
+    tsg += __popc(gt & (gt >> rec[1 + 2 * g]) & (uint32_t)rec[2 + 2 * g]);
+  const cptr<int32_t> L = rec + 1 + 2 * ng;
+#pragma unroll
+  for (int b = 0; b < kRegBits; ++b) {
+    const uint32_t Cb = (uint32_t)L[b];
+    if (Cb) {
+      const uint32_t sgn = (__popc(gt & Cb) & 1u) << 31;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j)
+          if (j & (1 << b)) {
+            Cx<R> &z = (*vs[s])[j];
+            z = Cx<R>{flip(z.x, sgn), flip(z.y, sgn)};
+          }
+    }
+  }
+  const uint32_t qm = (uint32_t)L[kRegBits];
 #pragma unroll
   for (int j = 0; j < kRegs; ++j)
-    if ((bits >> j) & 1u) v[j] = Cx<R>{-v[j].x, -v[j].y};
+    if ((qm >> j) & 1u)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        Cx<R> &z = (*vs[s])[j];
+        z = Cx<R>{-z.x, -z.y};
+      }
+}
+
+template <typename R, int NS>
+__device__ __forceinline__ void apply_thread_sign(Cx<R> (*const *vs)[kRegs], uint32_t tsg) {
+  const uint32_t sgn = (tsg & 1u) << 31;
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {
+      Cx<R> &z = (*vs[s])[j];
+      z = Cx<R>{flip(z.x, sgn), flip(z.y, sgn)};
+    }
 }
 
 // Transition-matrix components for register bit P over the thread's pairs:
@@ -337,6 +420,7 @@ __device__ __forceinline__ void tcomp(const Cx<R> (&v)[kRegs], const Cx<R> (&l)[
 
 struct FwdArgs {
   const int32_t *prog;
+  const int32_t *thr;
   int sweep_off;
   int n;
   void *state;
@@ -359,14 +443,21 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
   constexpr bool kMfma = std::is_same<R, float>::value && NT >= 64;
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<R> *lds = reinterpret_cast<Cx<R> *>(smem);
-  double *obs_acc = reinterpret_cast<double *>(smem + (sizeof(Cx<R>) << KT));
+  M2<R> *lds_m = reinterpret_cast<M2<R> *>(smem + (sizeof(Cx<R>) << KT));
+  double *obs_acc = reinterpret_cast<double *>(lds_m + kMaxSweepBlocks);
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int b = blockIdx.y;
   const cptr<int32_t> prog = as_const(a.prog);
   const cptr<int32_t> H = prog + a.sweep_off;
-  const int nst = H[0], nout = H[1];
+  const int nst = H[0], nout = H[1], nmat = H[3];
   Cx<R> *__restrict__ st = reinterpret_cast<Cx<R> *>(a.state) + ((int64_t)b << a.n);
-  const cptr<M2<R>> mats = as_const(reinterpret_cast<const M2<R> *>(a.mats)) + (int64_t)b * a.n_blocks;
+  {
+    // stage this sweep's gate matrices of sample b in LDS
+    const cptr<int32_t> mlist = H + kSwStages + nst + H[2];
+    const R *__restrict__ src = reinterpret_cast<const R *>(a.mats) + (int64_t)b * a.n_blocks * 8;
+    R *dst = reinterpret_cast<R *>(lds_m);
+    for (int i = t; i < nmat * 8; i += NT) dst[i] = src[mlist[i >> 3] * 8 + (i & 7)];
+  }
   uint32_t gload = 0;
 #pragma unroll
   for (int i = 0; i < KT - kRegBits; ++i)
@@ -391,15 +482,11 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
     for (int j = 0; j < kRegs; ++j) lds[lload ^ (uint32_t)H[kSwLoadL + j]] = v[j];
     for (int s = 0; s < nst; ++s) {
       const cptr<int32_t> S = prog + H[kSwStages + s];
+      const uint32_t gt = tbase | (uint32_t)a.thr[S[kStThr] + t];
+      const uint32_t lsw = lds_swizzle(stage_local_index((uint32_t)t, S));
+      uint32_t tsg = 0;
+      Cx<R>(*const vs[1])[kRegs] = {&v};
       __syncthreads();
-      uint32_t lt = 0, gt = tbase;
-#pragma unroll
-      for (int i = 0; i < KT - kRegBits; ++i)
-        if ((t >> i) & 1) {
-          lt |= 1u << S[kStTbLocal + i];
-          gt |= 1u << S[kStTbGlob + i];
-        }
-      const uint32_t lsw = lds_swizzle(lt);
 #pragma unroll
       for (int j = 0; j < kRegs; ++j) v[j] = lds[lsw ^ (uint32_t)S[kStLds + j]];
       const int nops = S[0];
@@ -407,9 +494,8 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
         const cptr<int32_t> op = S + kStOps + 4 * o;
         const int code = op[0];
         if (code == OP_U1) {
-          const M2<R> m = load_m2<R>(mats + op[2]);
+          const M2<R> m = lds_m[op[2]];
           if constexpr (kMfma) {
-            Cx<float>(*const vs[1])[kRegs] = {&v};
             u1_mfma<1>(vs, op[1], m, false, lane & 3);
           } else {
             u1<R>(v, op[1], m);
@@ -417,9 +503,10 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
         } else if (code == OP_CNOT) {
           cnot_op<R>(v, op[1], op[2], op[3], gt);
         } else {
-          apply_signs<R>(v, diag_signs(prog + op[1], gt));
+          diag_apply<R, 1>(vs, prog + op[1], gt, tsg);
         }
       }
+      if (S[kStFlags] & 1) apply_thread_sign<R, 1>(vs, tsg);
       if (a.last && s == nst - 1) {
         // per-thread partials in the state's precision, FP64 across lanes
         R p[kRegs];
@@ -463,6 +550,7 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
 
 struct BwdArgs {
   const int32_t *prog;
+  const int32_t *thr;
   int sweep_off;
   int n;
   void *psi;
@@ -489,22 +577,28 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<R> *lds_p = reinterpret_cast<Cx<R> *>(smem);
   Cx<R> *lds_l = lds_p + (1 << KT);
-  double *gacc = reinterpret_cast<double *>(smem + (2 * sizeof(Cx<R>) << KT));
+  M2<R> *lds_m = reinterpret_cast<M2<R> *>(smem + (2 * sizeof(Cx<R>) << KT));
+  double *nacc = reinterpret_cast<double *>(lds_m + kMaxSweepBlocks);  // [NW]
+  double *gacc = nacc + NW;  // [ngs][3][NW] per-wave gradient accumulators
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int b = blockIdx.y;
   const cptr<int32_t> prog = as_const(a.prog);
   const cptr<int32_t> H = prog + a.sweep_off;
-  const int nst = H[0], nout = H[1], ngs = H[2];
+  const int nst = H[0], nout = H[1], ngs = H[2], nmat = H[3];
   Cx<R> *__restrict__ ps = reinterpret_cast<Cx<R> *>(a.psi) + ((int64_t)b << a.n);
   Cx<R> *__restrict__ ls = reinterpret_cast<Cx<R> *>(a.lam) + ((int64_t)b << a.n);
-  const cptr<M2<R>> mats = as_const(reinterpret_cast<const M2<R> *>(a.mats)) + (int64_t)b * a.n_blocks;
+  {
+    const cptr<int32_t> mlist = H + kSwStages + nst + ngs;
+    const R *__restrict__ src = reinterpret_cast<const R *>(a.mats) + (int64_t)b * a.n_blocks * 8;
+    R *dst = reinterpret_cast<R *>(lds_m);
+    for (int i = t; i < nmat * 8; i += NT) dst[i] = src[mlist[i >> 3] * 8 + (i & 7)];
+  }
   uint32_t gload = 0;
 #pragma unroll
   for (int i = 0; i < KT - kRegBits; ++i)
     if ((t >> i) & 1) gload |= 1u << H[kSwLoadTb + i];
   const uint32_t lload = lds_swizzle((uint32_t)t);
-  for (int i = t; i < ngs * 3 * NW + NW; i += NT) gacc[i] = 0.0;
-  double *nacc = gacc + ngs * 3 * NW;
+  for (int i = t; i < NW + ngs * 3 * NW; i += NT) nacc[i] = 0.0;
   Cx<R> v[kRegs], l[kRegs];
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     uint32_t tbase = 0;
@@ -544,15 +638,11 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
     }
     for (int s = 0; s < nst; ++s) {
       const cptr<int32_t> S = prog + H[kSwStages + s];
+      const uint32_t gt = tbase | (uint32_t)a.thr[S[kStThr] + t];
+      const uint32_t lsw = lds_swizzle(stage_local_index((uint32_t)t, S));
+      uint32_t tsg = 0;
+      Cx<R>(*const vs[2])[kRegs] = {&v, &l};
       __syncthreads();
-      uint32_t lt = 0, gt = tbase;
-#pragma unroll
-      for (int i = 0; i < KT - kRegBits; ++i)
-        if ((t >> i) & 1) {
-          lt |= 1u << S[kStTbLocal + i];
-          gt |= 1u << S[kStTbGlob + i];
-        }
-      const uint32_t lsw = lds_swizzle(lt);
 #pragma unroll
       for (int j = 0; j < kRegs; ++j) {
         v[j] = lds_p[lsw ^ (uint32_t)S[kStLds + j]];
@@ -563,31 +653,34 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
         const cptr<int32_t> op = S + kStOps + 4 * o;
         const int code = op[0];
         if (code == OP_U1) {
-          const M2<R> m = load_m2<R>(mats + op[2]);
-          if (op[3] >= 0) {
-            R tx = 0, ty = 0, tz = 0;
-            tcomp<R>(v, l, op[1], tx, ty, tz);
-            R fx, fy, fz;
-            if constexpr (kMfma) {
-              fx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(tx)), 63));
-              fy = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(ty)), 63));
-              fz = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(tz)), 63));
-            } else {
-              fx = wave_sum_w<WS>(tx);
-              fy = wave_sum_w<WS>(ty);
-              fz = wave_sum_w<WS>(tz);
-            }
-            if (lane == 0) {
-              double *g = gacc + op[3] * 3 * NW;
+          const M2<R> m = lds_m[op[2]];
+          const int gs = op[3];
+          if constexpr (kMfma) {
+            // transition-matrix FMAs (VALU) and the un-apply (MFMA) read the
+            // same registers and sit in one basic block, so they co-issue
+            float tx, ty, tz;
+            bwd_u1_mfma(v, l, op[1], m, lane & 3, tx, ty, tz);
+            const float fx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(tx)), 63));
+            const float fy = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(ty)), 63));
+            const float fz = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(tz)), 63));
+            if (lane == 0 && gs >= 0) {
+              double *g = gacc + gs * 3 * NW;
               g[wave] += (double)fx;
               g[NW + wave] += (double)fy;
               g[2 * NW + wave] += (double)fz;
             }
-          }
-          if constexpr (kMfma) {
-            Cx<float>(*const vs[2])[kRegs] = {&v, &l};
-            u1_mfma<2>(vs, op[1], m, true, lane & 3);
           } else {
+            if (gs >= 0) {
+              R tx = 0, ty = 0, tz = 0;
+              tcomp<R>(v, l, op[1], tx, ty, tz);
+              const R fx = wave_sum_w<WS>(tx), fy = wave_sum_w<WS>(ty), fz = wave_sum_w<WS>(tz);
+              if (lane == 0) {
+                double *g = gacc + gs * 3 * NW;
+                g[wave] += (double)fx;
+                g[NW + wave] += (double)fy;
+                g[2 * NW + wave] += (double)fz;
+              }
+            }
             u1_adj<R>(v, op[1], m);
             u1_adj<R>(l, op[1], m);
           }
@@ -595,11 +688,10 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
           cnot_op<R>(v, op[1], op[2], op[3], gt);
           cnot_op<R>(l, op[1], op[2], op[3], gt);
         } else {
-          const uint32_t bits = diag_signs(prog + op[1], gt);
-          apply_signs<R>(v, bits);
-          apply_signs<R>(l, bits);
+          diag_apply<R, 2>(vs, prog + op[1], gt, tsg);
         }
       }
+      if (S[kStFlags] & 1) apply_thread_sign<R, 2>(vs, tsg);
 #pragma unroll
       for (int j = 0; j < kRegs; ++j) {
         lds_p[lsw ^ (uint32_t)S[kStLds + j]] = v[j];
@@ -662,12 +754,14 @@ __global__ void k_fused_grad_occ(const double *__restrict__ part, const double *
 template <typename R, int KT>
 static size_t fwd_lds(int M) {
   constexpr int NW = ((1 << (KT - kRegBits)) + 63) / 64;
-  return (sizeof(Cx<R>) << KT) + sizeof(double) * (size_t)(M + 1) * NW;
+  return (sizeof(Cx<R>) << KT) + sizeof(M2<R>) * kMaxSweepBlocks + sizeof(double) * (size_t)(M + 1) * NW;
 }
 template <typename R, int KT>
 static size_t bwd_lds(int ngs) {
-  constexpr int NW = ((1 << (KT - kRegBits)) + 63) / 64;
-  return (2 * sizeof(Cx<R>) << KT) + sizeof(double) * ((size_t)ngs * 3 * NW + NW);
+  constexpr int NT = 1 << (KT - kRegBits);
+  constexpr int NW = (NT + 63) / 64;
+  const size_t acc = (size_t)ngs * 3 * NW;
+  return (2 * sizeof(Cx<R>) << KT) + sizeof(M2<R>) * kMaxSweepBlocks + sizeof(double) * (NW + acc);
 }
 
 template <typename K>
@@ -687,6 +781,7 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *ma
   for (int sw = 0; sw < p.n_sweeps; ++sw) {
     FwdArgs a;
     a.prog = p.code;
+    a.thr = p.thr;
     a.sweep_off = p.sweep_off_fwd[sw];
     a.n = d.n;
     a.state = state;
@@ -718,6 +813,7 @@ static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const do
   for (int sw = 0; sw < p.n_sweeps; ++sw) {
     BwdArgs a;
     a.prog = p.code;
+    a.thr = p.thr;
     a.sweep_off = p.sweep_off_bwd[sw];
     a.n = d.n;
     a.psi = psi;

@@ -29,6 +29,7 @@ struct DevPlan {
   int n_sweeps = 0;
   std::vector<int32_t> sweep_off_fwd, sweep_off_bwd;
   int32_t *code = nullptr;      // program
+  int32_t *thr = nullptr;       // per-stage per-thread global offsets
   int32_t *blk = nullptr;       // block records for the matrix prep
   int32_t *blk_off = nullptr;   // block -> offset in blk
   int32_t *occ_gslot = nullptr; // occurrence -> gradient slot

@@ -9,21 +9,35 @@ import workloads as W
 
 KREG = 4
 SW_OUTER, SW_TILE, SW_LOADG, SW_LOADL, SW_LOADTB, SW_STAGES = 4, 34, 46, 62, 78, 90
-ST_LDS, ST_GLOB, ST_TBL, ST_TBG, ST_OPS = 4, 20, 36, 48, 60
+ST_FLAGS, ST_THR, ST_LDS, ST_GLOB, ST_REGPOS, ST_OPS = 1, 2, 4, 20, 36, 40
 
 
 def swz(i):
     return i ^ ((i >> 5) & 31) ^ ((i >> 10) & 31)
 
 
-def check_program(plan, n):
+def insert_zeros(t, regpos):
+    x = t.copy()
+    for r in regpos:
+        low = (1 << int(r)) - 1
+        x = ((x & ~low) << 1) | (x & low)
+    return x
+
+
+def parity(v):
+    return np.array([bin(int(a)).count("1") & 1 for a in np.ravel(v)]).reshape(np.shape(v))
+
+
+def check_program(plan, n, circ=None):
     code = np.array(plan["code"], dtype=np.int64)
+    thr = np.array(plan["thr"], dtype=np.int64)
     kt = plan["kt"]
     nt = 1 << (kt - KREG)
     t = np.arange(nt)
-    for offs in (plan["sweep_off_fwd"], plan["sweep_off_bwd"]):
+    rng = np.random.default_rng(0)
+    for direction, offs in (("fwd", plan["sweep_off_fwd"]), ("bwd", plan["sweep_off_bwd"])):
         assert len(offs) == len(plan["sweeps"])
-        for off in offs:
+        for si, off in enumerate(offs):
             H = code[off:]
             nst, nout = int(H[0]), int(H[1])
             assert nout == n - kt
@@ -42,37 +56,34 @@ def check_program(plan, n):
             lload = swz(t)[:, None] ^ H[SW_LOADL:SW_LOADL + 16][None, :]
             assert lload.max() < (1 << kt)
             assert len(np.unique(lload)) == 1 << kt
-            # the load layout and its LDS slot describe the same local index:
-            # local index t + nt*j, whose global image is gload | loadG_j
+            tile_pos = H[SW_TILE:SW_TILE + kt]
+            local_of = {}
+            for tt in range(nt):
+                for j in range(16):
+                    local = tt + nt * j
+                    g = 0
+                    for k in range(kt):
+                        if (local >> k) & 1:
+                            g |= 1 << int(tile_pos[k])
+                    local_of[swz(local)] = g
+            sweep = plan["sweeps"][si if direction == "fwd" else len(offs) - 1 - si]
             for s in range(nst):
                 S = code[int(H[SW_STAGES + s]):]
-                lt = np.zeros_like(t)
-                gt = np.zeros_like(t)
-                for i in range(kt - KREG):
-                    lt |= ((t >> i) & 1) << int(S[ST_TBL + i])
-                    gt |= ((t >> i) & 1) << int(S[ST_TBG + i])
+                regpos = S[ST_REGPOS:ST_REGPOS + 4]
+                assert list(regpos) == sorted(regpos) and len(set(regpos)) == 4
+                lt = insert_zeros(t, regpos)
+                gt = thr[int(S[ST_THR]):int(S[ST_THR]) + nt]
                 lidx = swz(lt)[:, None] ^ S[ST_LDS:ST_LDS + 16][None, :]
                 assert lidx.max() < (1 << kt)
                 assert len(np.unique(lidx)) == 1 << kt, "stage LDS slots not a permutation"
                 gidx = gt[:, None] | S[ST_GLOB:ST_GLOB + 16][None, :]
                 assert len(np.unique(gidx)) == 1 << kt
                 assert np.all((gt[:, None] & S[ST_GLOB:ST_GLOB + 16][None, :]) == 0)
-                # consistency: slot lidx holds the amplitude whose tile-local
-                # index maps to gidx; compare against the load layout's map
-                tile_pos = H[SW_TILE:SW_TILE + kt]
-                local_of = {}
-                for tt in range(nt):
-                    for j in range(16):
-                        local = tt + nt * j
-                        g = 0
-                        for k in range(kt):
-                            if (local >> k) & 1:
-                                g |= 1 << int(tile_pos[k])
-                        local_of[swz(local)] = g
                 for tt in range(nt):
                     for j in range(16):
                         assert local_of[int(lidx[tt, j])] == int(gidx[tt, j])
                 nops = int(S[0])
+                diag_recs = []
                 for o in range(nops):
                     op = S[ST_OPS + 4 * o: ST_OPS + 4 * o + 4]
                     assert op[0] in (1, 2, 3)
@@ -82,9 +93,45 @@ def check_program(plan, n):
                         assert 0 <= op[1] < 4 and op[2] in (0, 1)
                         assert (0 <= op[3] < 4 and op[3] != op[1]) if op[2] == 0 else 0 <= op[3] < n
                     else:
-                        rec = code[int(op[1]):]
-                        ng = int(rec[0])
-                        assert 0 <= ng <= n
+                        diag_recs.append(code[int(op[1]):])
+                if circ is None or not diag_recs:
+                    continue
+                # CZ runs of this stage (forward order) -> diag records
+                st_gates = sweep["stages"][s if direction == "fwd" else nst - 1 - s]["gates"]
+                runs, cur = [], []
+                for g in st_gates:
+                    if circ.gates[g][0] == 4:
+                        cur.append((int(circ.gates[g][1]), int(circ.gates[g][2])))
+                    elif cur:
+                        runs.append(cur)
+                        cur = []
+                if cur:
+                    runs.append(cur)
+                if direction == "bwd":
+                    runs = [list(r) for r in reversed(runs)]
+                assert len(runs) == len(diag_recs)
+                W = S[ST_GLOB:ST_GLOB + 16]
+                for pairs, rec in zip(runs, diag_recs):
+                    ng = int(rec[0])
+                    C = rec[1 + 2 * ng:1 + 2 * ng + 4]
+                    qm = int(rec[1 + 2 * ng + 4])
+                    for tb in rng.choice(tbase, size=min(3, len(tbase)), replace=False):
+                        G = tb | gt
+                        qg = np.zeros(nt, dtype=np.int64)
+                        for g in range(ng):
+                            d, m = int(rec[1 + 2 * g]), int(rec[2 + 2 * g])
+                            qg ^= parity(G & (G >> d) & m)
+                        for j in range(16):
+                            x = G | W[j]
+                            direct = np.zeros(nt, dtype=np.int64)
+                            for a, b in pairs:
+                                direct ^= ((x >> a) & (x >> b)) & 1
+                            lin = np.zeros(nt, dtype=np.int64)
+                            for b in range(4):
+                                if (j >> b) & 1:
+                                    lin ^= parity(G & int(C[b]))
+                            rec_sign = qg ^ lin ^ ((qm >> j) & 1)
+                            assert np.array_equal(direct, rec_sign), "diag sign decomposition"
 
 
 @pytest.mark.parametrize("name,tile,klo", [("c1", 0, 0), ("c2", 0, 0), ("c3", 0, 0),
@@ -99,7 +146,7 @@ def test_program_layout_configs(name, tile, klo):
         c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
     if name == "c5":
         pytest.skip("n = 26 emulation is too large for the CPU suite; covered by c3 layouts")
-    check_program(c.plan("c64"), wl.circuit.n)
+    check_program(c.plan("c64"), wl.circuit.n, wl.circuit)
 
 
 @pytest.mark.parametrize("n,L,ent,tile,klo", [(6, 2, "ring", 4, 2), (9, 3, "ladder", 5, 3),
@@ -107,10 +154,11 @@ def test_program_layout_configs(name, tile, klo):
                                               (14, 3, "ladder", 8, 5), (11, 4, "ring", 7, 6)])
 def test_program_layout_small(n, L, ent, tile, klo):
     import paper_2404_06314_amd as q
-    c = q.Circuit.from_workload(W.layered_circuit(n, L, ent))
+    c_w = W.layered_circuit(n, L, ent)
+    c = q.Circuit.from_workload(c_w)
     c.set_option(q.QTM_OPT_TILE_QUBITS, tile)
     c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
-    check_program(c.plan("c64"), n)
+    check_program(c.plan("c64"), n, c_w)
 
 
 def test_program_layout_random():
@@ -122,4 +170,15 @@ def test_program_layout_random():
         if n > 4:
             c.set_option(q.QTM_OPT_TILE_QUBITS, 4)
         c.set_option(q.QTM_OPT_LOW_QUBITS, 2)
-        check_program(c.plan("c64"), n)
+        check_program(c.plan("c64"), n, circ)
+
+
+def test_program_layout_empty_circuit():
+    """A circuit without gates still gets one sweep with one stage (it must
+    write |0...0> and read the observables)."""
+    import paper_2404_06314_amd as q
+    circ = W.Circuit(n=6, gates=np.zeros((0, 5), np.int32), n_inputs=0, n_weights=0,
+                     masks=W.z_masks(6))
+    plan = q.Circuit.from_workload(circ).plan("c64")
+    assert len(plan["sweeps"]) == 1 and len(plan["sweeps"][0]["stages"]) == 1
+    check_program(plan, 6, circ)
