@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "circuit evals/s (fwd+adjoint grad) n=20 depth 8 batch 64; % peak HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+MFMA_F32_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -39,6 +40,19 @@ def sweep_bytes(n_sweeps: int, kind: int) -> int:
     if n_sweeps == 1:
         return 1
     return 3 + 4 * (n_sweeps - 2) + 2
+
+
+def block_ops(plan) -> int:
+    """Number of fused single-qubit blocks (U1 ops) in the encoded program."""
+    code = plan["code"]
+    n = 0
+    for off in plan["sweep_off_fwd"]:
+        nst = code[off]
+        for s in range(nst):
+            so = code[off + 90 + s]
+            nops = code[so]
+            n += sum(1 for o in range(nops) if code[so + 40 + 4 * o] == 1)
+    return n
 
 
 def cpu_baseline(wl, threads: int, samples: int):
@@ -137,15 +151,30 @@ def main():
         bytes_per_step = B * (1 << circ.n) * elem * sweep_bytes(S, kind)
         per_launch_bytes = bytes_per_step / S
         avg_s = ms_tot / launches / 1e3
-        achieved = per_launch_bytes / avg_s / 1e9
+        gbs = per_launch_bytes / avg_s / 1e9
+        # algorithmic matrix-core work: every fused block is a 2x2 complex
+        # gate on each of the B * 2^(n-1) pairs = 16 real MACs (32 flop) per
+        # pair, applied to psi in the forward and to psi and lambda in the
+        # backward
+        nblk = block_ops(plan)
+        flop_step = B * (1 << (circ.n - 1)) * nblk * 32 * (2 if kind == 1 else 1)
+        per_launch_flop = flop_step / S
+        tfs = per_launch_flop / avg_s / 1e12
         name = "k_fused_bwd" if kind == 1 else "k_fused_fwd"
         log(f"{name}: {launches} launches, avg {avg_s * 1e6:.1f} us, {per_launch_bytes / 1e6:.1f} MB "
-            f"per launch -> {achieved:.1f} GB/s; fwd sweeps {res[0][0] / args.steps:.3f} ms/step, "
+            f"and {per_launch_flop / 1e9:.1f} GFLOP per launch -> {gbs:.1f} GB/s, {tfs:.2f} TFLOP/s; "
+            f"fwd sweeps {res[0][0] / args.steps:.3f} ms/step, "
             f"bwd sweeps {res[1][0] / args.steps:.3f} ms/step ({S} sweeps)")
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        hbm = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        mfma = {"achieved": round(tfs, 3), "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfs / MFMA_F32_PEAK_TFLOPS, 4)}
+        use_mfma = prec == "c64" and mfma["frac"] > hbm["frac"]
+        main, other = (mfma, hbm) if use_mfma else (hbm, mfma)
+        roof = {"bound": "mfma" if use_mfma else "hbm", **main, "traffic": None,
                 "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
-                "bytes_per_launch": int(per_launch_bytes), "sweeps": S}
+                "bytes_per_launch": int(per_launch_bytes), "flop_per_launch": int(per_launch_flop),
+                "sweeps": S, ("hbm" if use_mfma else "mfma"): other}
 
     cpu = None
     if not args.no_cpu_baseline:

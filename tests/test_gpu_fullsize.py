@@ -1,0 +1,94 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration bench.py
+times, against oracle results written by tests/golden/make_oracle_fixtures.py
+(which calls only the oracle), plus the parameter-shift check of the n = 12
+configuration and properties that hold at any size."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import assert_grad_close, assert_parity, run_gpu
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def fixture(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} missing: run tests/golden/make_oracle_fixtures.py")
+    d = np.load(path, allow_pickle=False)
+    return d["expvals"], d["grad_w"], d["grad_x"]
+
+
+@pytest.mark.parametrize("precision,path", [("c64", None), ("c128", None), ("c128", 1)])
+def test_c3_full_batch(precision, path):
+    """n=20, 8 layers, CZ ladder, batch 64: every output against the oracle."""
+    wl = W.config_workload("c3")
+    ref = fixture("oracle_c3_b64.npz")
+    got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, precision, path)
+    assert_parity(got, ref, precision, f"c3 {precision} path={path}")
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_c5_two_samples(precision):
+    """n=26, 10 layers, CNOT ring: a 2-sample batch against the oracle."""
+    wl = W.config_workload("c5", batch=2)
+    ref = fixture("oracle_c5_b2.npz")
+    got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, precision)
+    assert_parity(got, ref, precision, f"c5 {precision}")
+
+
+def test_c5_full_batch_sampled_and_linear():
+    """n=26, batch 16 (complex64): the first two samples' outputs match the
+    oracle, and dL/dw of the batch equals the sum over two sub-batches."""
+    wl = W.config_workload("c5")
+    rev, rgw2, rgx = fixture("oracle_c5_b2.npz")
+    ev, gw, gx = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, "c64")
+    assert np.max(np.abs(ev[:2] - rev)) <= 1e-5
+    for b in range(2):
+        assert_grad_close(gx[b], rgx[b], 1e-4, f"c5 dL/dx[{b}]", 1e-6)
+    _, gwa, _ = run_gpu(wl.circuit, wl.inputs[:2], wl.weights, wl.grad_out[:2], "c64")
+    _, gwb, _ = run_gpu(wl.circuit, wl.inputs[2:], wl.weights, wl.grad_out[2:], "c64")
+    assert_grad_close(gwa, rgw2, 1e-4, "c5 dL/dw first two", 1e-6)
+    assert_grad_close(gw, gwa + gwb, 1e-5, "c5 dL/dw linearity", 1e-7)
+
+
+def test_c2_adjoint_vs_parameter_shift():
+    """n=12, 4 layers, ring: the autograd Function's gradient equals the
+    parameter-shift gradient, both on the GPU.  Every rotation occurrence gets
+    its own input slot; one batched forward evaluates all +-pi/2 shifts."""
+    import torch
+    import paper_2404_06314_amd as q
+    from paper_2404_06314_amd.autograd import QtmFunction
+    wl = W.config_workload("c2", batch=4)
+    c = q.Circuit.from_workload(wl.circuit)
+    x = torch.tensor(wl.inputs, device="cuda", requires_grad=True)
+    w = torch.tensor(wl.weights, device="cuda", requires_grad=True)
+    G = torch.tensor(wl.grad_out, device="cuda")
+    out = QtmFunction.apply(x, w, c, "c64")
+    (out * G).sum().backward()
+    gw_adj = w.grad.cpu().numpy()
+    gx_adj = x.grad.cpu().numpy()
+    gw_ps = np.zeros_like(gw_adj)
+    gx_ps = np.zeros_like(gx_adj)
+    for b in range(wl.batch):
+        cu, base, occ = W.untie_to_inputs(wl.circuit, wl.inputs[b], wl.weights)
+        qc = q.Circuit.from_workload(cu)
+        K = len(occ)
+        rows = np.repeat(base[None, :], 2 * K, axis=0)
+        rows[np.arange(K), np.arange(K)] += np.pi / 2
+        rows[K + np.arange(K), np.arange(K)] -= np.pi / 2
+        ev = qc.forward(torch.tensor(rows, device="cuda"),
+                        torch.zeros(1, dtype=torch.float64, device="cuda"), "c64").cpu().numpy()
+        d = (ev[:K] - ev[K:]) / 2 @ wl.grad_out[b]          # per occurrence
+        for k, gi in enumerate(occ):
+            t, q0, q1, src, idx = wl.circuit.gates[gi]
+            if src == W.SRC_WEIGHT:
+                gw_ps[idx] += d[k]
+            else:
+                gx_ps[b, idx] += d[k]
+    assert_grad_close(gw_adj, gw_ps, 1e-4, "c2 dL/dw adjoint vs shift", 1e-6)
+    for b in range(wl.batch):
+        assert_grad_close(gx_adj[b], gx_ps[b], 1e-4, f"c2 dL/dx[{b}] adjoint vs shift", 1e-6)

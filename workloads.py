@@ -200,3 +200,21 @@ def untie(circ: Circuit, x: np.ndarray, w: np.ndarray):
                 n_weights=len(occ), masks=circ.masks.copy(),
                 name=circ.name + "_untied")
     return c, np.array(vals, dtype=np.float64), occ
+
+
+def untie_to_inputs(circ: Circuit, x_b: np.ndarray, w: np.ndarray):
+    """Like `untie`, but every rotation occurrence k reads input slot k, so a
+    batch of rows can carry differently shifted angle vectors.  Returns
+    (circuit, base_row, occ) with base_row[k] the angle of occurrence k."""
+    g = circ.gates.copy()
+    vals, occ = [], []
+    for k in range(g.shape[0]):
+        t, q0, q1, src, idx = (int(v) for v in g[k])
+        if t in PARAM_TYPES:
+            vals.append(x_b[idx] if src == SRC_INPUT else w[idx])
+            g[k, 3] = SRC_INPUT
+            g[k, 4] = len(occ)
+            occ.append(k)
+    c = Circuit(n=circ.n, gates=g, n_inputs=len(occ), n_weights=0, masks=circ.masks.copy(),
+                name=circ.name + "_untied_inputs")
+    return c, np.array(vals, dtype=np.float64), occ
