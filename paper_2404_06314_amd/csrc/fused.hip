@@ -436,113 +436,12 @@ struct FwdArgs {
 
 template <typename R, int KT>
 __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) k_fused_fwd(FwdArgs a) {
-  constexpr int NT = 1 << (KT - kRegBits);
-  constexpr int NW = (NT + 63) / 64;
-  constexpr int WS = NT < 64 ? NT : 64;  // lanes per wave in use
-  // complex64 gates run on the matrix cores (needs full 64-lane waves)
-  constexpr bool kMfma = std::is_same<R, float>::value && NT >= 64;
   extern __shared__ __align__(16) unsigned char smem[];
-  Cx<R> *lds = reinterpret_cast<Cx<R> *>(smem);
-  M2<R> *lds_m = reinterpret_cast<M2<R> *>(smem + (sizeof(Cx<R>) << KT));
-  double *obs_acc = reinterpret_cast<double *>(lds_m + kMaxSweepBlocks);
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int b = blockIdx.y;
-  const cptr<int32_t> prog = as_const(a.prog);
-  const cptr<int32_t> H = prog + a.sweep_off;
-  const int nst = H[0], nout = H[1], nmat = H[3];
-  Cx<R> *__restrict__ st = reinterpret_cast<Cx<R> *>(a.state) + ((int64_t)b << a.n);
-  {
-    // stage this sweep's gate matrices of sample b in LDS
-    const cptr<int32_t> mlist = H + kSwStages + nst + H[2];
-    const R *__restrict__ src = reinterpret_cast<const R *>(a.mats) + (int64_t)b * a.n_blocks * 8;
-    R *dst = reinterpret_cast<R *>(lds_m);
-    for (int i = t; i < nmat * 8; i += NT) dst[i] = src[mlist[i >> 3] * 8 + (i & 7)];
-  }
-  uint32_t gload = 0;
-#pragma unroll
-  for (int i = 0; i < KT - kRegBits; ++i)
-    if ((t >> i) & 1) gload |= 1u << H[kSwLoadTb + i];
-  const uint32_t lload = lds_swizzle((uint32_t)t);
-  if (a.last)
-    for (int i = t; i < (a.M + 1) * NW; i += NT) obs_acc[i] = 0.0;
-  Cx<R> v[kRegs];
-  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    uint32_t tbase = 0;
-    for (int i = 0; i < nout; ++i)
-      if ((tile >> i) & 1) tbase |= 1u << H[kSwOuter + i];
-    if (a.first) {
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j)
-        v[j] = Cx<R>{((tbase | gload | (uint32_t)H[kSwLoadG + j]) == 0u) ? (R)1 : (R)0, (R)0};
-    } else {
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) v[j] = st[tbase | gload | (uint32_t)H[kSwLoadG + j]];
-    }
-#pragma unroll
-    for (int j = 0; j < kRegs; ++j) lds[lload ^ (uint32_t)H[kSwLoadL + j]] = v[j];
-    for (int s = 0; s < nst; ++s) {
-      const cptr<int32_t> S = prog + H[kSwStages + s];
-      const uint32_t gt = tbase | (uint32_t)a.thr[S[kStThr] + t];
-      const uint32_t lsw = lds_swizzle(stage_local_index((uint32_t)t, S));
-      uint32_t tsg = 0;
-      Cx<R>(*const vs[1])[kRegs] = {&v};
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) v[j] = lds[lsw ^ (uint32_t)S[kStLds + j]];
-      const int nops = S[0];
-      for (int o = 0; o < nops; ++o) {
-        const cptr<int32_t> op = S + kStOps + 4 * o;
-        const int code = op[0];
-        if (code == OP_U1) {
-          const M2<R> m = lds_m[op[2]];
-          if constexpr (kMfma) {
-            u1_mfma<1>(vs, op[1], m, false, lane & 3);
-          } else {
-            u1<R>(v, op[1], m);
-          }
-        } else if (code == OP_CNOT) {
-          cnot_op<R>(v, op[1], op[2], op[3], gt);
-        } else {
-          diag_apply<R, 1>(vs, prog + op[1], gt, tsg);
-        }
-      }
-      if (S[kStFlags] & 1) apply_thread_sign<R, 1>(vs, tsg);
-      if (a.last && s == nst - 1) {
-        // per-thread partials in the state's precision, FP64 across lanes
-        R p[kRegs];
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) p[j] = v[j].x * v[j].x + v[j].y * v[j].y;
-        for (int m = 0; m <= a.M; ++m) {
-          const cptr<float> sg = as_const(a.obs_sgn) + m * kRegs;
-          R acc = 0;
-#pragma unroll
-          for (int j = 0; j < kRegs; ++j) acc += (R)sg[j] * p[j];
-          const uint32_t mask = m < a.M ? (uint32_t)as_const(a.masks)[m] : 0u;
-          double d = (__popc(gt & mask) & 1) ? -(double)acc : (double)acc;
-          d = wave_sum_w<WS>(d);
-          if (lane == 0) obs_acc[m * NW + wave] += d;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) lds[lsw ^ (uint32_t)S[kStLds + j]] = v[j];
-    }
-    __syncthreads();
-    if (a.store) {
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) v[j] = lds[lload ^ (uint32_t)H[kSwLoadL + j]];
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) st[tbase | gload | (uint32_t)H[kSwLoadG + j]] = v[j];
-    }
-    __syncthreads();
-  }
-  if (a.last) {
-    __syncthreads();
-    for (int m = t; m <= a.M; m += NT) {
-      double acc = 0.0;
-      for (int wv = 0; wv < NW; ++wv) acc += obs_acc[m * NW + wv];
-      a.part_obs[((int64_t)b * gridDim.x + blockIdx.x) * (a.M + 1) + m] = acc;
-    }
-  }
+  constexpr bool FULL = true;
+  constexpr int ntb = KT - kRegBits;
+  constexpr bool active = true;
+  const int b = blockIdx.y, wg = blockIdx.x, nwg = gridDim.x;
+#include "sweep_fwd.inc"
 }
 
 // ---------------------------------------------------------------------------
@@ -570,162 +469,12 @@ struct BwdArgs {
 
 template <typename R, int KT>
 __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) k_fused_bwd(BwdArgs a) {
-  constexpr int NT = 1 << (KT - kRegBits);
-  constexpr int NW = (NT + 63) / 64;
-  constexpr int WS = NT < 64 ? NT : 64;  // lanes per wave in use
-  constexpr bool kMfma = std::is_same<R, float>::value && NT >= 64;
   extern __shared__ __align__(16) unsigned char smem[];
-  Cx<R> *lds_p = reinterpret_cast<Cx<R> *>(smem);
-  Cx<R> *lds_l = lds_p + (1 << KT);
-  M2<R> *lds_m = reinterpret_cast<M2<R> *>(smem + (2 * sizeof(Cx<R>) << KT));
-  double *nacc = reinterpret_cast<double *>(lds_m + kMaxSweepBlocks);  // [NW]
-  double *gacc = nacc + NW;  // [ngs][3][NW] per-wave gradient accumulators
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int b = blockIdx.y;
-  const cptr<int32_t> prog = as_const(a.prog);
-  const cptr<int32_t> H = prog + a.sweep_off;
-  const int nst = H[0], nout = H[1], ngs = H[2], nmat = H[3];
-  Cx<R> *__restrict__ ps = reinterpret_cast<Cx<R> *>(a.psi) + ((int64_t)b << a.n);
-  Cx<R> *__restrict__ ls = reinterpret_cast<Cx<R> *>(a.lam) + ((int64_t)b << a.n);
-  {
-    const cptr<int32_t> mlist = H + kSwStages + nst + ngs;
-    const R *__restrict__ src = reinterpret_cast<const R *>(a.mats) + (int64_t)b * a.n_blocks * 8;
-    R *dst = reinterpret_cast<R *>(lds_m);
-    for (int i = t; i < nmat * 8; i += NT) dst[i] = src[mlist[i >> 3] * 8 + (i & 7)];
-  }
-  uint32_t gload = 0;
-#pragma unroll
-  for (int i = 0; i < KT - kRegBits; ++i)
-    if ((t >> i) & 1) gload |= 1u << H[kSwLoadTb + i];
-  const uint32_t lload = lds_swizzle((uint32_t)t);
-  for (int i = t; i < NW + ngs * 3 * NW; i += NT) nacc[i] = 0.0;
-  Cx<R> v[kRegs], l[kRegs];
-  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    uint32_t tbase = 0;
-    for (int i = 0; i < nout; ++i)
-      if ((tile >> i) & 1) tbase |= 1u << H[kSwOuter + i];
-    const uint32_t g0 = tbase | gload;
-#pragma unroll
-    for (int j = 0; j < kRegs; ++j) v[j] = ps[g0 | (uint32_t)H[kSwLoadG + j]];
-    if (a.first) {
-      // lambda = D psi, D(x) = sum_m G_m (-1)^popcount(x & S_m), x = g0 | W_j (disjoint bits)
-      double dj[kRegs];
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) dj[j] = 0.0;
-      for (int m = 0; m < a.M; ++m) {
-        double gm = as_const(a.G)[(int64_t)b * a.M + m];
-        if (__popc(g0 & (uint32_t)as_const(a.masks)[m]) & 1) gm = -gm;
-        const cptr<double> sg = as_const(a.seed_sgn) + m * kRegs;
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) dj[j] += sg[j] * gm;
-      }
-      R nrm = 0;
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) {
-        l[j] = Cx<R>{(R)(dj[j] * (double)v[j].x), (R)(dj[j] * (double)v[j].y)};
-        nrm += v[j].x * v[j].x + v[j].y * v[j].y;
-      }
-      double dn = wave_sum_w<WS>((double)nrm);
-      if (lane == 0) nacc[wave] += dn;
-    } else {
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) l[j] = ls[g0 | (uint32_t)H[kSwLoadG + j]];
-    }
-#pragma unroll
-    for (int j = 0; j < kRegs; ++j) {
-      lds_p[lload ^ (uint32_t)H[kSwLoadL + j]] = v[j];
-      lds_l[lload ^ (uint32_t)H[kSwLoadL + j]] = l[j];
-    }
-    for (int s = 0; s < nst; ++s) {
-      const cptr<int32_t> S = prog + H[kSwStages + s];
-      const uint32_t gt = tbase | (uint32_t)a.thr[S[kStThr] + t];
-      const uint32_t lsw = lds_swizzle(stage_local_index((uint32_t)t, S));
-      uint32_t tsg = 0;
-      Cx<R>(*const vs[2])[kRegs] = {&v, &l};
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) {
-        v[j] = lds_p[lsw ^ (uint32_t)S[kStLds + j]];
-        l[j] = lds_l[lsw ^ (uint32_t)S[kStLds + j]];
-      }
-      const int nops = S[0];
-      for (int o = 0; o < nops; ++o) {
-        const cptr<int32_t> op = S + kStOps + 4 * o;
-        const int code = op[0];
-        if (code == OP_U1) {
-          const M2<R> m = lds_m[op[2]];
-          const int gs = op[3];
-          if constexpr (kMfma) {
-            // transition-matrix FMAs (VALU) and the un-apply (MFMA) read the
-            // same registers and sit in one basic block, so they co-issue
-            float tx, ty, tz;
-            bwd_u1_mfma(v, l, op[1], m, lane & 3, tx, ty, tz);
-            const float fx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(tx)), 63));
-            const float fy = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(ty)), 63));
-            const float fz = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dpp_sum_to_lane63(tz)), 63));
-            if (lane == 0 && gs >= 0) {
-              double *g = gacc + gs * 3 * NW;
-              g[wave] += (double)fx;
-              g[NW + wave] += (double)fy;
-              g[2 * NW + wave] += (double)fz;
-            }
-          } else {
-            if (gs >= 0) {
-              R tx = 0, ty = 0, tz = 0;
-              tcomp<R>(v, l, op[1], tx, ty, tz);
-              const R fx = wave_sum_w<WS>(tx), fy = wave_sum_w<WS>(ty), fz = wave_sum_w<WS>(tz);
-              if (lane == 0) {
-                double *g = gacc + gs * 3 * NW;
-                g[wave] += (double)fx;
-                g[NW + wave] += (double)fy;
-                g[2 * NW + wave] += (double)fz;
-              }
-            }
-            u1_adj<R>(v, op[1], m);
-            u1_adj<R>(l, op[1], m);
-          }
-        } else if (code == OP_CNOT) {
-          cnot_op<R>(v, op[1], op[2], op[3], gt);
-          cnot_op<R>(l, op[1], op[2], op[3], gt);
-        } else {
-          diag_apply<R, 2>(vs, prog + op[1], gt, tsg);
-        }
-      }
-      if (S[kStFlags] & 1) apply_thread_sign<R, 2>(vs, tsg);
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) {
-        lds_p[lsw ^ (uint32_t)S[kStLds + j]] = v[j];
-        lds_l[lsw ^ (uint32_t)S[kStLds + j]] = l[j];
-      }
-    }
-    __syncthreads();
-    if (a.store) {
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) {
-        v[j] = lds_p[lload ^ (uint32_t)H[kSwLoadL + j]];
-        l[j] = lds_l[lload ^ (uint32_t)H[kSwLoadL + j]];
-      }
-#pragma unroll
-      for (int j = 0; j < kRegs; ++j) {
-        ps[g0 | (uint32_t)H[kSwLoadG + j]] = v[j];
-        ls[g0 | (uint32_t)H[kSwLoadG + j]] = l[j];
-      }
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  const cptr<int32_t> gsl = H + kSwStages + nst;
-  for (int i = t; i < ngs * 3; i += NT) {
-    const int ls_ = i / 3, c = i % 3;
-    double acc = 0.0;
-    for (int wv = 0; wv < NW; ++wv) acc += gacc[(ls_ * 3 + c) * NW + wv];
-    a.part_grad[(((int64_t)b * a.n_gslots + gsl[ls_]) * gridDim.x + blockIdx.x) * 3 + c] = acc;
-  }
-  if (a.first && t == 0) {
-    double acc = 0.0;
-    for (int wv = 0; wv < NW; ++wv) acc += nacc[wv];
-    a.part_norm[(int64_t)b * gridDim.x + blockIdx.x] = acc;
-  }
+  constexpr bool FULL = true;
+  constexpr int ntb = KT - kRegBits;
+  constexpr bool active = true;
+  const int b = blockIdx.y, wg = blockIdx.x, nwg = gridDim.x;
+#include "sweep_bwd.inc"
 }
 
 // g[b][k] = (px TX + py TY + pz TZ) / norm for occurrence k of slot gs(k)
