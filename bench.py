@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=[None, "c64", "c128"])
     ap.add_argument("--path", default="fused", choices=["fused", "plain"])
     ap.add_argument("--tile", type=int, default=0)
@@ -94,6 +94,8 @@ def main():
     import workloads as W
     import paper_2404_06314_amd as q
 
+    if args.config == "c4":
+        return bench_uneven(args)
     wl = W.config_workload(args.config)
     prec = args.precision or wl.meta["precision"]
     circ = wl.circuit
@@ -203,6 +205,97 @@ def main():
                    "observables": circ.n_obs, "precision": prec, "path": args.path},
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_uneven(args):
+    """1024 circuits (n 8..16, 2..10 layers, CNOT ring), one sample each, in one
+    persistent kernel per direction.  The timed region launches the two HIP
+    graphs; a second pass with per-kernel events (kernels launched one by one)
+    gives the persistent kernels' durations for the roofline."""
+    import ctypes
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2404_06314_amd as q
+
+    items = W.uneven_items(1024)
+    circs = [q.Circuit.from_workload(wl.circuit) for wl in items]
+    m = q.Multi(circs)
+    dev = torch.device("cuda:0")
+    cat = lambda k: torch.as_tensor(np.concatenate([getattr(wl, k).reshape(-1) for wl in items]),
+                                    dtype=torch.float64, device=dev)
+    x, w, G = cat("inputs"), cat("weights"), cat("grad_out")
+    st = m.alloc_state()
+    N = len(items)
+    log(f"workload uneven batch: {N} circuits, n 8..16, 2..10 layers, ring; "
+        f"state {m.state_bytes / 2**20:.1f} MiB")
+
+    def step():
+        m.forward(x, w, st)
+        m.backward(x, w, G, st)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps); units fwd {m.units(0)} bwd {m.units(1)}")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = N * args.steps / (t1 - t0)
+    log(f"timed {args.steps} steps (graphs): {ms_per_step:.3f} ms/step, {value:.1f} circuits/s")
+
+    m.set_timing(True)
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    e1 = time.perf_counter()
+    res = {k: m.timing_read(k) for k in (0, 1)}
+    m.set_timing(False)
+    kind = 1 if res[1][0] >= res[0][0] else 0
+    ms_tot, launches = res[kind]
+    avg_s = ms_tot / launches / 1e3
+    # algorithmic matrix-core work, as for the batched path: 32 flop per pair
+    # per fused block, on psi (forward) or psi and lambda (backward)
+    flop = 0
+    for c, wl in zip(circs, items):
+        plan = c.plan("c64")
+        flop += (1 << (wl.circuit.n - 1)) * block_ops(plan) * 32 * (2 if kind == 1 else 1)
+    tfs = flop / avg_s / 1e12
+    name = "k_multi_bwd" if kind == 1 else "k_multi_fwd"
+    log(f"{name}: {launches} launches, avg {avg_s * 1e6:.1f} us, {flop / 1e9:.2f} GFLOP per launch "
+        f"-> {tfs:.2f} TFLOP/s; eager pass {(e1 - e0) * 1e3 / args.steps:.3f} ms/step; "
+        f"persistent fwd {res[0][0] / args.steps:.3f} ms, bwd {res[1][0] / args.steps:.3f} ms per step")
+    roof = {"bound": "mfma", "achieved": round(tfs, 3), "peak": MFMA_F32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tfs / MFMA_F32_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2), "flop_per_launch": int(flop)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        ns = args.cpu_samples or 64
+        t0 = time.perf_counter()
+        for wl in items[:ns]:
+            oracle.vjp(wl.circuit, wl.inputs, wl.weights, wl.grad_out, threads=1)
+        dt = time.perf_counter() - t0
+        cpu = {"value": ns / dt, "unit": "circuit evals/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {ns} of the {N} circuits, forward + adjoint VJP in complex128, "
+                         f"one thread; {dt:.1f} s"}
+        log(f"cpu baseline: {cpu['value']:.2f} evals/s")
+    out = {
+        "metric": "circuit evals/s (fwd+adjoint grad) uneven batch of 1024 circuits",
+        "value": round(value, 2), "unit": "circuit evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": W.WORKLOAD_NAMES["c4"], "circuits": N, "precision": "c64",
+                   "launch": "persistent kernels in HIP graphs"},
+        "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

@@ -125,12 +125,33 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
                  double *grad_weights, double *grad_inputs, void *stream);
 
 /* Uneven batch (one sample per circuit, circuits of different size and depth,
- * Sec. II-B: batch elements are independent).  The item handles must stay
- * alive while the multi handle exists.  Packed arrays: item i reads
- * inputs[in_off[i] ...], weights[w_off[i] ...], writes expvals[out_off[i] ...]
- * (n_obs of item i values) and gradients at the same offsets as inputs/weights.
- * qtm_multi_layout fills the offsets (arrays of `count` + 1 entries; the last
- * entry is the total length) and the C64 state bytes. */
+ * Sec. II-B: batch elements are independent; each circuit has its own
+ * weights, so no gradient is summed across items).  Amplitudes are complex64.
+ *
+ * qtm_multi_create copies the item list (the item handles must stay alive
+ * while the multi handle exists) and plans every distinct circuit once
+ * (items with equal gates, observables and tile options share one program).
+ * Packed caller arrays: item i reads inputs[in_off[i] ...] (n_inputs of item
+ * i), weights[w_off[i] ...] (n_weights), writes expvals[out_off[i] ...]
+ * (n_obs values), grad_inputs / grad_weights at the input / weight offsets,
+ * and reads grad_expvals at the expval offsets.  qtm_multi_layout fills the
+ * offsets (arrays of `count` + 1 entries; the last entry is the total
+ * length) and the state bytes (8 * 2^n per item, packed in item order).
+ *
+ * Items with at least 4 qubits run in one persistent kernel per direction
+ * (tile units of all circuits in one queue, longest remaining chain first),
+ * launched together with its prep and reduction kernels as one HIP graph
+ * built on the first call; the graph's pointer arguments are updated when
+ * the caller's pointers change.  Items below 4 qubits run one by one on the
+ * per-gate kernels after the graph.
+ *
+ * qtm_multi_forward keeps every item's final state in `state` (dev, caller
+ * owned, qtm_multi_layout bytes); qtm_multi_backward needs the state of the
+ * preceding qtm_multi_forward on the same handle and inputs, and consumes it
+ * (the adjoint un-computes it).  inputs / weights / grad_inputs may be NULL
+ * only when the corresponding total length is 0 (grad_inputs: always).
+ * If a persistent kernel's dependency wait ever times out (an internal
+ * error), the pass's outputs are NaN. */
 int qtm_multi_create(const qtm_circuit_t *items, int32_t count, qtm_multi_t *out);
 int qtm_multi_destroy(qtm_multi_t m);
 int qtm_multi_layout(qtm_multi_t m, int64_t *in_off, int64_t *w_off, int64_t *out_off,
@@ -140,6 +161,15 @@ int qtm_multi_forward(qtm_multi_t m, const double *inputs, const double *weights
 int qtm_multi_backward(qtm_multi_t m, const double *inputs, const double *weights,
                        const double *grad_expvals, void *state, double *grad_weights,
                        double *grad_inputs, void *stream);
+/* Only QTM_OPT_TIMING: with it set, the multi kernels are launched one by one
+ * (no graph) and events bracket each persistent kernel; read them with
+ * qtm_multi_timing_read (kind 0 forward, 1 backward; same contract as
+ * qtm_timing_read). */
+int qtm_multi_set_option(qtm_multi_t m, int32_t option, int64_t value);
+int qtm_multi_timing_read(qtm_multi_t m, int32_t kind, double *total_ms, int64_t *launches);
+/* Number of tile work units in the persistent queue of a pass (kind 0
+ * forward, 1 backward); -1 before the first call has built the queue. */
+int qtm_multi_units(qtm_multi_t m, int32_t kind, int64_t *units);
 
 /* Diagnostics: with QTM_OPT_TIMING set, the library records a pair of HIP
  * events on the call's stream around every sweep kernel it launches.

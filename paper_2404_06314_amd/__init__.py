@@ -159,12 +159,19 @@ def _check_f64(*ts):
 
 
 class Multi:
-    """Uneven batch: one sample per circuit, circuits of any size and depth."""
+    """Uneven batch: one sample per circuit, circuits of any size and depth.
+
+    Items of 4 or more qubits run in one persistent kernel per direction,
+    launched as a HIP graph; item i owns the slices [in_off[i], in_off[i+1])
+    of the packed inputs and input gradients, [w_off[i], w_off[i+1]) of the
+    packed weights and weight gradients, and [out_off[i], out_off[i+1]) of the
+    packed expectation values and their upstream gradients.
+    """
 
     def __init__(self, circuits):
         lib = _lib.load()
         self.items = list(circuits)
-        arr = (ctypes.c_void_p * len(self.items))(*[c.handle.value for c in self.items])
+        arr = (ctypes.c_void_p * max(len(self.items), 1))(*[c.handle.value for c in self.items])
         h = ctypes.c_void_p()
         _lib.check(lib.qtm_multi_create(arr, len(self.items), ctypes.byref(h)))
         self._h = h
@@ -179,6 +186,10 @@ class Multi:
                                         ctypes.byref(sb)))
         self.state_bytes = int(sb.value)
 
+    @property
+    def handle(self):
+        return self._h
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.load().qtm_multi_destroy(self._h)
@@ -190,17 +201,43 @@ class Multi:
         except Exception:
             pass
 
-    def forward(self, inputs, weights, state, stream=None):
+    def set_timing(self, on: bool):
+        _lib.check(_lib.load().qtm_multi_set_option(self._h, QTM_OPT_TIMING, 1 if on else 0))
+
+    def timing_read(self, kind: int):
+        """(total ms, launches) of the persistent kernel of pass `kind` since the last read."""
+        ms = ctypes.c_double()
+        nl = ctypes.c_int64()
+        _lib.check(_lib.load().qtm_multi_timing_read(self._h, kind, ctypes.byref(ms),
+                                                     ctypes.byref(nl)))
+        return ms.value, nl.value
+
+    def units(self, kind: int) -> int:
+        u = ctypes.c_int64()
+        _lib.check(_lib.load().qtm_multi_units(self._h, kind, ctypes.byref(u)))
+        return int(u.value)
+
+    def alloc_state(self, device=None):
         import torch
-        out = torch.empty(int(self.out_off[-1]), dtype=torch.float64, device=inputs.device)
+        return torch.empty(max(self.state_bytes, 1), dtype=torch.uint8, device=device or "cuda")
+
+    def forward(self, inputs, weights, state, stream=None):
+        """Packed inputs / weights (float64 cuda) -> packed expvals (float64)."""
+        import torch
+        _check_f64(inputs, weights)
+        out = torch.empty(int(self.out_off[-1]), dtype=torch.float64, device=state.device)
         _lib.check(_lib.load().qtm_multi_forward(self._h, _ptr(inputs), _ptr(weights), _ptr(out),
                                                  _ptr(state), _stream_ptr(stream)))
         return out
 
-    def backward(self, inputs, weights, grad_expvals, state, stream=None):
+    def backward(self, inputs, weights, grad_expvals, state, need_inputs=True, stream=None):
+        """Returns packed (grad_weights, grad_inputs or None); consumes `state`."""
         import torch
-        gw = torch.empty(int(self.w_off[-1]), dtype=torch.float64, device=inputs.device)
-        gx = torch.empty(int(self.in_off[-1]), dtype=torch.float64, device=inputs.device)
+        _check_f64(inputs, weights, grad_expvals)
+        dev = state.device
+        gw = torch.empty(int(self.w_off[-1]), dtype=torch.float64, device=dev)
+        gx = torch.empty(int(self.in_off[-1]), dtype=torch.float64, device=dev) \
+            if need_inputs else None
         _lib.check(_lib.load().qtm_multi_backward(self._h, _ptr(inputs), _ptr(weights),
                                                   _ptr(grad_expvals), _ptr(state), _ptr(gw),
                                                   _ptr(gx), _stream_ptr(stream)))

@@ -41,6 +41,9 @@ SIGNATURES = {
     "qtm_multi_layout": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "qtm_multi_forward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "qtm_multi_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "qtm_multi_set_option": (ctypes.c_int, [_P, _I32, ctypes.c_int64]),
+    "qtm_multi_timing_read": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "qtm_multi_units": (ctypes.c_int, [_P, _I32, _P]),
     "qtm_timing_read": (ctypes.c_int, [_P, _I32, _P, _P]),
     "qtm_plan_json": (ctypes.c_int, [_P, _I32, ctypes.c_char_p, _SZ, _P]),
     "qtm_last_error": (ctypes.c_char_p, []),
@@ -63,6 +66,12 @@ def load():
         if not LIB_PATH.exists():
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2404_06314_amd.build` (no CPU fallback exists)")
+        # One HIP runtime per process: torch's libraries name the runtime by
+        # a different file name than libqtm does, so if libqtm were loaded
+        # first the process would end up with two HIP/HSA runtimes and the
+        # second one to initialise would see no device.  Loading torch first
+        # makes libqtm bind to the runtime torch already holds.
+        import torch  # noqa: F401
         lib = ctypes.CDLL(str(LIB_PATH))
         for name, (res, args) in SIGNATURES.items():
             f = getattr(lib, name)

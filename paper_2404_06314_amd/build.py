@@ -10,7 +10,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libqtm.so"
-SOURCES = ["api.hip", "plain.hip", "fused.hip", "circuit.cpp"]
+SOURCES = ["api.hip", "plain.hip", "fused.hip", "multi.hip", "circuit.cpp", "schedule.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -13,6 +13,7 @@
 #include "qtm.h"
 #include "circuit.h"
 #include "kernels.h"
+#include "multi.h"
 
 using namespace qtm;
 
@@ -24,8 +25,8 @@ int fail(int code, const std::string &msg) {
   g_err = msg;
   return code;
 }
-int hip_fail(hipError_t e, const char *where) {
-  g_err = std::string(where) + ": " + hipGetErrorString(e);
+int hip_fail(hipError_t e, const std::string &where) {
+  g_err = where + ": " + hipGetErrorString(e);
   return QTM_ERR_HIP;
 }
 
@@ -144,6 +145,10 @@ struct qtm_circuit_s {
 struct qtm_multi_s {
   std::vector<qtm_circuit_t> items;
   std::vector<int64_t> in_off, w_off, out_off, st_off;
+  std::vector<int32_t> narrow;  // items below 4 qubits: per-item plain path
+  MultiRuntime *rt = nullptr;   // every other item: persistent kernels
+  std::unique_ptr<EventTimer> timer;
+  ~qtm_multi_s() { multi_runtime_destroy(rt); }
 };
 
 namespace {
@@ -211,64 +216,26 @@ int get_plan(qtm_circuit_t c, int precision, DevPlan **out) {
     *out = &it->second;
     return QTM_OK;
   }
-  Plan plan = make_plan(c->desc, kt, klo);
-  std::string why = check_plan(c->desc, plan);
+  HostPlan hp;
+  std::string why = build_host_plan(c->desc, kt, klo, hp);
   if (!why.empty()) return fail(QTM_ERR_UNSUPPORTED, "internal planner error: " + why);
-  Program prog = encode_program(c->desc, plan);
   DevPlan dp;
   dp.kt = kt;
   dp.klo = klo;
-  dp.n_blocks = plan.n_blocks;
-  dp.n_gslots = plan.n_gslots;
-  dp.max_gslots = prog.max_gslots_per_sweep;
-  dp.n_sweeps = (int)plan.sweeps.size();
-  dp.sweep_off_fwd = prog.sweep_off_fwd;
-  dp.sweep_off_bwd = prog.sweep_off_bwd;
-  // block records for the matrix prep
-  std::vector<int32_t> blk, blk_off;
-  std::vector<int32_t> occ_gslot(c->desc.occ_gate.size(), 0);
-  for (int b = 0; b < plan.n_blocks; ++b) {
-    const FOp &o = plan.ops[plan.block_op[b]];
-    blk_off.push_back((int32_t)blk.size());
-    blk.push_back(o.q0);
-    blk.push_back((int32_t)o.gates.size());
-    for (int g : o.gates) {
-      const Gate &gt = c->desc.gates[g];
-      int occ = c->desc.gate_occ[g];
-      blk.push_back(gt.type);
-      blk.push_back(gt.src);
-      blk.push_back(gt.index);
-      blk.push_back(occ);
-      occ_gslot[occ] = o.gslot;
-    }
-  }
-  // observable signs of the last forward stage and seed signs of the first
-  // backward load layout
-  const int M = (int)c->desc.masks.size();
-  std::vector<float> osg((size_t)(M + 1) * kRegs, 1.f);
-  std::vector<double> ssg((size_t)M * kRegs, 1.0);
-  if (!plan.sweeps.empty()) {
-    const int last_fwd = prog.sweep_off_fwd.back();
-    const int32_t *H = prog.code.data() + last_fwd;
-    const int nst = H[0];
-    const int32_t *S = prog.code.data() + H[kSwStages + nst - 1];
-    const int first_bwd = prog.sweep_off_bwd.front();
-    const int32_t *HB = prog.code.data() + first_bwd;
-    for (int m = 0; m < M; ++m)
-      for (int j = 0; j < kRegs; ++j) {
-        uint32_t mk = (uint32_t)c->desc.masks[m];
-        osg[m * kRegs + j] = (__builtin_popcount((uint32_t)S[kStGlob + j] & mk) & 1) ? -1.f : 1.f;
-        ssg[m * kRegs + j] = (__builtin_popcount((uint32_t)HB[kSwLoadG + j] & mk) & 1) ? -1.0 : 1.0;
-      }
-  }
+  dp.n_blocks = hp.n_blocks;
+  dp.n_gslots = hp.n_gslots;
+  dp.max_gslots = hp.max_gslots;
+  dp.n_sweeps = hp.n_sweeps;
+  dp.sweep_off_fwd = hp.prog.sweep_off_fwd;
+  dp.sweep_off_bwd = hp.prog.sweep_off_bwd;
   int rc;
-  if ((rc = upload(&dp.code, prog.code, c->owned))) return rc;
-  if ((rc = upload(&dp.thr, prog.thr, c->owned))) return rc;
-  if ((rc = upload(&dp.blk, blk, c->owned))) return rc;
-  if ((rc = upload(&dp.blk_off, blk_off, c->owned))) return rc;
-  if ((rc = upload(&dp.occ_gslot, occ_gslot, c->owned))) return rc;
-  if ((rc = upload(&dp.obs_sgn_f, osg, c->owned))) return rc;
-  if ((rc = upload(&dp.seed_sgn, ssg, c->owned))) return rc;
+  if ((rc = upload(&dp.code, hp.prog.code, c->owned))) return rc;
+  if ((rc = upload(&dp.thr, hp.prog.thr, c->owned))) return rc;
+  if ((rc = upload(&dp.blk, hp.blk, c->owned))) return rc;
+  if ((rc = upload(&dp.blk_off, hp.blk_off, c->owned))) return rc;
+  if ((rc = upload(&dp.occ_gslot, hp.occ_gslot, c->owned))) return rc;
+  if ((rc = upload(&dp.obs_sgn_f, hp.obs_sgn, c->owned))) return rc;
+  if ((rc = upload(&dp.seed_sgn, hp.seed_sgn, c->owned))) return rc;
   auto ins = c->plans.emplace(key, dp);
   *out = &ins.first->second;
   return QTM_OK;
@@ -490,13 +457,12 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
   return QTM_OK;
 }
 
-int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *launches) {
-  if (!c || kind < 0 || kind > 1 || !total_ms || !launches)
-    return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+namespace {
+int read_timer(EventTimer *tp, int32_t kind, double *total_ms, int64_t *launches) {
   *total_ms = 0.0;
   *launches = 0;
-  if (!c->timer) return fail(QTM_ERR_INVALID_ARG, "timing is not enabled (QTM_OPT_TIMING)");
-  EventTimer &t = *c->timer;
+  if (!tp) return fail(QTM_ERR_INVALID_ARG, "timing is not enabled (QTM_OPT_TIMING)");
+  EventTimer &t = *tp;
   if (t.err != hipSuccess) return hip_fail(t.err, "hipEventCreate");
   for (auto &pr : t.pending[kind]) {
     hipError_t e = hipEventSynchronize(pr.second);
@@ -511,6 +477,13 @@ int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *la
   }
   t.pending[kind].clear();
   return QTM_OK;
+}
+}  // namespace
+
+int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *launches) {
+  if (!c || kind < 0 || kind > 1 || !total_ms || !launches)
+    return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  return read_timer(c->timer.get(), kind, total_ms, launches);
 }
 
 // Diagnostics: JSON description of the fused plan for (precision) into buf.
@@ -558,22 +531,36 @@ int qtm_multi_create(const qtm_circuit_t *items, int32_t count, qtm_multi_t *out
   std::unique_ptr<qtm_multi_s> m(new (std::nothrow) qtm_multi_s());
   if (!m) return fail(QTM_ERR_WORKSPACE, "out of host memory");
   int64_t io = 0, wo = 0, oo = 0, so = 0;
+  std::vector<MultiItemIn> wide;
   for (int32_t i = 0; i < count; ++i) {
-    if (!items[i]) return fail(QTM_ERR_INVALID_ARG, "NULL item");
-    m->items.push_back(items[i]);
+    qtm_circuit_t c = items[i];
+    if (!c) return fail(QTM_ERR_INVALID_ARG, "NULL item");
+    m->items.push_back(c);
     m->in_off.push_back(io);
     m->w_off.push_back(wo);
     m->out_off.push_back(oo);
     m->st_off.push_back(so);
-    io += items[i]->desc.n_inputs;
-    wo += items[i]->desc.n_weights;
-    oo += (int64_t)items[i]->desc.masks.size();
-    so += (int64_t)8 << items[i]->desc.n;
+    if (c->desc.n >= kMinTileQubits) {
+      const int kt = default_kt(c, QTM_C64);
+      const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
+      wide.push_back(MultiItemIn{&c->desc, kt, klo, io, wo, oo, so / 8});
+    } else {
+      m->narrow.push_back(i);
+    }
+    io += c->desc.n_inputs;
+    wo += c->desc.n_weights;
+    oo += (int64_t)c->desc.masks.size();
+    so += (int64_t)8 << c->desc.n;
   }
   m->in_off.push_back(io);
   m->w_off.push_back(wo);
   m->out_off.push_back(oo);
   m->st_off.push_back(so);
+  if (!wide.empty()) {
+    std::string err;
+    m->rt = multi_runtime_create(wide, err);
+    if (!m->rt) return fail(QTM_ERR_UNSUPPORTED, err);
+  }
   *out = m.release();
   return QTM_OK;
 }
@@ -594,14 +581,44 @@ int qtm_multi_layout(qtm_multi_t m, int64_t *in_off, int64_t *w_off, int64_t *ou
   return QTM_OK;
 }
 
+int qtm_multi_set_option(qtm_multi_t m, int32_t option, int64_t value) {
+  if (!m) return fail(QTM_ERR_INVALID_ARG, "NULL multi handle");
+  if (option != QTM_OPT_TIMING) return fail(QTM_ERR_UNSUPPORTED, "unknown multi option");
+  if (value && !m->timer) m->timer.reset(new EventTimer());
+  if (!value) m->timer.reset();
+  return QTM_OK;
+}
+
+int qtm_multi_timing_read(qtm_multi_t m, int32_t kind, double *total_ms, int64_t *launches) {
+  if (!m || kind < 0 || kind > 1 || !total_ms || !launches)
+    return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  return read_timer(m->timer.get(), kind, total_ms, launches);
+}
+
+namespace {
+int check_multi_io(qtm_multi_t m, const double *inputs, const double *weights) {
+  if (m->in_off.back() > 0 && !inputs) return fail(QTM_ERR_INVALID_ARG, "inputs is NULL");
+  if (m->w_off.back() > 0 && !weights) return fail(QTM_ERR_INVALID_ARG, "weights is NULL");
+  return QTM_OK;
+}
+}  // namespace
+
 int qtm_multi_forward(qtm_multi_t m, const double *inputs, const double *weights, double *expvals,
                       void *state, void *stream) {
   if (!m || !expvals || !state) return fail(QTM_ERR_INVALID_ARG, "bad arguments");
-  for (size_t i = 0; i < m->items.size(); ++i) {
+  int rc = check_multi_io(m, inputs, weights);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (m->rt) {
+    hipError_t e = multi_runtime_forward(m->rt, inputs, weights, expvals, state, s, m->timer.get());
+    if (e != hipSuccess)
+      return hip_fail(e, std::string("multi forward: ") + multi_runtime_where(m->rt));
+  }
+  for (int32_t i : m->narrow) {
     qtm_circuit_t c = m->items[i];
-    int rc = qtm_forward(c, 1, QTM_C64, inputs ? inputs + m->in_off[i] : nullptr,
-                         weights ? weights + m->w_off[i] : nullptr, expvals + m->out_off[i],
-                         (char *)state + m->st_off[i], stream);
+    rc = qtm_forward(c, 1, QTM_C64, inputs ? inputs + m->in_off[i] : nullptr,
+                     weights ? weights + m->w_off[i] : nullptr, expvals + m->out_off[i],
+                     (char *)state + m->st_off[i], stream);
     if (rc) return rc;
   }
   return QTM_OK;
@@ -610,15 +627,31 @@ int qtm_multi_forward(qtm_multi_t m, const double *inputs, const double *weights
 int qtm_multi_backward(qtm_multi_t m, const double *inputs, const double *weights,
                        const double *grad_expvals, void *state, double *grad_weights,
                        double *grad_inputs, void *stream) {
-  if (!m || !grad_expvals || !state || !grad_weights) return fail(QTM_ERR_INVALID_ARG, "bad arguments");
-  for (size_t i = 0; i < m->items.size(); ++i) {
+  if (!m || !grad_expvals || !state) return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  if (m->w_off.back() > 0 && !grad_weights) return fail(QTM_ERR_INVALID_ARG, "grad_weights is NULL");
+  int rc = check_multi_io(m, inputs, weights);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (m->rt) {
+    hipError_t e = multi_runtime_backward(m->rt, inputs, weights, grad_expvals, state, grad_weights,
+                                          grad_inputs, s, m->timer.get());
+    if (e != hipSuccess)
+      return hip_fail(e, std::string("multi backward: ") + multi_runtime_where(m->rt));
+  }
+  for (int32_t i : m->narrow) {
     qtm_circuit_t c = m->items[i];
-    int rc = qtm_backward(c, 1, QTM_C64, inputs ? inputs + m->in_off[i] : nullptr,
-                          weights ? weights + m->w_off[i] : nullptr, grad_expvals + m->out_off[i],
-                          (char *)state + m->st_off[i], grad_weights + m->w_off[i],
-                          grad_inputs ? grad_inputs + m->in_off[i] : nullptr, stream);
+    rc = qtm_backward(c, 1, QTM_C64, inputs ? inputs + m->in_off[i] : nullptr,
+                      weights ? weights + m->w_off[i] : nullptr, grad_expvals + m->out_off[i],
+                      (char *)state + m->st_off[i], grad_weights ? grad_weights + m->w_off[i] : nullptr,
+                      grad_inputs ? grad_inputs + m->in_off[i] : nullptr, stream);
     if (rc) return rc;
   }
+  return QTM_OK;
+}
+
+int qtm_multi_units(qtm_multi_t m, int32_t kind, int64_t *units) {
+  if (!m || kind < 0 || kind > 1 || !units) return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  *units = m->rt ? multi_runtime_units(m->rt, kind) : 0;
   return QTM_OK;
 }
 

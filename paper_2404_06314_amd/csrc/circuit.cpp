@@ -616,4 +616,53 @@ Program encode_program(const CircuitDesc &c, const Plan &p) {
   return pr;
 }
 
+std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostPlan &out) {
+  Plan plan = make_plan(c, kt, klo);
+  std::string why = check_plan(c, plan);
+  if (!why.empty()) return why;
+  HostPlan &h = out;
+  h.prog = encode_program(c, plan);
+  h.kt = kt;
+  h.klo = klo;
+  h.n_blocks = plan.n_blocks;
+  h.n_gslots = plan.n_gslots;
+  h.max_gslots = h.prog.max_gslots_per_sweep;
+  h.n_sweeps = (int32_t)plan.sweeps.size();
+  h.blk.clear();
+  h.blk_off.clear();
+  h.occ_gslot.assign(c.occ_gate.size(), 0);
+  for (int b = 0; b < plan.n_blocks; ++b) {
+    const FOp &o = plan.ops[plan.block_op[b]];
+    h.blk_off.push_back((int32_t)h.blk.size());
+    h.blk.push_back(o.q0);
+    h.blk.push_back((int32_t)o.gates.size());
+    for (int g : o.gates) {
+      const Gate &gt = c.gates[g];
+      const int occ = c.gate_occ[g];
+      h.blk.push_back(gt.type);
+      h.blk.push_back(gt.src);
+      h.blk.push_back(gt.index);
+      h.blk.push_back(occ);
+      h.occ_gslot[occ] = o.gslot;
+    }
+  }
+  // Z-string signs of the register bits of the last forward stage (the
+  // thread part is applied by the kernel) and of the first backward load
+  const int M = (int)c.masks.size();
+  h.obs_sgn.assign((size_t)(M + 1) * kRegs, 1.f);
+  h.seed_sgn.assign((size_t)M * kRegs, 1.0);
+  if (!plan.sweeps.empty()) {
+    const int32_t *H = h.prog.code.data() + h.prog.sweep_off_fwd.back();
+    const int32_t *S = h.prog.code.data() + H[kSwStages + H[0] - 1];
+    const int32_t *HB = h.prog.code.data() + h.prog.sweep_off_bwd.front();
+    for (int m = 0; m < M; ++m)
+      for (int j = 0; j < kRegs; ++j) {
+        const uint32_t mk = (uint32_t)c.masks[m];
+        h.obs_sgn[m * kRegs + j] = (__builtin_popcount((uint32_t)S[kStGlob + j] & mk) & 1) ? -1.f : 1.f;
+        h.seed_sgn[m * kRegs + j] = (__builtin_popcount((uint32_t)HB[kSwLoadG + j] & mk) & 1) ? -1.0 : 1.0;
+      }
+  }
+  return "";
+}
+
 }  // namespace qtm

@@ -167,4 +167,20 @@ struct Program {
 
 Program encode_program(const CircuitDesc &c, const Plan &p);
 
+// Everything the fused kernels read for one (circuit, kt, klo), in host
+// memory: the program, the block records of the matrix prep, the
+// occurrence -> gradient slot map and the two sign tables.
+struct HostPlan {
+  int32_t kt = 0, klo = 0, n_blocks = 0, n_gslots = 0, max_gslots = 0, n_sweeps = 0;
+  Program prog;
+  std::vector<int32_t> blk;        // per block: [q, ng, (type, src, idx, occ) x ng]
+  std::vector<int32_t> blk_off;    // block -> offset in blk
+  std::vector<int32_t> occ_gslot;  // occurrence -> gradient slot
+  std::vector<float> obs_sgn;      // [(M+1)][16] signs of the last forward stage
+  std::vector<double> seed_sgn;    // [M][16] signs of the first backward load layout
+};
+
+// Plan, check and encode.  Returns "" or the planner's error.
+std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostPlan &out);
+
 }  // namespace qtm

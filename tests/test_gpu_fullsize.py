@@ -92,3 +92,19 @@ def test_c2_adjoint_vs_parameter_shift():
     assert_grad_close(gw_adj, gw_ps, 1e-4, "c2 dL/dw adjoint vs shift", 1e-6)
     for b in range(wl.batch):
         assert_grad_close(gx_adj[b], gx_ps[b], 1e-4, f"c2 dL/dx[{b}] adjoint vs shift", 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_c3_repeats_are_bitwise_identical(precision):
+    """Four forward + backward runs of the full n=20 batch give the same bits
+    (every reduction has a fixed order), and match the oracle.  Guards the
+    backward sweep's LDS accumulators, which must be cleared before any wave
+    adds its first-sweep norm partial."""
+    wl = W.config_workload("c3")
+    ref = fixture("oracle_c3_b64.npz")
+    first = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, precision)
+    assert_parity(first, ref, precision, f"c3 {precision} run 0")
+    for rep in range(1, 4):
+        got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, precision)
+        for a, b in zip(first, got):
+            assert np.array_equal(a, b), f"c3 {precision}: run {rep} differs from run 0"
