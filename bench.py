@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--path", default="fused", choices=["fused", "plain"])
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--klo", type=int, default=0)
+    ap.add_argument("--jit", type=int, default=1, choices=[0, 1],
+                    help="1: sweep kernels specialised for the circuit at run time (QTM_OPT_JIT, "
+                         "the default); 0: the compiled generic sweep kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--cpu-samples", type=int, default=0)
@@ -115,6 +118,8 @@ def main():
         c.set_option(q.QTM_OPT_TILE_QUBITS, args.tile)
     if args.klo:
         c.set_option(q.QTM_OPT_LOW_QUBITS, args.klo)
+    if args.jit and args.path == "fused":
+        c.set_option(q.QTM_OPT_JIT, 1)
     dev = torch.device("cuda:0")
     x = torch.as_tensor(wl.inputs, device=dev)
     w = torch.as_tensor(wl.weights, device=dev)
@@ -128,10 +133,12 @@ def main():
         c.forward(x, w, prec, state=state)
         c.backward(x, w, G, prec, state=state)
 
+    t0 = time.perf_counter()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
+    log(f"warmup done ({args.warmup} steps, {time.perf_counter() - t0:.1f} s"
+        f"{', including compiling the specialised kernels' if args.jit else ''})")
 
     c.set_option(q.QTM_OPT_TIMING, 1 if args.path == "fused" else 0)
     torch.cuda.synchronize()
@@ -172,7 +179,13 @@ def main():
         flop_step = B * (1 << (circ.n - 1)) * nblk * 32 * (2 if kind == 1 else 1)
         per_launch_flop = flop_step / S
         tfs = per_launch_flop / avg_s / 1e12
-        name = "k_fused_bwd" if kind == 1 else "k_fused_fwd"
+        use_jit = args.jit and args.path == "fused"
+        name = ("qtm_jit_bwd" if kind == 1 else "qtm_jit_fwd") if use_jit else \
+            ("k_fused_bwd" if kind == 1 else "k_fused_fwd")
+        if use_jit:
+            for d in (0, 1):
+                info = [c.jit_info(prec, d, s_) for s_ in range(S)]
+                log(f"specialised {'bwd' if d else 'fwd'} kernels (VGPRs, scratch bytes): {info}")
         log(f"{name}: {launches} launches, avg {avg_s * 1e6:.1f} us, {per_launch_bytes / 1e6:.1f} MB "
             f"and {per_launch_flop / 1e9:.1f} GFLOP per launch -> {gbs:.1f} GB/s, {tfs:.2f} TFLOP/s; "
             f"fwd sweeps {res[0][0] / args.steps:.3f} ms/step, "
@@ -212,7 +225,8 @@ def main():
         "config": {"workload": W.WORKLOAD_NAMES[args.config], "n_qubits": circ.n,
                    "layers": W.CONFIGS[args.config]["layers"],
                    "entangler": W.CONFIGS[args.config]["entangler"], "batch": B,
-                   "observables": circ.n_obs, "precision": prec, "path": args.path},
+                   "observables": circ.n_obs, "precision": prec, "path": args.path,
+                   "specialised_kernels": bool(args.jit and args.path == "fused")},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

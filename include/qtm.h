@@ -71,7 +71,12 @@ enum {
   QTM_OPT_TILE_QUBITS = 1, /* fused path: qubits per LDS tile (0 = default) */
   QTM_OPT_LOW_QUBITS = 2,  /* fused path: contiguous low qubits always in a tile */
   QTM_OPT_RENORM = 3,      /* reserved: expectation values are always divided by the norm */
-  QTM_OPT_TIMING = 4       /* 1: record HIP events around every sweep kernel (qtm_timing_read) */
+  QTM_OPT_TIMING = 4,      /* 1: record HIP events around every sweep kernel (qtm_timing_read) */
+  QTM_OPT_JIT = 5          /* fused path: 1 = run sweep kernels specialised for this circuit
+                              (generated from its plan and compiled with hiprtc on the first
+                              call per precision, which takes seconds; errors surface as
+                              QTM_ERR_UNSUPPORTED with the compiler's message), 0 = the
+                              compiled generic sweep kernels (default) */
 };
 
 /* One gate.  Rotations (RX, RY, RZ): q0 = qubit, src = QTM_SRC_INPUT or
@@ -177,6 +182,21 @@ int qtm_multi_units(qtm_multi_t m, int32_t kind, int64_t *units);
  * milliseconds and the number of launches of `kind` (0 = forward sweep,
  * 1 = backward sweep) since the last read, and forgets them. */
 int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *launches);
+
+/* Diagnostics: the HIP source of the specialised kernel of forward (dir 0)
+ * or backward (dir 1) sweep `sweep` at `precision` into buf (truncated to
+ * len - 1 bytes, NUL-terminated); *needed = full length + 1.  Host only. */
+int qtm_jit_source(qtm_circuit_t c, int32_t precision, int32_t dir, int32_t sweep, char *buf,
+                   size_t len, size_t *needed);
+/* Compile (without loading) the specialised sweep kernels of c at
+ * `precision`; host only, no device needed.  QTM_ERR_UNSUPPORTED with the
+ * compiler's message on failure.  The compiled code is kept for later calls
+ * with QTM_OPT_JIT. */
+int qtm_jit_compile(qtm_circuit_t c, int32_t precision);
+/* Diagnostics: vector registers and scratch bytes per thread of a loaded
+ * specialised kernel (after a call with QTM_OPT_JIT on this device). */
+int qtm_jit_info(qtm_circuit_t c, int32_t precision, int32_t dir, int32_t sweep, int32_t *vgprs,
+                 int32_t *scratch);
 
 /* Diagnostics: JSON description of the fused-path plan (sweeps, tile qubits,
  * stages and the gate indices each stage runs) for the given precision.

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import (QTM_C64, QTM_C128, QTM_CNOT, QTM_CZ, QTM_PATH_AUTO, QTM_PATH_FUSED,
                    QTM_PATH_PLAIN, QTM_RX, QTM_RY, QTM_RZ, QTM_SRC_INPUT, QTM_SRC_NONE,
                    QTM_SRC_WEIGHT, QTM_OPT_LOW_QUBITS, QTM_OPT_PATH, QTM_OPT_RENORM,
-                   QTM_OPT_TILE_QUBITS, QTM_OPT_TIMING, QtmError)
+                   QTM_OPT_TILE_QUBITS, QTM_OPT_TIMING, QTM_OPT_JIT, QtmError)
 
 __all__ = ["Circuit", "Multi", "QtmError", "precision_code", "lib_path",
            "QTM_C64", "QTM_C128", "QTM_PATH_AUTO", "QTM_PATH_PLAIN", "QTM_PATH_FUSED"]
@@ -105,6 +105,28 @@ class Circuit:
         _lib.check(lib.qtm_plan_json(self._h, precision_code(precision), buf, need.value,
                                      ctypes.byref(need)))
         return json.loads(buf.value.decode())
+
+    def jit_source(self, precision=QTM_C64, direction: int = 0, sweep: int = 0) -> str:
+        """HIP source of the specialised kernel of one sweep (diagnostics)."""
+        lib = _lib.load()
+        need = ctypes.c_size_t()
+        p = precision_code(precision)
+        _lib.check(lib.qtm_jit_source(self._h, p, direction, sweep, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _lib.check(lib.qtm_jit_source(self._h, p, direction, sweep, buf, need.value, ctypes.byref(need)))
+        return buf.value.decode()
+
+    def jit_compile(self, precision=QTM_C64):
+        """Compile the specialised sweep kernels now (no device needed)."""
+        _lib.check(_lib.load().qtm_jit_compile(self._h, precision_code(precision)))
+
+    def jit_info(self, precision=QTM_C64, direction: int = 0, sweep: int = 0):
+        """(vector registers, scratch bytes) of a loaded specialised kernel."""
+        v = ctypes.c_int32()
+        sc = ctypes.c_int32()
+        _lib.check(_lib.load().qtm_jit_info(self._h, precision_code(precision), direction, sweep,
+                                            ctypes.byref(v), ctypes.byref(sc)))
+        return int(v.value), int(sc.value)
 
     # --- raw pointer calls ----------------------------------------------------
     def forward_ptr(self, batch, precision, inputs, weights, expvals, state, stream):

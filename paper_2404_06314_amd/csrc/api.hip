@@ -7,11 +7,13 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
 #include "qtm.h"
 #include "circuit.h"
+#include "jit.h"
 #include "kernels.h"
 #include "multi.h"
 
@@ -132,6 +134,9 @@ struct qtm_circuit_s {
   DevCircuit dev;
   std::vector<void *> owned;
   std::map<std::pair<int, int>, DevPlan> plans;
+  std::map<std::pair<int, int>, HostPlan> hplans;
+  int jit = 0;  // QTM_OPT_JIT
+  std::map<std::tuple<int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision)
   DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm;
 
   ~qtm_circuit_s() {
@@ -207,28 +212,42 @@ int default_kt(const qtm_circuit_s *c, int precision) {
   return std::max(kt, kMinTileQubits);
 }
 
-int get_plan(qtm_circuit_t c, int precision, DevPlan **out) {
+// Host plan for (kt, klo) of this precision (planned once, kept).
+int get_host_plan(qtm_circuit_t c, int precision, const HostPlan **out) {
   const int kt = default_kt(c, precision);
   const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
   auto key = std::make_pair(kt, klo);
+  auto it = c->hplans.find(key);
+  if (it == c->hplans.end()) {
+    HostPlan hp;
+    std::string why = build_host_plan(c->desc, kt, klo, hp);
+    if (!why.empty()) return fail(QTM_ERR_UNSUPPORTED, "internal planner error: " + why);
+    it = c->hplans.emplace(key, std::move(hp)).first;
+  }
+  *out = &it->second;
+  return QTM_OK;
+}
+
+int get_plan(qtm_circuit_t c, int precision, DevPlan **out) {
+  const HostPlan *hpp = nullptr;
+  int rc = get_host_plan(c, precision, &hpp);
+  if (rc) return rc;
+  const HostPlan &hp = *hpp;
+  auto key = std::make_pair(hp.kt, hp.klo);
   auto it = c->plans.find(key);
   if (it != c->plans.end()) {
     *out = &it->second;
     return QTM_OK;
   }
-  HostPlan hp;
-  std::string why = build_host_plan(c->desc, kt, klo, hp);
-  if (!why.empty()) return fail(QTM_ERR_UNSUPPORTED, "internal planner error: " + why);
   DevPlan dp;
-  dp.kt = kt;
-  dp.klo = klo;
+  dp.kt = hp.kt;
+  dp.klo = hp.klo;
   dp.n_blocks = hp.n_blocks;
   dp.n_gslots = hp.n_gslots;
   dp.max_gslots = hp.max_gslots;
   dp.n_sweeps = hp.n_sweeps;
   dp.sweep_off_fwd = hp.prog.sweep_off_fwd;
   dp.sweep_off_bwd = hp.prog.sweep_off_bwd;
-  int rc;
   if ((rc = upload(&dp.code, hp.prog.code, c->owned))) return rc;
   if ((rc = upload(&dp.thr, hp.prog.thr, c->owned))) return rc;
   if ((rc = upload(&dp.blk, hp.blk, c->owned))) return rc;
@@ -238,6 +257,41 @@ int get_plan(qtm_circuit_t c, int precision, DevPlan **out) {
   if ((rc = upload(&dp.seed_sgn, hp.seed_sgn, c->owned))) return rc;
   auto ins = c->plans.emplace(key, dp);
   *out = &ins.first->second;
+  return QTM_OK;
+}
+
+JitSpec jit_spec(qtm_circuit_t c, int precision, const HostPlan &hp) {
+  JitSpec sp;
+  sp.n = c->desc.n;
+  sp.kt = hp.kt;
+  sp.dbl = precision == QTM_C128;
+  sp.M = (int)c->desc.masks.size();
+  sp.n_blocks = hp.n_blocks;
+  sp.masks = c->desc.masks;
+  sp.hp = &hp;
+  return sp;
+}
+
+// Compile (once) the sweep kernels specialised for this circuit's plan at
+// `precision`; with load, also load them on the current device.
+int get_jit(qtm_circuit_t c, int precision, bool load, const JitSweeps **out) {
+  *out = nullptr;
+  const HostPlan *hp = nullptr;
+  int rc = get_host_plan(c, precision, &hp);
+  if (rc) return rc;
+  const auto key = std::make_tuple(hp->kt, hp->klo, precision);
+  auto it = c->jits.find(key);
+  if (it == c->jits.end()) {
+    std::unique_ptr<JitSweeps> js(new JitSweeps());
+    std::string err = jit_compile(jit_spec(c, precision, *hp), *js);
+    if (!err.empty()) return fail(QTM_ERR_UNSUPPORTED, "specialised sweep kernels: " + err);
+    it = c->jits.emplace(key, std::move(js)).first;
+  }
+  if (load) {
+    hipError_t e = jit_load(*it->second);
+    if (e != hipSuccess) return hip_fail(e, "loading the specialised sweep kernels");
+  }
+  *out = it->second.get();
   return QTM_OK;
 }
 
@@ -270,10 +324,12 @@ int do_forward(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, const 
     if ((rc = get_plan(c, prec, &p))) return rc;
     if ((rc = c->mats.ensure((size_t)B * std::max(p->n_blocks, 1) * sizeof(M2<double>)))) return rc;
     if ((rc = c->part_obs.ensure(fused_part_obs_doubles(d, *p, B) * sizeof(double)))) return rc;
+    const JitSweeps *js = nullptr;
+    if (c->jit && (rc = get_jit(c, prec, true, &js))) return rc;
     hipError_t e =
         prec == QTM_C64
-            ? fused_forward<float>(d, *p, B, x, w, c->mats.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get())
-            : fused_forward<double>(d, *p, B, x, w, c->mats.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get());
+            ? fused_forward<float>(d, *p, B, x, w, c->mats.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get(), js)
+            : fused_forward<double>(d, *p, B, x, w, c->mats.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get(), js);
     if (e != hipSuccess) return hip_fail(e, "fused forward launch");
     return QTM_OK;
   }
@@ -352,6 +408,9 @@ int qtm_set_option(qtm_circuit_t c, int32_t option, int64_t value) {
       if (value && !c->timer) c->timer.reset(new EventTimer());
       if (!value) c->timer.reset();
       return QTM_OK;
+    case QTM_OPT_JIT:
+      c->jit = value ? 1 : 0;
+      return QTM_OK;
     default:
       return fail(QTM_ERR_UNSUPPORTED, "unknown option");
   }
@@ -429,17 +488,19 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
     if ((rc = c->mats.ensure((size_t)batch * std::max(p->n_blocks, 1) * sizeof(M2<double>)))) return rc;
     if ((rc = c->coef.ensure((size_t)batch * std::max(d.n_occ, 1) * 3 * sizeof(double)))) return rc;
     if ((rc = c->part_grad.ensure(fused_part_grad_doubles(d, *p, batch) * sizeof(double)))) return rc;
+    const JitSweeps *js = nullptr;
+    if (c->jit && (rc = get_jit(c, precision, true, &js))) return rc;
     if ((rc = c->part_norm.ensure((size_t)batch * fused_wg_per_sample(d.n, p->kt) * sizeof(double))))
       return rc;
     e = precision == QTM_C64
             ? fused_backward<float>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
                                     (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
                                     (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
-                                    grad_inputs, s, c->timer.get())
+                                    grad_inputs, s, c->timer.get(), js)
             : fused_backward<double>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
                                      (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
                                      (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
-                                     grad_inputs, s, c->timer.get());
+                                     grad_inputs, s, c->timer.get(), js);
   } else {
     if ((rc = c->cs.ensure((size_t)batch * std::max(d.n_occ, 1) * sizeof(double2)))) return rc;
     if ((rc = c->part.ensure(plain_part_doubles(d, batch) * sizeof(double)))) return rc;
@@ -521,6 +582,50 @@ int qtm_plan_json(qtm_circuit_t c, int32_t precision, char *buf, size_t len, siz
     buf[k] = 0;
   }
   return why.empty() ? QTM_OK : fail(QTM_ERR_UNSUPPORTED, why);
+}
+
+// Diagnostics: source of a specialised sweep kernel.
+int qtm_jit_source(qtm_circuit_t c, int32_t precision, int32_t dir, int32_t sweep, char *buf, size_t len,
+                   size_t *needed) {
+  if (!c || (precision != QTM_C64 && precision != QTM_C128) || dir < 0 || dir > 1)
+    return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  if (c->desc.n < kMinTileQubits) return fail(QTM_ERR_UNSUPPORTED, "no fused plan below 4 qubits");
+  const HostPlan *hp = nullptr;
+  int rc = get_host_plan(c, precision, &hp);
+  if (rc) return rc;
+  if (sweep < 0 || sweep >= hp->n_sweeps) return fail(QTM_ERR_INVALID_ARG, "sweep out of range");
+  const std::string src = jit_source(jit_spec(c, precision, *hp), dir, sweep);
+  if (needed) *needed = src.size() + 1;
+  if (buf && len > 0) {
+    size_t k = std::min(len - 1, src.size());
+    memcpy(buf, src.data(), k);
+    buf[k] = 0;
+  }
+  return QTM_OK;
+}
+
+// Compile the specialised sweep kernels of a circuit (no device needed).
+int qtm_jit_compile(qtm_circuit_t c, int32_t precision) {
+  if (!c || (precision != QTM_C64 && precision != QTM_C128)) return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  if (c->desc.n < kMinTileQubits) return fail(QTM_ERR_UNSUPPORTED, "no fused plan below 4 qubits");
+  const JitSweeps *js = nullptr;
+  return get_jit(c, precision, false, &js);
+}
+
+// Diagnostics: registers and scratch bytes of a loaded specialised kernel.
+int qtm_jit_info(qtm_circuit_t c, int32_t precision, int32_t dir, int32_t sweep, int32_t *vgprs,
+                 int32_t *scratch) {
+  if (!c || (precision != QTM_C64 && precision != QTM_C128) || dir < 0 || dir > 1 || !vgprs || !scratch)
+    return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  const HostPlan *hp = nullptr;
+  int rc = get_host_plan(c, precision, &hp);
+  if (rc) return rc;
+  auto it = c->jits.find(std::make_tuple(hp->kt, hp->klo, (int)precision));
+  if (it == c->jits.end() || !it->second->loaded) return fail(QTM_ERR_INVALID_ARG, "specialised kernels not loaded");
+  if (sweep < 0 || sweep >= (int)it->second->k[dir].size()) return fail(QTM_ERR_INVALID_ARG, "sweep out of range");
+  *vgprs = it->second->k[dir][sweep].vgprs;
+  *scratch = it->second->k[dir][sweep].scratch;
+  return QTM_OK;
 }
 
 // --- uneven batch --------------------------------------------------------

@@ -1,8 +1,19 @@
 // Device helpers shared by the HIP kernels of libqtm.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#else
+// runtime compilation: the fixed-width integer types live in hiprtc's namespace
+typedef __hip_internal::int32_t int32_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::int64_t int64_t;
+typedef __hip_internal::uint64_t uint64_t;
+typedef unsigned long uintptr_t;
+#endif
 
 namespace qtm {
 
@@ -16,6 +27,15 @@ template <typename T>
 __device__ __forceinline__ cptr<T> as_const(const T *p) {
   return (cptr<T>)(uintptr_t)p;
 }
+
+template <typename A, typename B>
+struct same_type {
+  static constexpr bool value = false;
+};
+template <typename A>
+struct same_type<A, A> {
+  static constexpr bool value = true;
+};
 
 template <typename R>
 struct Cx {

@@ -20,6 +20,8 @@
 #include <mutex>
 #include <type_traits>
 
+#include "jit.h"
+#include "kernels.h"
 #include "sweep_ops.h"
 
 namespace qtm {
@@ -123,9 +125,23 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// One sweep launch: the specialised kernel when there is one, else the
+// compiled kernel for this tile size.
+template <typename K, typename A>
+static hipError_t launch_sweep(K kernel, const JitSweeps *js, int dir, int sw, int nwg, int B, int nt,
+                               size_t lds, hipStream_t s, A &a) {
+  if (js) {
+    void *args[] = {&a};
+    return hipModuleLaunchKernel(js->k[dir][sw].fn, nwg, B, 1, nt, 1, 1, 0, s, args, nullptr);
+  }
+  hipLaunchKernelGGL(kernel, dim3(nwg, B), dim3(nt), lds, s, a);
+  return hipSuccess;
+}
+
 template <typename R, int KT>
 static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *mats, void *state,
-                          double *part_obs, bool store_final, hipStream_t s, SweepTimer *tm) {
+                          double *part_obs, bool store_final, hipStream_t s, SweepTimer *tm,
+                          const JitSweeps *js) {
   const int nwg = fused_wg_per_sample(d.n, KT);
   const size_t lds = fwd_lds<R, KT>(d.n_obs);
   hipError_t e = allow_lds(k_fused_fwd<R, KT>, lds);
@@ -148,8 +164,9 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *ma
     a.obs_sgn = p.obs_sgn_f;
     a.part_obs = part_obs;
     if (tm) tm->before(0, s);
-    hipLaunchKernelGGL((k_fused_fwd<R, KT>), dim3(nwg, B), dim3(1 << (KT - kRegBits)), lds, s, a);
+    e = launch_sweep(k_fused_fwd<R, KT>, js, 0, sw, nwg, B, 1 << (KT - kRegBits), lds, s, a);
     if (tm) tm->after(0, s);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -157,7 +174,7 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *ma
 template <typename R, int KT>
 static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const double *G, void *mats,
                           void *psi, void *lam, double *part_grad, double *part_norm, hipStream_t s,
-                          SweepTimer *tm) {
+                          SweepTimer *tm, const JitSweeps *js) {
   const int nwg = fused_wg_per_sample(d.n, KT);
   const size_t lds = bwd_lds<R, KT>(p.max_gslots);
   hipError_t e = allow_lds(k_fused_bwd<R, KT>, lds);
@@ -183,8 +200,9 @@ static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const do
     a.n_gslots = p.n_gslots > 0 ? p.n_gslots : 1;
     a.part_norm = part_norm;
     if (tm) tm->before(1, s);
-    hipLaunchKernelGGL((k_fused_bwd<R, KT>), dim3(nwg, B), dim3(1 << (KT - kRegBits)), lds, s, a);
+    e = launch_sweep(k_fused_bwd<R, KT>, js, 1, sw, nwg, B, 1 << (KT - kRegBits), lds, s, a);
     if (tm) tm->after(1, s);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -218,10 +236,10 @@ static hipError_t prep(const DevCircuit &d, const DevPlan &p, int B, const doubl
 template <typename R>
 hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                          const double *w, void *mats, void *state, double *part_obs, double *out,
-                         bool store_final, hipStream_t s, SweepTimer *tm) {
+                         bool store_final, hipStream_t s, SweepTimer *tm, const JitSweeps *js) {
   hipError_t e = prep<R>(d, p, B, x, w, mats, nullptr, s);
   if (e != hipSuccess) return e;
-#define FWD_CALL(K) e = run_fwd<R, K>(d, p, B, mats, state, part_obs, store_final, s, tm)
+#define FWD_CALL(K) e = run_fwd<R, K>(d, p, B, mats, state, part_obs, store_final, s, tm, js)
   QTM_KT_DISPATCH(p.kt, FWD_CALL)
 #undef FWD_CALL
   if (e != hipSuccess) return e;
@@ -232,10 +250,10 @@ template <typename R>
 hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                           const double *w, const double *G, void *mats, double *coef, void *state,
                           void *lam, double *part_grad, double *part_norm, double *gocc, double *gw,
-                          double *gx, hipStream_t s, SweepTimer *tm) {
+                          double *gx, hipStream_t s, SweepTimer *tm, const JitSweeps *js) {
   hipError_t e = prep<R>(d, p, B, x, w, mats, coef, s);
   if (e != hipSuccess) return e;
-#define BWD_CALL(K) e = run_bwd<R, K>(d, p, B, G, mats, state, lam, part_grad, part_norm, s, tm)
+#define BWD_CALL(K) e = run_bwd<R, K>(d, p, B, G, mats, state, lam, part_grad, part_norm, s, tm, js)
   QTM_KT_DISPATCH(p.kt, BWD_CALL)
 #undef BWD_CALL
   if (e != hipSuccess) return e;
@@ -252,17 +270,17 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
 
 template hipError_t fused_forward<float>(const DevCircuit &, const DevPlan &, int, const double *,
                                          const double *, void *, void *, double *, double *, bool,
-                                         hipStream_t, SweepTimer *);
+                                         hipStream_t, SweepTimer *, const JitSweeps *);
 template hipError_t fused_forward<double>(const DevCircuit &, const DevPlan &, int, const double *,
                                           const double *, void *, void *, double *, double *, bool,
-                                          hipStream_t, SweepTimer *);
+                                          hipStream_t, SweepTimer *, const JitSweeps *);
 template hipError_t fused_backward<float>(const DevCircuit &, const DevPlan &, int, const double *,
                                           const double *, const double *, void *, double *, void *,
                                           void *, double *, double *, double *, double *, double *,
-                                          hipStream_t, SweepTimer *);
+                                          hipStream_t, SweepTimer *, const JitSweeps *);
 template hipError_t fused_backward<double>(const DevCircuit &, const DevPlan &, int, const double *,
                                            const double *, const double *, void *, double *, void *,
                                            void *, double *, double *, double *, double *, double *,
-                                           hipStream_t, SweepTimer *);
+                                           hipStream_t, SweepTimer *, const JitSweeps *);
 
 }  // namespace qtm

@@ -10,6 +10,8 @@
 
 namespace qtm {
 
+struct JitSweeps;
+
 // Device copies of a circuit's static data (owned by the circuit handle).
 struct DevCircuit {
   int n = 0, n_inputs = 0, n_weights = 0, n_obs = 0, n_occ = 0;
@@ -66,14 +68,15 @@ int fused_wg_per_sample(int n, int kt);
 size_t fused_part_obs_doubles(const DevCircuit &d, const DevPlan &p, int B);
 size_t fused_part_grad_doubles(const DevCircuit &d, const DevPlan &p, int B);
 
+// js: kernels specialised for this plan (nullptr: the compiled sweep kernels).
 template <typename R>
 hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                          const double *w, void *mats, void *state, double *part_obs, double *out,
-                         bool store_final, hipStream_t s, SweepTimer *tm);
+                         bool store_final, hipStream_t s, SweepTimer *tm, const JitSweeps *js);
 template <typename R>
 hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                           const double *w, const double *G, void *mats, double *coef, void *state,
                           void *lam, double *part_grad, double *part_norm, double *gocc, double *gw,
-                          double *gx, hipStream_t s, SweepTimer *tm);
+                          double *gx, hipStream_t s, SweepTimer *tm, const JitSweeps *js);
 
 }  // namespace qtm

@@ -29,6 +29,7 @@
 
 #include "multi.h"
 #include "schedule.h"
+#include "kernels.h"
 #include "sweep_ops.h"
 
 namespace qtm {

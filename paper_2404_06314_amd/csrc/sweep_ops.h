@@ -5,9 +5,8 @@
 // (sweep_fwd.inc, sweep_bwd.inc) read.
 #pragma once
 
-#include <type_traits>
-
-#include "kernels.h"
+#include "device_common.h"
+#include "layout.h"
 
 namespace qtm {
 
@@ -154,6 +153,35 @@ __device__ __forceinline__ MCols mfma_cols(Cx<float> a, Cx<float> b, Cx<float> c
   const Cx<float> q = row < 2 ? b : d;
   const bool odd = row & 1;
   return {odd ? p.y : p.x, odd ? p.x : -p.y, odd ? q.y : q.x, odd ? q.x : -q.y};
+}
+
+// A operand columns of a gate (adjoint = false) or of its conjugate transpose.
+__device__ __forceinline__ MCols mfma_cols_m(const M2<float> &m, int row, bool adjoint) {
+  return adjoint ? mfma_cols(Cx<float>{m.a.x, -m.a.y}, Cx<float>{m.c.x, -m.c.y},
+                             Cx<float>{m.b.x, -m.b.y}, Cx<float>{m.d.x, -m.d.y}, row)
+                 : mfma_cols(m.a, m.b, m.c, m.d, row);
+}
+
+// Entry (row, k) of the 4x4 real form of a gate (or of its conjugate
+// transpose) given as the 8 floats a.x a.y b.x b.y c.x c.y d.x d.y.
+__device__ __forceinline__ float mfma_entry(const float *e, int row, int k, bool adjoint) {
+  Cx<float> a{e[0], e[1]}, b{e[2], e[3]}, c{e[4], e[5]}, d{e[6], e[7]};
+  if (adjoint) {
+    const Cx<float> t = b;
+    a = Cx<float>{a.x, -a.y};
+    b = Cx<float>{c.x, -c.y};
+    c = Cx<float>{t.x, -t.y};
+    d = Cx<float>{d.x, -d.y};
+  }
+  const MCols m = mfma_cols(a, b, c, d, row);
+  return k == 0 ? m.k0 : k == 1 ? m.k1 : k == 2 ? m.k2 : m.k3;
+}
+
+// A operand columns of slot `slot` from a table of expanded gates
+// ([slot][row][k] floats); arow = 4 * (lane & 3).
+__device__ __forceinline__ MCols lds_cols(const float *tab, int slot, int arow) {
+  const floatx4 x = *reinterpret_cast<const floatx4 *>(tab + slot * 16 + arow);
+  return MCols{x[0], x[1], x[2], x[3]};
 }
 
 template <int P>
@@ -308,6 +336,17 @@ __device__ __forceinline__ uint32_t stage_local_index(uint32_t t, cptr<int32_t> 
     const uint32_t low = (1u << S[kStRegPos + r]) - 1u;
     x = ((x & ~low) << 1) | (x & low);
   }
+  return x;
+}
+
+// The same with the register positions as template arguments (ascending).
+template <int R0, int R1, int R2, int R3>
+__device__ __forceinline__ uint32_t stage_local_index_c(uint32_t t) {
+  uint32_t x = t;
+  x = ((x & ~((1u << R0) - 1u)) << 1) | (x & ((1u << R0) - 1u));
+  x = ((x & ~((1u << R1) - 1u)) << 1) | (x & ((1u << R1) - 1u));
+  x = ((x & ~((1u << R2) - 1u)) << 1) | (x & ((1u << R2) - 1u));
+  x = ((x & ~((1u << R3) - 1u)) << 1) | (x & ((1u << R3) - 1u));
   return x;
 }
 

@@ -149,3 +149,18 @@ def test_plan_sizes_for_configs(qtm):
         c = qtm.Circuit.from_workload(W.config_workload(name).circuit)
         plan = c.plan("c64")
         assert 1 <= len(plan["sweeps"]) <= max_sweeps, (name, len(plan["sweeps"]))
+
+
+def test_specialised_kernels_compile_without_a_device(qtm):
+    """The sweep kernels generated for a circuit compile with the runtime
+    compiler on a host with no GPU (both precisions, CNOT ring and CZ
+    ladder), and the generated source names the circuit's register bits as
+    literals."""
+    import workloads as W
+    for ent in ("ring", "ladder"):
+        circ = W.layered_circuit(6, 2, ent)
+        c = qtm.Circuit.from_workload(circ)
+        for prec in ("c64", "c128"):
+            c.jit_compile(prec)
+            src = c.jit_source(prec, 1, 0)
+            assert "qtm_jit_bwd" in src and "u1_" in src
