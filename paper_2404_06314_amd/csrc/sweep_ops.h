@@ -129,6 +129,29 @@ __device__ __forceinline__ void u1_adj(Cx<R> (&v)[kRegs], int p, const M2<R> &m)
   }
 }
 
+// Transition-matrix components of one pair (v0, v1) / (l0, l1), one fused
+// multiply-add per product:
+//   tx += Im(v0 conj l1 + v1 conj l0), ty += Re(v0 conj l1 - v1 conj l0),
+//   tz += Im(v0 conj l0 - v1 conj l1).
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename R>
+__device__ __forceinline__ void tpair(const Cx<R> &p0, const Cx<R> &p1, const Cx<R> &l0, const Cx<R> &l1,
+                                      R &tx, R &ty, R &tz) {
+  tx = fmadd(p0.y, l1.x, tx);
+  tx = fmadd(-p0.x, l1.y, tx);
+  tx = fmadd(p1.y, l0.x, tx);
+  tx = fmadd(-p1.x, l0.y, tx);
+  ty = fmadd(p0.x, l1.x, ty);
+  ty = fmadd(p0.y, l1.y, ty);
+  ty = fmadd(-p1.x, l0.x, ty);
+  ty = fmadd(-p1.y, l0.y, ty);
+  tz = fmadd(p0.y, l0.x, tz);
+  tz = fmadd(-p0.x, l0.y, tz);
+  tz = fmadd(-p1.y, l1.x, tz);
+  tz = fmadd(p1.x, l1.y, tz);
+}
+
 // --- complex64 gates on the matrix cores -----------------------------------
 //
 // A 2x2 complex gate [[a, b], [c, d]] acting on one pair (v0, v1) is the 4x4
@@ -247,9 +270,7 @@ __device__ __forceinline__ void bwd_u1_mfma_bit(Cx<float> (&v)[kRegs], Cx<float>
   for (int j = 0; j < kRegs; ++j)
     if (!(j & (1 << P))) {
       const Cx<float> p0 = v[j], p1 = v[j | (1 << P)], l0 = l[j], l1 = l[j | (1 << P)];
-      tx += p0.y * l1.x - p0.x * l1.y + p1.y * l0.x - p1.x * l0.y;
-      ty += p0.x * l1.x + p0.y * l1.y - p1.x * l0.x - p1.y * l0.y;
-      tz += p0.y * l0.x - p0.x * l0.y - p1.y * l1.x + p1.x * l1.y;
+      tpair(p0, p1, l0, l1, tx, ty, tz);
     }
   Cx<float>(*const vs[2])[kRegs] = {&v, &l};
   u1_mfma_bit<P, 2>(vs, A);
@@ -410,9 +431,7 @@ __device__ __forceinline__ void tcomp_bit(const Cx<R> (&v)[kRegs], const Cx<R> (
   for (int j = 0; j < kRegs; ++j)
     if (!(j & (1 << P))) {
       const Cx<R> p0 = v[j], p1 = v[j | (1 << P)], l0 = l[j], l1 = l[j | (1 << P)];
-      tx += p0.y * l1.x - p0.x * l1.y + p1.y * l0.x - p1.x * l0.y;
-      ty += p0.x * l1.x + p0.y * l1.y - p1.x * l0.x - p1.y * l0.y;
-      tz += p0.y * l0.x - p0.x * l0.y - p1.y * l1.x + p1.x * l1.y;
+      tpair(p0, p1, l0, l1, tx, ty, tz);
     }
 }
 template <typename R>
