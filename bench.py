@@ -28,6 +28,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources that determine a sweep kernel family's memory traffic: the HBM
+# byte counts recorded under profiles/ hold for a kernel only while these are
+# unchanged.
+_COMMON = ["sweep_ops.h", "device_common.h", "layout.h", "circuit.cpp"]
+KERNEL_SOURCES = {
+    "qtm_jit": ["jit.cpp"] + _COMMON,
+    "k_fused": ["fused.hip", "sweep_fwd.inc", "sweep_bwd.inc"] + _COMMON,
+    "k_multi": ["multi.hip", "schedule.cpp", "sweep_fwd.inc", "sweep_bwd.inc"] + _COMMON,
+}
+
+
+def kernel_digest(kernel: str) -> str:
+    import hashlib
+    fam = next(k for k in KERNEL_SOURCES if kernel.startswith(k))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[fam]:
+        with open(os.path.join(ROOT, "paper_2404_06314_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the counter summaries
+    in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a device copy), or None
+    when none was recorded for the current kernel sources."""
+    import glob
+    digest = kernel_digest(kernel)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        with open(path) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) == 6 and f[0] == "traffic_bytes_per_launch" and f[1] == kernel \
+                        and f[2] == workload and f[4] == "sources" and f[5] == digest:
+                    return int(f[3])
+    return None
+
+
 def sweep_bytes(n_sweeps: int, kind: int) -> int:
     """State-array reads + writes per amplitude, summed over a pass's sweeps.
 
@@ -87,7 +124,12 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--digest", default="",
+                    help="print the digest of the sources of this kernel (traffic records refer to it)")
     args = ap.parse_args()
+    if args.digest:
+        print(kernel_digest(args.digest))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batch would be "
               "split across GPUs with one all-reduce of dL/dweights, which this build does not do",
@@ -196,7 +238,8 @@ def main():
                 "frac": round(tfs / MFMA_F32_PEAK_TFLOPS, 4)}
         use_mfma = prec == "c64" and mfma["frac"] > hbm["frac"]
         main, other = (mfma, hbm) if use_mfma else (hbm, mfma)
-        roof = {"bound": "mfma" if use_mfma else "hbm", **main, "traffic": None,
+        roof = {"bound": "mfma" if use_mfma else "hbm", **main,
+                "traffic": recorded_traffic(name, W.WORKLOAD_NAMES[args.config]),
                 "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
                 "bytes_per_launch": int(per_launch_bytes), "flop_per_launch": int(per_launch_flop),
                 "sweeps": S, ("hbm" if use_mfma else "mfma"): other}
@@ -297,7 +340,8 @@ def bench_uneven(args):
         f"-> {tfs:.2f} TFLOP/s; eager pass {(e1 - e0) * 1e3 / args.steps:.3f} ms/step; "
         f"persistent fwd {res[0][0] / args.steps:.3f} ms, bwd {res[1][0] / args.steps:.3f} ms per step")
     roof = {"bound": "mfma", "achieved": round(tfs, 3), "peak": MFMA_F32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(tfs / MFMA_F32_PEAK_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(tfs / MFMA_F32_PEAK_TFLOPS, 4),
+            "traffic": recorded_traffic(name, W.WORKLOAD_NAMES["c4"]),
             "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2), "flop_per_launch": int(flop)}
     cpu = None
     if not args.no_cpu_baseline:
