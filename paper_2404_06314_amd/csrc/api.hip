@@ -253,6 +253,15 @@ int get_plan(qtm_circuit_t c, int precision, DevPlan **out) {
   if ((rc = upload(&dp.blk, hp.blk, c->owned))) return rc;
   if ((rc = upload(&dp.blk_off, hp.blk_off, c->owned))) return rc;
   if ((rc = upload(&dp.occ_gslot, hp.occ_gslot, c->owned))) return rc;
+  {
+    std::vector<int32_t> ptr(std::max(hp.n_gslots, 0) + 1, 0), occ(hp.occ_gslot.size());
+    for (int32_t g : hp.occ_gslot) ++ptr[g + 1];
+    for (int g = 0; g < hp.n_gslots; ++g) ptr[g + 1] += ptr[g];
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t k = 0; k < hp.occ_gslot.size(); ++k) occ[fill[hp.occ_gslot[k]]++] = (int32_t)k;
+    if ((rc = upload(&dp.gs_ptr, ptr, c->owned))) return rc;
+    if ((rc = upload(&dp.gs_occ, occ, c->owned))) return rc;
+  }
   if ((rc = upload(&dp.obs_sgn_f, hp.obs_sgn, c->owned))) return rc;
   if ((rc = upload(&dp.seed_sgn, hp.seed_sgn, c->owned))) return rc;
   auto ins = c->plans.emplace(key, dp);

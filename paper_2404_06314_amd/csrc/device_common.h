@@ -98,6 +98,20 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sum over a workgroup whose size is a multiple of 64 (every thread gets the
+// same value; fixed order, so results are reproducible bit for bit).  sh
+// holds one double per wave.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < nw; ++w) r += sh[w];
+  return r;
+}
+
 // Sum over the first W lanes of a wave (W = power of two <= 64); every lane
 // of those W must be active.
 template <int W, typename T>

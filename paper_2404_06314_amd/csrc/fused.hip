@@ -82,24 +82,35 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
 #include "sweep_bwd.inc"
 }
 
-// g[b][k] = (px TX + py TY + pz TZ) / norm for occurrence k of slot gs(k)
-__global__ void k_fused_grad_occ(const double *__restrict__ part, const double *__restrict__ pnorm,
-                                 const double *__restrict__ coef, const int32_t *__restrict__ occ_gslot,
-                                 int B, int n_occ, int n_gslots, int nwg, double *__restrict__ gocc) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)B * n_occ) return;
-  const int b = (int)(i / n_occ), k = (int)(i % n_occ);
-  const int gs = occ_gslot[k];
-  double T[3] = {0, 0, 0}, nrm = 0;
-  for (int wg = 0; wg < nwg; ++wg) {
+// One workgroup per (gradient slot gs, sample b): the slot's transition-
+// matrix components summed over the workgroup partials and the norm summed
+// over the first backward sweep's partials (fixed order), then
+// g[b][k] = (px TX + py TY + pz TZ) / norm for every rotation k of the slot.
+__global__ void __launch_bounds__(256) k_fused_grad_slot(const double *__restrict__ part,
+                                                         const double *__restrict__ pnorm,
+                                                         const double *__restrict__ coef,
+                                                         const int32_t *__restrict__ gs_ptr,
+                                                         const int32_t *__restrict__ gs_occ, int n_occ,
+                                                         int n_gslots, int nwg, double *__restrict__ gocc) {
+  __shared__ double sh[4];
+  const int gs = blockIdx.x, b = blockIdx.y;
+  double tx = 0.0, ty = 0.0, tz = 0.0, nr = 0.0;
+  for (int wg = threadIdx.x; wg < nwg; wg += blockDim.x) {
     const double *p = part + (((int64_t)b * n_gslots + gs) * nwg + wg) * 3;
-    T[0] += p[0];
-    T[1] += p[1];
-    T[2] += p[2];
-    nrm += pnorm[(int64_t)b * nwg + wg];
+    tx += p[0];
+    ty += p[1];
+    tz += p[2];
+    nr += pnorm[(int64_t)b * nwg + wg];
   }
-  const double *cf = coef + i * 3;
-  gocc[i] = (cf[0] * T[0] + cf[1] * T[1] + cf[2] * T[2]) / nrm;
+  tx = block_sum(tx, sh);
+  ty = block_sum(ty, sh);
+  tz = block_sum(tz, sh);
+  nr = block_sum(nr, sh);
+  for (int e = gs_ptr[gs] + threadIdx.x; e < gs_ptr[gs + 1]; e += blockDim.x) {
+    const int k = gs_occ[e];
+    const double *cf = coef + ((int64_t)b * n_occ + k) * 3;
+    gocc[(int64_t)b * n_occ + k] = (cf[0] * tx + cf[1] * ty + cf[2] * tz) / nr;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -257,11 +268,10 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
   QTM_KT_DISPATCH(p.kt, BWD_CALL)
 #undef BWD_CALL
   if (e != hipSuccess) return e;
-  if (d.n_occ > 0) {
+  if (d.n_occ > 0 && p.n_gslots > 0) {
     const int nwg = fused_wg_per_sample(d.n, p.kt);
-    k_fused_grad_occ<<<nblocks256((int64_t)B * d.n_occ), 256, 0, s>>>(
-        part_grad, part_norm, coef, p.occ_gslot, B, d.n_occ, p.n_gslots > 0 ? p.n_gslots : 1, nwg,
-        gocc);
+    k_fused_grad_slot<<<dim3(p.n_gslots, B), nwg >= 256 ? 256 : 64, 0, s>>>(
+        part_grad, part_norm, coef, p.gs_ptr, p.gs_occ, d.n_occ, p.n_gslots, nwg, gocc);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

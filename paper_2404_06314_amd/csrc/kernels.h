@@ -35,6 +35,8 @@ struct DevPlan {
   int32_t *blk = nullptr;       // block records for the matrix prep
   int32_t *blk_off = nullptr;   // block -> offset in blk
   int32_t *occ_gslot = nullptr; // occurrence -> gradient slot
+  int32_t *gs_ptr = nullptr;    // gradient slot -> its occurrences (CSR, [n_gslots + 1])
+  int32_t *gs_occ = nullptr;
   float *obs_sgn_f = nullptr;   // [(M+1)][16] signs of the last forward stage (float)
   double *seed_sgn = nullptr;   // [M][16] signs of the first backward load layout (double)
 };

@@ -148,17 +148,21 @@ __global__ void __launch_bounds__(kThreads)
 
 // out[b][m] = sum over partial blocks, in block order; divided by the norm
 // when `normalise` is set.
-__global__ void k_obs_final(const double *__restrict__ part, int B, int nblk, int M,
-                            double *__restrict__ out, int normalise) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B * M) return;
-  int b = i / M, m = i % M;
+// <Z_m> of sample b: sum over the partial rows of column m, divided by the
+// sum of column M (the norm).  One workgroup per (m, b), fixed-order sums.
+__global__ void __launch_bounds__(256) k_obs_final(const double *__restrict__ part, int nblk, int M,
+                                                   double *__restrict__ out, int normalise) {
+  __shared__ double sh[4];
+  const int m = blockIdx.x, b = blockIdx.y;
+  const double *p = part + (int64_t)b * nblk * (M + 1);
   double acc = 0.0, nrm = 0.0;
-  for (int k = 0; k < nblk; ++k) {
-    acc += part[((int64_t)b * nblk + k) * (M + 1) + m];
-    nrm += part[((int64_t)b * nblk + k) * (M + 1) + M];
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+    acc += p[(int64_t)k * (M + 1) + m];
+    nrm += p[(int64_t)k * (M + 1) + M];
   }
-  out[i] = normalise ? acc / nrm : acc;
+  acc = block_sum(acc, sh);
+  nrm = block_sum(nrm, sh);
+  if (threadIdx.x == 0) out[(int64_t)b * M + m] = normalise ? acc / nrm : acc;
 }
 
 // lambda = D psi with D(x) = sum_m G[b][m] (-1)^popcount(x & S_m), D in FP64.
@@ -228,26 +232,31 @@ __global__ void k_plain_grad_final(const double *__restrict__ part, int B, int n
 
 // Scatter per-occurrence derivatives into parameter slots (fixed order):
 // grad_w[j] = sum_b sum_{k in occ(w_j)} gocc[b][k];  grad_x[b][i] = sum_{k in occ(x_i)} gocc[b][k].
-__global__ void k_scatter(const double *__restrict__ gocc, int B, int n_occ,
-                          const int32_t *__restrict__ w_ptr, const int32_t *__restrict__ w_list,
-                          int n_w, const int32_t *__restrict__ x_ptr,
-                          const int32_t *__restrict__ x_list, int n_in, double *__restrict__ gw,
-                          double *__restrict__ gx) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_w) {
-    double acc = 0.0;
-    for (int b = 0; b < B; ++b)
-      for (int e = w_ptr[i]; e < w_ptr[i + 1]; ++e) acc += gocc[(int64_t)b * n_occ + w_list[e]];
-    gw[i] = acc;
-    return;
-  }
-  i -= n_w;
-  if (gx && i < (int64_t)B * n_in) {
-    int b = (int)(i / n_in), k = (int)(i % n_in);
-    double acc = 0.0;
-    for (int e = x_ptr[k]; e < x_ptr[k + 1]; ++e) acc += gocc[(int64_t)b * n_occ + x_list[e]];
-    gx[i] = acc;
-  }
+// dL/dw_j = sum over the batch and over the occurrences of weight j: one
+// workgroup per weight, samples over the threads, fixed-order sums.
+__global__ void __launch_bounds__(256) k_scatter_w(const double *__restrict__ gocc, int B, int n_occ,
+                                                   const int32_t *__restrict__ w_ptr,
+                                                   const int32_t *__restrict__ w_list,
+                                                   double *__restrict__ gw) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x)
+    for (int e = w_ptr[j]; e < w_ptr[j + 1]; ++e) acc += gocc[(int64_t)b * n_occ + w_list[e]];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) gw[j] = acc;
+}
+
+// dL/dx[b][i] = sum over the occurrences of input i (per sample).
+__global__ void k_scatter_x(const double *__restrict__ gocc, int B, int n_occ,
+                            const int32_t *__restrict__ x_ptr, const int32_t *__restrict__ x_list,
+                            int n_in, double *__restrict__ gx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * n_in) return;
+  const int b = (int)(i / n_in), k = (int)(i % n_in);
+  double acc = 0.0;
+  for (int e = x_ptr[k]; e < x_ptr[k + 1]; ++e) acc += gocc[(int64_t)b * n_occ + x_list[e]];
+  gx[i] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -290,9 +299,9 @@ hipError_t plain_forward(const DevCircuit &d, const HostCircuitInfo &h, int B, c
   }
   int nblk = plain_nblk(B, dim);
   k_plain_expval<R><<<dim3(nblk, B), kThreads, 0, s>>>(st, n, d.masks, d.n_obs, part, nblk);
-  k_obs_final<<<nb((int64_t)B * d.n_obs), kThreads, 0, s>>>(part, B, nblk, d.n_obs, out,
-                                                            normalise ? 1 : 0);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_obs_final(part, B, nblk, d.n_obs, out, normalise, s);
 }
 
 template <typename R>
@@ -322,18 +331,25 @@ hipError_t plain_backward(const DevCircuit &d, const HostCircuitInfo &h, int B, 
   return launch_scatter(d, B, gocc, gw, gx, s);
 }
 
+static inline unsigned red_threads(int64_t n) { return n >= 256 ? 256u : 64u; }
+
 hipError_t launch_obs_final(const double *part, int B, int nblk, int M, double *out,
                             bool normalise, hipStream_t s) {
-  k_obs_final<<<nb((int64_t)B * M), kThreads, 0, s>>>(part, B, nblk, M, out, normalise ? 1 : 0);
+  if (B <= 0 || M <= 0) return hipSuccess;
+  k_obs_final<<<dim3(M, B), red_threads(nblk), 0, s>>>(part, nblk, M, out, normalise ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, double *gw, double *gx,
                           hipStream_t s) {
-  int64_t work = (int64_t)d.n_weights + (gx ? (int64_t)B * d.n_inputs : 0);
-  if (work == 0) return hipSuccess;
-  k_scatter<<<nb(work), kThreads, 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, d.n_weights, d.x_ptr,
-                                          d.x_list, d.n_inputs, gw, gx);
+  if (d.n_weights > 0) {
+    k_scatter_w<<<d.n_weights, red_threads(B), 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, gw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (gx && d.n_inputs > 0)
+    k_scatter_x<<<nb((int64_t)B * d.n_inputs), kThreads, 0, s>>>(gocc, B, d.n_occ, d.x_ptr, d.x_list,
+                                                                d.n_inputs, gx);
   return hipGetLastError();
 }
 
