@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--jit", type=int, default=1, choices=[0, 1],
                     help="1: sweep kernels specialised for the circuit at run time (QTM_OPT_JIT, "
                          "the default); 0: the compiled generic sweep kernels")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="1: run the autotuner (tile size, low qubits, generic/specialised) first; "
+                         "its time is not part of the timed steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--cpu-samples", type=int, default=0)
@@ -162,6 +165,13 @@ def main():
         c.set_option(q.QTM_OPT_LOW_QUBITS, args.klo)
     if args.jit and args.path == "fused":
         c.set_option(q.QTM_OPT_JIT, 1)
+    tuned = None
+    if args.autotune and args.path == "fused":
+        t0 = time.perf_counter()
+        tuned = c.autotune(wl.batch, prec, cache=False)
+        args.jit = tuned["jit"]
+        log(f"autotune ({time.perf_counter() - t0:.1f} s): tile {tuned['tile']} klo {tuned['klo']} "
+            f"jit {tuned['jit']} ({len(tuned['candidates'])} candidates)")
     dev = torch.device("cuda:0")
     x = torch.as_tensor(wl.inputs, device=dev)
     w = torch.as_tensor(wl.weights, device=dev)
@@ -194,6 +204,10 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.1f} evals/s")
 
     roof = None
+    plan_kt = plan_klo = None
+    if args.path == "fused":
+        pl = c.plan(prec)
+        plan_kt, plan_klo = pl["kt"], pl["klo"]
     elem = 8 if prec == "c64" else 16
     if args.path == "fused":
         import ctypes
@@ -222,7 +236,8 @@ def main():
         per_launch_flop = flop_step / S
         tfs = per_launch_flop / avg_s / 1e12
         use_jit = args.jit and args.path == "fused"
-        name = ("qtm_jit_bwd" if kind == 1 else "qtm_jit_fwd") if use_jit else \
+        sfx = f"_t{plan_kt}l{plan_klo}" + ("_c128" if prec == "c128" else "")
+        name = (("qtm_jit_bwd" if kind == 1 else "qtm_jit_fwd") + sfx) if use_jit else \
             ("k_fused_bwd" if kind == 1 else "k_fused_fwd")
         if use_jit:
             for d in (0, 1):
@@ -269,7 +284,9 @@ def main():
                    "layers": W.CONFIGS[args.config]["layers"],
                    "entangler": W.CONFIGS[args.config]["entangler"], "batch": B,
                    "observables": circ.n_obs, "precision": prec, "path": args.path,
-                   "specialised_kernels": bool(args.jit and args.path == "fused")},
+                   "specialised_kernels": bool(args.jit and args.path == "fused"),
+                   "tile_qubits": plan_kt, "low_qubits": plan_klo,
+                   "autotuned": tuned is not None},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -183,6 +183,22 @@ int qtm_multi_units(qtm_multi_t m, int32_t kind, int64_t *units);
  * 1 = backward sweep) since the last read, and forgets them. */
 int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *launches);
 
+/* Tune the fused path of c for (batch, precision) on the current device:
+ * tile qubits, contiguous low qubits, and the compiled generic versus the
+ * specialised sweep kernels (QTM_OPT_JIT).  Every candidate must reproduce
+ * the per-gate complex128 result on seeded synthetic inputs within the
+ * precision's tolerances (<Z> 1e-5 absolute and gradients 1e-4 relative for
+ * complex64; 1e-12 / 1e-10 for complex128) before it is timed; the fastest
+ * is installed with qtm_set_option.  flags bit 0: read and update the JSON
+ * cache ($QTM_AUTOTUNE_CACHE, else ~/.cache/qtm_autotune.json), keyed by the
+ * circuit's gates and observables, batch, precision and GPU architecture.
+ * report (may be NULL): JSON summary of the candidates (truncated to len - 1
+ * bytes); *needed = its full length + 1.  Allocates device memory for the
+ * trial inputs and one state, synchronises `stream`, takes seconds.
+ * QTM_ERR_UNSUPPORTED if no candidate passed (options reset to defaults). */
+int qtm_autotune(qtm_circuit_t c, int32_t batch, int32_t precision, void *stream, int32_t flags,
+                 char *report, size_t len, size_t *needed);
+
 /* Diagnostics: the HIP source of the specialised kernel of forward (dir 0)
  * or backward (dir 1) sweep `sweep` at `precision` into buf (truncated to
  * len - 1 bytes, NUL-terminated); *needed = full length + 1.  Host only. */

@@ -120,6 +120,19 @@ class Circuit:
         """Compile the specialised sweep kernels now (no device needed)."""
         _lib.check(_lib.load().qtm_jit_compile(self._h, precision_code(precision)))
 
+    def autotune(self, batch: int, precision=QTM_C64, cache: bool = True, stream=None) -> dict:
+        """Search tile size, contiguous low qubits and generic / specialised
+        sweep kernels for (batch, precision); installs the fastest candidate
+        that reproduces the complex128 per-gate result.  Returns the JSON
+        report (candidates with timings and errors)."""
+        lib = _lib.load()
+        need = ctypes.c_size_t()
+        buf = ctypes.create_string_buffer(1 << 16)
+        rc = lib.qtm_autotune(self._h, int(batch), precision_code(precision), _stream_ptr(stream),
+                              1 if cache else 0, buf, len(buf), ctypes.byref(need))
+        _lib.check(rc)
+        return json.loads(buf.value.decode())
+
     def jit_info(self, precision=QTM_C64, direction: int = 0, sweep: int = 0):
         """(vector registers, scratch bytes) of a loaded specialised kernel."""
         v = ctypes.c_int32()

@@ -16,6 +16,7 @@
 #include "jit.h"
 #include "kernels.h"
 #include "multi.h"
+#include "tune.h"
 
 using namespace qtm;
 
@@ -634,6 +635,44 @@ int qtm_jit_info(qtm_circuit_t c, int32_t precision, int32_t dir, int32_t sweep,
   if (sweep < 0 || sweep >= (int)it->second->k[dir].size()) return fail(QTM_ERR_INVALID_ARG, "sweep out of range");
   *vgprs = it->second->k[dir][sweep].vgprs;
   *scratch = it->second->k[dir][sweep].scratch;
+  return QTM_OK;
+}
+
+int qtm_autotune(qtm_circuit_t c, int32_t batch, int32_t precision, void *stream, int32_t flags, char *report,
+                 size_t len, size_t *needed) {
+  int rc = check_common(c, batch, precision);
+  if (rc) return rc;
+  if (c->desc.n < kMinTileQubits) return fail(QTM_ERR_UNSUPPORTED, "no fused path below 4 qubits");
+  TuneInfo info;
+  info.n = c->desc.n;
+  info.n_inputs = c->desc.n_inputs;
+  info.n_weights = c->desc.n_weights;
+  info.n_obs = (int)c->desc.masks.size();
+  {
+    // FNV-1a over the sizes, gate records and masks
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+      const unsigned char *b = (const unsigned char *)p;
+      for (size_t k = 0; k < n; ++k) h = (h ^ b[k]) * 1099511628211ull;
+    };
+    const int32_t sz[4] = {info.n, info.n_inputs, info.n_weights, info.n_obs};
+    mix(sz, sizeof sz);
+    mix(c->desc.gates.data(), c->desc.gates.size() * sizeof(Gate));
+    mix(c->desc.masks.data(), c->desc.masks.size() * sizeof(uint64_t));
+    char buf[40];
+    snprintf(buf, sizeof buf, "n%d_%016llx", info.n, (unsigned long long)h);
+    info.signature = buf;
+  }
+  std::string rep;
+  rc = autotune(c, info, batch, precision, (hipStream_t)stream, (flags & 1) != 0, rep);
+  if (needed) *needed = rep.size() + 1;
+  if (report && len > 0) {
+    size_t k = std::min(len - 1, rep.size());
+    memcpy(report, rep.data(), k);
+    report[k] = 0;
+  }
+  if (rc == QTM_ERR_UNSUPPORTED) return fail(rc, "autotune: no candidate reproduced the reference");
+  if (rc) return rc == QTM_ERR_HIP ? hip_fail(hipGetLastError(), "autotune") : rc;
   return QTM_OK;
 }
 

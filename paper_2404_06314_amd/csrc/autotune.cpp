@@ -1,0 +1,297 @@
+// Autotuner for the fused path: searches the tile size (kt), the number of
+// contiguous low qubits in a tile (klo) and generic vs specialised sweep
+// kernels for one (circuit, batch, precision) on the current device.
+//
+// Every candidate first has to reproduce a reference result (the per-gate
+// complex128 kernels on the same seeded inputs) within the tolerances of
+// the precision; only then is it timed.  The winner is installed as the
+// circuit's options and kept in a JSON cache keyed by the circuit's gate
+// list and observables, the batch size, the precision and the GPU's name.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <random>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include <sys/stat.h>
+
+#include "qtm.h"
+#include "tune.h"
+
+namespace qtm {
+
+namespace {
+
+struct Cand {
+  int kt, klo, jit;
+  bool ok = false;
+  double ms = 0.0;
+  double err_z = 0.0, err_g = 0.0;
+};
+
+struct Bufs {
+  std::vector<void *> p;
+  ~Bufs() {
+    for (void *x : p) (void)hipFree(x);
+  }
+  template <typename T>
+  T *alloc(size_t n) {
+    void *x = nullptr;
+    if (hipMalloc(&x, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    p.push_back(x);
+    return (T *)x;
+  }
+};
+
+std::string cache_path() {
+  const char *e = getenv("QTM_AUTOTUNE_CACHE");
+  if (e && *e) return e;
+  const char *h = getenv("HOME");
+  return std::string(h && *h ? h : "/tmp") + "/.cache/qtm_autotune.json";
+}
+
+// The cache is a flat JSON array of {"key": ..., "tile": .., "klo": .., "jit": .., "ms": ..}.
+bool cache_lookup(const std::string &key, int &kt, int &klo, int &jit) {
+  std::ifstream f(cache_path());
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  const std::string pat = "\"key\": \"" + key + "\"";
+  size_t i = s.find(pat);
+  if (i == std::string::npos) return false;
+  const size_t end = s.find('}', i);
+  auto num = [&](const char *name, int &out) {
+    const std::string q = std::string("\"") + name + "\": ";
+    size_t j = s.find(q, i);
+    if (j == std::string::npos || j > end) return false;
+    out = atoi(s.c_str() + j + q.size());
+    return true;
+  };
+  return num("tile", kt) && num("klo", klo) && num("jit", jit);
+}
+
+void cache_store(const std::string &key, int kt, int klo, int jit, double ms) {
+  static std::mutex mu;
+  std::lock_guard<std::mutex> g(mu);
+  const std::string path = cache_path();
+  std::string s;
+  {
+    std::ifstream f(path);
+    if (f) {
+      std::stringstream ss;
+      ss << f.rdbuf();
+      s = ss.str();
+    }
+  }
+  std::vector<std::string> entries;
+  size_t i = 0;
+  while ((i = s.find('{', i)) != std::string::npos) {
+    const size_t j = s.find('}', i);
+    if (j == std::string::npos) break;
+    const std::string e = s.substr(i, j - i + 1);
+    if (e.find("\"key\": \"" + key + "\"") == std::string::npos) entries.push_back(e);
+    i = j + 1;
+  }
+  char buf[512];
+  snprintf(buf, sizeof buf, "{\"key\": \"%s\", \"tile\": %d, \"klo\": %d, \"jit\": %d, \"ms\": %.4f}", key.c_str(),
+           kt, klo, jit, ms);
+  entries.push_back(buf);
+  // create missing parent directories
+  for (size_t k = 1; k < path.size(); ++k)
+    if (path[k] == '/') (void)mkdir(path.substr(0, k).c_str(), 0755);
+  std::ofstream f(path + ".tmp");
+  if (!f) return;
+  f << "[\n";
+  for (size_t k = 0; k < entries.size(); ++k) f << "  " << entries[k] << (k + 1 < entries.size() ? ",\n" : "\n");
+  f << "]\n";
+  f.close();
+  (void)rename((path + ".tmp").c_str(), path.c_str());
+}
+
+double max_abs_diff(const std::vector<double> &a, const std::vector<double> &b, size_t lo, size_t hi) {
+  double m = 0.0;
+  for (size_t k = lo; k < hi; ++k) m = std::max(m, std::fabs(a[k] - b[k]));
+  return m;
+}
+double max_abs(const std::vector<double> &a, size_t lo, size_t hi) {
+  double m = 0.0;
+  for (size_t k = lo; k < hi; ++k) m = std::max(m, std::fabs(a[k]));
+  return m;
+}
+
+}  // namespace
+
+int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t precision, hipStream_t stream,
+             bool use_cache, std::string &report) {
+  char dev_name[256] = "gpu";
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      snprintf(dev_name, sizeof dev_name, "%s", prop.gcnArchName);
+  }
+  char keybuf[512];
+  snprintf(keybuf, sizeof keybuf, "%s_B%d_%s_%s", info.signature.c_str(), batch,
+           precision == QTM_C128 ? "c128" : "c64", dev_name);
+  const std::string key = keybuf;
+  std::ostringstream rep;
+  rep << "{\"key\": \"" << key << "\"";
+  int kt = 0, klo = 0, jit = 0;
+  if (use_cache && cache_lookup(key, kt, klo, jit)) {
+    qtm_set_option(c, QTM_OPT_PATH, QTM_PATH_FUSED);
+    qtm_set_option(c, QTM_OPT_TILE_QUBITS, kt);
+    qtm_set_option(c, QTM_OPT_LOW_QUBITS, klo);
+    qtm_set_option(c, QTM_OPT_JIT, jit);
+    rep << ", \"cached\": true, \"tile\": " << kt << ", \"klo\": " << klo << ", \"jit\": " << jit << "}";
+    report = rep.str();
+    return QTM_OK;
+  }
+  const int B = batch, M = info.n_obs, nin = info.n_inputs, nw = info.n_weights;
+  // seeded inputs
+  std::mt19937_64 rng(20240406ull);
+  const double pi = 3.14159265358979323846;
+  std::uniform_real_distribution<double> ang(-pi, pi), gu(-1.0, 1.0);
+  std::vector<double> hx((size_t)B * nin), hw(nw), hG((size_t)B * M);
+  for (double &v : hw) v = ang(rng);
+  for (double &v : hx) v = ang(rng);
+  for (double &v : hG) v = gu(rng);
+  Bufs bufs;
+  double *dx = bufs.alloc<double>(hx.size()), *dw = bufs.alloc<double>(hw.size());
+  double *dG = bufs.alloc<double>(hG.size()), *dout = bufs.alloc<double>((size_t)B * M);
+  double *dgw = bufs.alloc<double>(nw), *dgx = bufs.alloc<double>((size_t)B * nin);
+  size_t sb = 0, sb128 = 0;
+  int rc = qtm_state_bytes(c, B, precision, &sb);
+  if (rc) return rc;
+  rc = qtm_state_bytes(c, B, QTM_C128, &sb128);
+  if (rc) return rc;
+  void *dst = bufs.alloc<char>(std::max(sb, sb128));
+  if (!dx || !dw || !dG || !dout || !dgw || !dgx || !dst) return QTM_ERR_WORKSPACE;
+  if (hipMemcpy(dx, hx.data(), hx.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dw, hw.data(), hw.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dG, hG.data(), hG.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return QTM_ERR_HIP;
+  auto run = [&](int prec, std::vector<double> *res) -> int {
+    int r = qtm_forward(c, B, prec, dx, dw, dout, dst, stream);
+    if (r) return r;
+    r = qtm_backward(c, B, prec, dx, dw, dG, dst, dgw, nin ? dgx : nullptr, stream);
+    if (r) return r;
+    if (!res) return QTM_OK;
+    if (hipStreamSynchronize(stream) != hipSuccess) return QTM_ERR_HIP;
+    res->assign((size_t)B * M + nw + (size_t)B * nin, 0.0);
+    if (hipMemcpy(res->data(), dout, (size_t)B * M * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(res->data() + (size_t)B * M, dgw, (size_t)nw * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        (nin && hipMemcpy(res->data() + (size_t)B * M + nw, dgx, (size_t)B * nin * 8, hipMemcpyDeviceToHost) !=
+                    hipSuccess))
+      return QTM_ERR_HIP;
+    return QTM_OK;
+  };
+  // reference: per-gate kernels, complex128
+  std::vector<double> ref;
+  qtm_set_option(c, QTM_OPT_PATH, QTM_PATH_PLAIN);
+  qtm_set_option(c, QTM_OPT_JIT, 0);
+  if ((rc = run(QTM_C128, &ref))) return rc;
+  const double tol_z = precision == QTM_C128 ? 1e-12 : 1e-5;
+  const double tol_g = precision == QTM_C128 ? 1e-10 : 1e-4;
+  const double floor_g = precision == QTM_C128 ? 1e-13 : 1e-6;
+  const size_t nz = (size_t)B * M, ng = nz + nw, nall = ref.size();
+  const double gscale = std::max(max_abs(ref, nz, ng), max_abs(ref, ng, nall));
+
+  std::vector<Cand> cands;
+  const int kmax = std::min(info.n, 12);
+  for (int t = kmax; t >= std::max(4, kmax - 2); --t)
+    for (int lo = 3; lo <= 7; ++lo) {
+      if (lo > t || (info.n > t && lo > t - 1)) continue;
+      cands.push_back(Cand{t, lo, 0});
+    }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QTM_ERR_HIP;
+  auto measure = [&](Cand &cd) -> int {
+    qtm_set_option(c, QTM_OPT_PATH, QTM_PATH_FUSED);
+    qtm_set_option(c, QTM_OPT_TILE_QUBITS, cd.kt);
+    qtm_set_option(c, QTM_OPT_LOW_QUBITS, cd.klo);
+    qtm_set_option(c, QTM_OPT_JIT, cd.jit);
+    std::vector<double> got;
+    int r = run(precision, &got);
+    if (r) return r;
+    cd.err_z = max_abs_diff(got, ref, 0, nz);
+    cd.err_g = max_abs_diff(got, ref, nz, nall);
+    cd.ok = cd.err_z <= tol_z && cd.err_g <= tol_g * gscale + floor_g;
+    if (!cd.ok) return QTM_OK;
+    // time: enough repetitions for ~30 ms, at least 3
+    (void)hipEventRecord(e0, stream);
+    if ((r = run(precision, nullptr))) return r;
+    (void)hipEventRecord(e1, stream);
+    if (hipEventSynchronize(e1) != hipSuccess) return QTM_ERR_HIP;
+    float one = 0.f;
+    (void)hipEventElapsedTime(&one, e0, e1);
+    const int reps = std::max(3, std::min(50, (int)(30.0 / std::max(one, 0.01f))));
+    (void)hipEventRecord(e0, stream);
+    for (int k = 0; k < reps; ++k)
+      if ((r = run(precision, nullptr))) return r;
+    (void)hipEventRecord(e1, stream);
+    if (hipEventSynchronize(e1) != hipSuccess) return QTM_ERR_HIP;
+    float tot = 0.f;
+    (void)hipEventElapsedTime(&tot, e0, e1);
+    cd.ms = tot / reps;
+    return QTM_OK;
+  };
+  for (Cand &cd : cands)
+    if ((rc = measure(cd))) break;
+  if (!rc) {
+    // specialised kernels for the two fastest generic configurations
+    std::vector<Cand> best;
+    for (const Cand &cd : cands)
+      if (cd.ok) best.push_back(cd);
+    std::sort(best.begin(), best.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+    for (size_t k = 0; k < best.size() && k < 2; ++k) {
+      Cand j{best[k].kt, best[k].klo, 1};
+      if ((rc = measure(j))) break;
+      cands.push_back(j);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  const Cand *win = nullptr;
+  for (const Cand &cd : cands)
+    if (cd.ok && (!win || cd.ms < win->ms)) win = &cd;
+  rep << ", \"cached\": false, \"candidates\": [";
+  for (size_t k = 0; k < cands.size(); ++k) {
+    const Cand &cd = cands[k];
+    char b[256];
+    snprintf(b, sizeof b, "%s{\"tile\": %d, \"klo\": %d, \"jit\": %d, \"ok\": %s, \"ms\": %.4f, \"err_z\": %.3e, \"err_g\": %.3e}",
+             k ? ", " : "", cd.kt, cd.klo, cd.jit, cd.ok ? "true" : "false", cd.ms, cd.err_z, cd.err_g);
+    rep << b;
+  }
+  rep << "]";
+  if (!win) {
+    qtm_set_option(c, QTM_OPT_PATH, QTM_PATH_AUTO);
+    qtm_set_option(c, QTM_OPT_TILE_QUBITS, 0);
+    qtm_set_option(c, QTM_OPT_LOW_QUBITS, 0);
+    qtm_set_option(c, QTM_OPT_JIT, 0);
+    rep << ", \"tile\": 0, \"klo\": 0, \"jit\": 0}";
+    report = rep.str();
+    return QTM_ERR_UNSUPPORTED;
+  }
+  qtm_set_option(c, QTM_OPT_PATH, QTM_PATH_FUSED);
+  qtm_set_option(c, QTM_OPT_TILE_QUBITS, win->kt);
+  qtm_set_option(c, QTM_OPT_LOW_QUBITS, win->klo);
+  qtm_set_option(c, QTM_OPT_JIT, win->jit);
+  rep << ", \"tile\": " << win->kt << ", \"klo\": " << win->klo << ", \"jit\": " << win->jit << ", \"ms\": " << win->ms
+      << "}";
+  report = rep.str();
+  if (use_cache) cache_store(key, win->kt, win->klo, win->jit, win->ms);
+  return QTM_OK;
+}
+
+}  // namespace qtm

@@ -31,9 +31,13 @@ struct JitSpec {
   const HostPlan *hp = nullptr;
 };
 
-// HIP source of forward / backward sweep `sweep` (its kernel is `qtm_jit_fwd`
-// / `qtm_jit_bwd`, argument FwdArgs / BwdArgs as for the compiled kernels).
+// HIP source of forward / backward sweep `sweep` (argument FwdArgs / BwdArgs
+// as for the compiled kernels).  Its kernel is named by jit_kernel_name:
+// qtm_jit_fwd / qtm_jit_bwd with the tile configuration appended
+// (`_t<kt>l<klo>`, plus `_c128` for complex128), so that profiles tell
+// configurations apart.
 std::string jit_source(const JitSpec &sp, int dir, int sweep);
+std::string jit_kernel_name(const JitSpec &sp, int dir);
 
 // Static LDS bytes of that kernel.
 size_t jit_lds_bytes(const JitSpec &sp, int dir, int sweep);
@@ -47,6 +51,7 @@ struct JitKernel {
 
 struct JitSweeps {
   std::vector<JitKernel> k[2];  // [dir][sweep]
+  std::string name[2];          // kernel name per direction
   int device = -1;
   bool loaded = false;
   ~JitSweeps();

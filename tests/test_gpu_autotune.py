@@ -1,0 +1,33 @@
+"""Autotuner: every timed candidate reproduces the complex128 per-gate
+reference, the installed configuration is the fastest of those, results
+after tuning match the oracle, and the cache answers the second call."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import assert_parity, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision,n,L,ent,B", [("c64", 12, 3, "ring", 16), ("c128", 9, 2, "ladder", 4)])
+def test_autotune_installs_fastest_passing_candidate(tmp_path, monkeypatch, precision, n, L, ent, B):
+    import oracle
+    import paper_2404_06314_amd as q
+    monkeypatch.setenv("QTM_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    circ = W.layered_circuit(n, L, ent)
+    c = q.Circuit.from_workload(circ)
+    rep = c.autotune(B, precision)
+    assert not rep["cached"]
+    ok = [x for x in rep["candidates"] if x["ok"]]
+    assert ok, rep
+    best = min(ok, key=lambda x: x["ms"])
+    assert (rep["tile"], rep["klo"], rep["jit"]) == (best["tile"], best["klo"], best["jit"])
+    assert any(x["jit"] == 1 for x in rep["candidates"])
+    rng = np.random.default_rng(7)
+    wl = W.random_workload(rng, circ, B)
+    got = run_gpu(circ, wl.inputs, wl.weights, wl.grad_out, precision, qcirc=c)
+    assert_parity(got, oracle.vjp(circ, wl.inputs, wl.weights, wl.grad_out), precision, "tuned")
+    c2 = q.Circuit.from_workload(circ)
+    rep2 = c2.autotune(B, precision)
+    assert rep2["cached"] and (rep2["tile"], rep2["klo"], rep2["jit"]) == (best["tile"], best["klo"], best["jit"])
