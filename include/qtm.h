@@ -129,6 +129,20 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
                  const double *weights, const double *grad_expvals, void *state,
                  double *grad_weights, double *grad_inputs, void *stream);
 
+/* Full Jacobian of the expectation values (the paper's (B, M, |Theta|)
+ * result, Sec. II-A, Eq. (5)-(6)): forward once, then one adjoint backward
+ * per observable m with the upstream gradient e_m, each restarted from a
+ * saved copy of the final states (library workspace: two state buffers).
+ *   expvals      dev [batch][n_obs] float64, overwritten; may be NULL
+ *   jac_weights  dev [batch][n_obs][n_weights] float64: d<O_m>(sample b)/dw_j
+ *                (per sample, not summed over the batch)
+ *   jac_inputs   dev [batch][n_obs][n_inputs] float64, or NULL
+ * Cost ~ forward + n_obs backward passes.  Same stream semantics as
+ * qtm_backward. */
+int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
+                 const double *weights, double *expvals, double *jac_weights, double *jac_inputs,
+                 void *stream);
+
 /* Uneven batch (one sample per circuit, circuits of different size and depth,
  * Sec. II-B: batch elements are independent; each circuit has its own
  * weights, so no gradient is summed across items).  Amplitudes are complex64.

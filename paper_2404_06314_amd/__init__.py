@@ -184,6 +184,24 @@ class Circuit:
         return gw, gx
 
 
+def _jacobian(self, inputs, weights, precision=QTM_C64, need_inputs=True, stream=None):
+    """Full Jacobian: (expvals (B, M), J_w (B, M, n_weights), J_x (B, M, n_inputs) or None)."""
+    import torch
+    B = int(inputs.shape[0])
+    _check_f64(inputs, weights)
+    dev = inputs.device
+    out = torch.empty((B, self.n_obs), dtype=torch.float64, device=dev)
+    jw = torch.empty((B, self.n_obs, max(self.n_weights, 0)), dtype=torch.float64, device=dev)
+    jx = torch.empty((B, self.n_obs, self.n_inputs), dtype=torch.float64, device=dev) \
+        if need_inputs else None
+    _lib.check(_lib.load().qtm_jacobian(self._h, B, precision_code(precision), _ptr(inputs), _ptr(weights),
+                                        _ptr(out), _ptr(jw), _ptr(jx), _stream_ptr(stream)))
+    return out, jw, jx
+
+
+Circuit.jacobian = _jacobian
+
+
 def _check_f64(*ts):
     import torch
     for t in ts:

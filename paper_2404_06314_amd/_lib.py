@@ -48,6 +48,7 @@ SIGNATURES = {
     "qtm_timing_read": (ctypes.c_int, [_P, _I32, _P, _P]),
     "qtm_jit_source": (ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_char_p, _SZ, _P]),
     "qtm_jit_compile": (ctypes.c_int, [_P, _I32]),
+    "qtm_jacobian": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P, _P]),
     "qtm_autotune": (ctypes.c_int, [_P, _I32, _I32, _P, _I32, ctypes.c_char_p, _SZ, _P]),
     "qtm_jit_info": (ctypes.c_int, [_P, _I32, _I32, _I32, _P, _P]),
     "qtm_plan_json": (ctypes.c_int, [_P, _I32, ctypes.c_char_p, _SZ, _P]),

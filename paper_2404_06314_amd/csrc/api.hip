@@ -139,11 +139,12 @@ struct qtm_circuit_s {
   int jit = 0;  // QTM_OPT_JIT
   std::map<std::tuple<int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision)
   DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm;
+  DevBuf jac_state, jac_G, jac_gw, jac_out;
 
   ~qtm_circuit_s() {
     for (void *p : owned) (void)hipFree(p);
     for (DevBuf *b : {&cs, &part, &gocc, &lam, &state_ws, &mats, &coef, &part_obs, &part_grad,
-                      &part_norm})
+                      &part_norm, &jac_state, &jac_G, &jac_gw, &jac_out})
       b->release();
   }
 };
@@ -355,6 +356,54 @@ int do_forward(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, const 
   return QTM_OK;
 }
 
+// Adjoint backward from the final states in psi (consumed).  Leaves the
+// per-sample, per-rotation derivatives in c->gocc.
+int run_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
+                 const double *weights, const double *grad_expvals, void *psi, double *grad_weights,
+                 double *grad_inputs, hipStream_t s) {
+  const DevCircuit &d = c->dev;
+  const size_t sbytes = ((size_t)batch << c->desc.n) * elem_bytes(precision);
+  int rc;
+  if ((rc = c->lam.ensure(sbytes))) return rc;
+  if ((rc = c->gocc.ensure((size_t)batch * std::max(std::max(d.n_occ, d.n_obs), 1) * sizeof(double))))
+    return rc;
+  hipError_t e;
+  if (use_fused(c)) {
+    DevPlan *p = nullptr;
+    if ((rc = get_plan(c, precision, &p))) return rc;
+    if ((rc = c->mats.ensure((size_t)batch * std::max(p->n_blocks, 1) * sizeof(M2<double>)))) return rc;
+    if ((rc = c->coef.ensure((size_t)batch * std::max(d.n_occ, 1) * 3 * sizeof(double)))) return rc;
+    if ((rc = c->part_grad.ensure(fused_part_grad_doubles(d, *p, batch) * sizeof(double)))) return rc;
+    const JitSweeps *js = nullptr;
+    if (c->jit && (rc = get_jit(c, precision, true, &js))) return rc;
+    if ((rc = c->part_norm.ensure((size_t)batch * fused_wg_per_sample(d.n, p->kt) * sizeof(double))))
+      return rc;
+    e = precision == QTM_C64
+            ? fused_backward<float>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
+                                    (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
+                                    (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
+                                    grad_inputs, s, c->timer.get(), js)
+            : fused_backward<double>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
+                                     (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
+                                     (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
+                                     grad_inputs, s, c->timer.get(), js);
+  } else {
+    if ((rc = c->cs.ensure((size_t)batch * std::max(d.n_occ, 1) * sizeof(double2)))) return rc;
+    if ((rc = c->part.ensure(plain_part_doubles(d, batch) * sizeof(double)))) return rc;
+    e = launch_half_angles(d, batch, inputs, weights, (double2 *)c->cs.p, s);
+    if (e == hipSuccess)
+      e = precision == QTM_C64
+              ? plain_backward<float>(d, c->hinfo, batch, (double2 *)c->cs.p, psi, c->lam.p,
+                                      grad_expvals, (double *)c->part.p, (double *)c->gocc.p,
+                                      grad_weights, grad_inputs, s)
+              : plain_backward<double>(d, c->hinfo, batch, (double2 *)c->cs.p, psi, c->lam.p,
+                                       grad_expvals, (double *)c->part.p, (double *)c->gocc.p,
+                                       grad_weights, grad_inputs, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  return QTM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -488,43 +537,42 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
     if ((rc = do_forward(c, batch, precision, inputs, weights, (double *)c->gocc.p, psi, true, s)))
       return rc;
   }
-  if ((rc = c->lam.ensure(sbytes))) return rc;
-  if ((rc = c->gocc.ensure((size_t)batch * std::max(std::max(d.n_occ, d.n_obs), 1) * sizeof(double))))
+  return run_backward(c, batch, precision, inputs, weights, grad_expvals, psi, grad_weights, grad_inputs, s);
+}
+
+int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
+                 const double *weights, double *expvals, double *jac_weights, double *jac_inputs,
+                 void *stream) {
+  int rc = check_common(c, batch, precision);
+  if (rc) return rc;
+  const CircuitDesc &cd = c->desc;
+  if (cd.n_weights > 0 && !jac_weights) return fail(QTM_ERR_INVALID_ARG, "jac_weights is NULL");
+  if (cd.n_inputs > 0 && !inputs) return fail(QTM_ERR_INVALID_ARG, "inputs is NULL");
+  if (cd.n_weights > 0 && !weights) return fail(QTM_ERR_INVALID_ARG, "weights is NULL");
+  if ((rc = ensure_device(c))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const DevCircuit &d = c->dev;
+  const int M = d.n_obs;
+  const size_t sbytes = ((size_t)batch << cd.n) * elem_bytes(precision);
+  if ((rc = c->state_ws.ensure(sbytes)) || (rc = c->jac_state.ensure(sbytes)) ||
+      (rc = c->jac_G.ensure((size_t)batch * M * sizeof(double))) ||
+      (rc = c->jac_gw.ensure((size_t)std::max(cd.n_weights, 1) * sizeof(double))) ||
+      (rc = c->jac_out.ensure((size_t)batch * M * sizeof(double))))
     return rc;
-  hipError_t e;
-  if (use_fused(c)) {
-    DevPlan *p = nullptr;
-    if ((rc = get_plan(c, precision, &p))) return rc;
-    if ((rc = c->mats.ensure((size_t)batch * std::max(p->n_blocks, 1) * sizeof(M2<double>)))) return rc;
-    if ((rc = c->coef.ensure((size_t)batch * std::max(d.n_occ, 1) * 3 * sizeof(double)))) return rc;
-    if ((rc = c->part_grad.ensure(fused_part_grad_doubles(d, *p, batch) * sizeof(double)))) return rc;
-    const JitSweeps *js = nullptr;
-    if (c->jit && (rc = get_jit(c, precision, true, &js))) return rc;
-    if ((rc = c->part_norm.ensure((size_t)batch * fused_wg_per_sample(d.n, p->kt) * sizeof(double))))
+  double *out = expvals ? expvals : (double *)c->jac_out.p;
+  if ((rc = do_forward(c, batch, precision, inputs, weights, out, c->state_ws.p, true, s))) return rc;
+  hipError_t e = hipMemcpyAsync(c->jac_state.p, c->state_ws.p, sbytes, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "jacobian state copy");
+  for (int m = 0; m < M; ++m) {
+    if (m > 0 && (e = hipMemcpyAsync(c->state_ws.p, c->jac_state.p, sbytes, hipMemcpyDeviceToDevice, s)))
+      return hip_fail(e, "jacobian state copy");
+    if ((e = launch_onehot((double *)c->jac_G.p, batch, M, m, s))) return hip_fail(e, "jacobian seed");
+    if ((rc = run_backward(c, batch, precision, inputs, weights, (double *)c->jac_G.p, c->state_ws.p,
+                           (double *)c->jac_gw.p, nullptr, s)))
       return rc;
-    e = precision == QTM_C64
-            ? fused_backward<float>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
-                                    (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
-                                    (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
-                                    grad_inputs, s, c->timer.get(), js)
-            : fused_backward<double>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
-                                     (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
-                                     (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
-                                     grad_inputs, s, c->timer.get(), js);
-  } else {
-    if ((rc = c->cs.ensure((size_t)batch * std::max(d.n_occ, 1) * sizeof(double2)))) return rc;
-    if ((rc = c->part.ensure(plain_part_doubles(d, batch) * sizeof(double)))) return rc;
-    e = launch_half_angles(d, batch, inputs, weights, (double2 *)c->cs.p, s);
-    if (e == hipSuccess)
-      e = precision == QTM_C64
-              ? plain_backward<float>(d, c->hinfo, batch, (double2 *)c->cs.p, psi, c->lam.p,
-                                      grad_expvals, (double *)c->part.p, (double *)c->gocc.p,
-                                      grad_weights, grad_inputs, s)
-              : plain_backward<double>(d, c->hinfo, batch, (double2 *)c->cs.p, psi, c->lam.p,
-                                       grad_expvals, (double *)c->part.p, (double *)c->gocc.p,
-                                       grad_weights, grad_inputs, s);
+    if ((e = launch_scatter_jac(d, batch, (double *)c->gocc.p, m, jac_weights, jac_inputs, s)))
+      return hip_fail(e, "jacobian scatter");
   }
-  if (e != hipSuccess) return hip_fail(e, "backward launch");
   return QTM_OK;
 }
 

@@ -56,6 +56,9 @@ hipError_t launch_obs_final(const double *part, int B, int nblk, int M, double *
 hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, double *gw, double *gx,
                           hipStream_t s);
 size_t plain_part_doubles(const DevCircuit &d, int B);
+hipError_t launch_onehot(double *G, int B, int M, int m, hipStream_t s);
+hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, int m, double *jw,
+                              double *jx, hipStream_t s);
 
 template <typename R>
 hipError_t plain_forward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,

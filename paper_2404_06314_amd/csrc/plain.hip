@@ -259,6 +259,35 @@ __global__ void k_scatter_x(const double *__restrict__ gocc, int B, int n_occ,
   gx[i] = acc;
 }
 
+// Upstream gradient selecting observable m for every sample.
+__global__ void k_onehot(double *__restrict__ G, int B, int M, int m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)B * M) G[i] = (int)(i % M) == m ? 1.0 : 0.0;
+}
+
+// Row m of the Jacobian: per sample, every weight and input slot sums its
+// rotation occurrences (no sum over the batch).
+__global__ void k_scatter_jac(const double *__restrict__ gocc, int B, int n_occ,
+                              const int32_t *__restrict__ w_ptr, const int32_t *__restrict__ w_list,
+                              int n_w, const int32_t *__restrict__ x_ptr,
+                              const int32_t *__restrict__ x_list, int n_in, int m, int M,
+                              double *__restrict__ jw, double *__restrict__ jx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = n_w + (jx ? n_in : 0);
+  if (i >= (int64_t)B * per) return;
+  const int b = (int)(i / per), j = (int)(i % per);
+  const double *g = gocc + (int64_t)b * n_occ;
+  double acc = 0.0;
+  if (j < n_w) {
+    for (int e = w_ptr[j]; e < w_ptr[j + 1]; ++e) acc += g[w_list[e]];
+    jw[((int64_t)b * M + m) * n_w + j] = acc;
+  } else {
+    const int k = j - n_w;
+    for (int e = x_ptr[k]; e < x_ptr[k + 1]; ++e) acc += g[x_list[e]];
+    jx[((int64_t)b * M + m) * n_in + k] = acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 
@@ -350,6 +379,20 @@ hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, double
   if (gx && d.n_inputs > 0)
     k_scatter_x<<<nb((int64_t)B * d.n_inputs), kThreads, 0, s>>>(gocc, B, d.n_occ, d.x_ptr, d.x_list,
                                                                 d.n_inputs, gx);
+  return hipGetLastError();
+}
+
+hipError_t launch_onehot(double *G, int B, int M, int m, hipStream_t s) {
+  k_onehot<<<nb((int64_t)B * M), kThreads, 0, s>>>(G, B, M, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, int m, double *jw,
+                              double *jx, hipStream_t s) {
+  const int64_t work = (int64_t)B * (d.n_weights + (jx ? d.n_inputs : 0));
+  if (work == 0) return hipSuccess;
+  k_scatter_jac<<<nb(work), kThreads, 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, d.n_weights, d.x_ptr,
+                                              d.x_list, d.n_inputs, m, d.n_obs, jw, jx);
   return hipGetLastError();
 }
 

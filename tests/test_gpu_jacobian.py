@@ -1,0 +1,73 @@
+"""Full Jacobian (B, M, |Theta|) through qtm_jacobian: against the oracle's
+multi-bra Jacobian (one adjoint bra per observable, the paper's form), and
+at n=20 against the VJP it must contract to."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import FLOOR_G_C64, FLOOR_G_C128, TOL_G_C64, TOL_G_C128, TOL_Z_C64, TOL_Z_C128, \
+    assert_grad_close
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_jacobian(circ, x, w, precision, path=None, jit=False):
+    import torch
+    import paper_2404_06314_amd as q
+    c = q.Circuit.from_workload(circ)
+    if path is not None:
+        c.set_path(path)
+    if jit:
+        c.set_option(q.QTM_OPT_JIT, 1)
+    xt = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+    wt = torch.as_tensor(np.ascontiguousarray(w), dtype=torch.float64, device="cuda:0")
+    ev, jw, jx = c.jacobian(xt, wt, precision)
+    torch.cuda.synchronize()
+    return c, ev.cpu().numpy(), jw.cpu().numpy(), jx.cpu().numpy()
+
+
+def check(got, ref, precision, what):
+    ev, jw, jx = got
+    rev, rjw, rjx = ref
+    tz = TOL_Z_C64 if precision == "c64" else TOL_Z_C128
+    tg = TOL_G_C64 if precision == "c64" else TOL_G_C128
+    fl = FLOOR_G_C64 if precision == "c64" else FLOOR_G_C128
+    assert np.max(np.abs(ev - rev)) <= tz, what
+    for b in range(rev.shape[0]):
+        for m in range(rev.shape[1]):
+            assert_grad_close(jw[b, m], rjw[b, m], tg, f"{what} J_w[{b},{m}]", fl)
+            assert_grad_close(jx[b, m], rjx[b, m], tg, f"{what} J_x[{b},{m}]", fl)
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+@pytest.mark.parametrize("case", ["c1", "layered", "random_plain", "layered_jit"])
+def test_jacobian_against_oracle(precision, case):
+    import oracle
+    rng = np.random.default_rng(77)
+    path, jit = None, False
+    if case == "c1":
+        wl = W.config_workload("c1")
+    elif case.startswith("layered"):
+        wl = W.random_workload(rng, W.layered_circuit(8, 3, "ring", extra_masks=(0xFF,)), 4)
+        jit = case.endswith("jit")
+    else:
+        import paper_2404_06314_amd as q
+        wl = W.random_workload(rng, W.random_circuit(rng, 6, 40), 3)
+        path = q.QTM_PATH_PLAIN
+    _, ev, jw, jx = gpu_jacobian(wl.circuit, wl.inputs, wl.weights, precision, path, jit)
+    ref = oracle.jacobian(wl.circuit, wl.inputs, wl.weights)
+    check((ev, jw, jx), ref, precision, f"{case} {precision}")
+
+
+def test_jacobian_contracts_to_vjp_n20():
+    """n=20, 8 layers, CZ ladder, first 8 samples: sum_m G[b,m] J[b,m,:]
+    equals the VJP's per-sample dL/dx and, summed over b, its dL/dw."""
+    from gpu_helpers import run_gpu
+    wl = W.config_workload("c3", batch=8)
+    c, ev, jw, jx = gpu_jacobian(wl.circuit, wl.inputs, wl.weights, "c64")
+    ev2, gw, gx = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, "c64")
+    assert np.max(np.abs(ev - ev2)) <= 1e-6
+    G = wl.grad_out
+    assert_grad_close(np.einsum("bm,bmj->j", G, jw), gw, 1e-4, "contracted J_w", 1e-6)
+    for b in range(8):
+        assert_grad_close(np.einsum("m,mj->j", G[b], jx[b]), gx[b], 1e-4, f"contracted J_x[{b}]", 1e-6)
