@@ -4,9 +4,11 @@
 //
 // Every candidate first has to reproduce a reference result (the per-gate
 // complex128 kernels on the same seeded inputs) within the tolerances of
-// the precision; only then is it timed.  The winner is installed as the
-// circuit's options and kept in a JSON cache keyed by the circuit's gate
-// list and observables, the batch size, the precision and the GPU's name.
+// the precision; only then is it timed.  The winner (the fastest, or among
+// candidates within 3% of it the one with the most contiguous low qubits)
+// is installed as the circuit's options and kept in a JSON cache keyed by
+// the circuit's gate list and observables, the batch size, the precision
+// and the GPU's name.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -262,9 +264,19 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  const Cand *win = nullptr;
+  // fastest passing candidate; among those within 3% of it (timing noise),
+  // prefer more contiguous low qubits (full 128-byte rows: fewer partially
+  // used lines fetched from HBM), then the larger tile
+  const Cand *fast = nullptr;
   for (const Cand &cd : cands)
-    if (cd.ok && (!win || cd.ms < win->ms)) win = &cd;
+    if (cd.ok && (!fast || cd.ms < fast->ms)) fast = &cd;
+  const Cand *win = fast;
+  if (fast)
+    for (const Cand &cd : cands)
+      if (cd.ok && cd.ms <= fast->ms * 1.03 &&
+          (cd.klo > win->klo || (cd.klo == win->klo && cd.kt > win->kt) ||
+           (cd.klo == win->klo && cd.kt == win->kt && cd.ms < win->ms)))
+        win = &cd;
   rep << ", \"cached\": false, \"candidates\": [";
   for (size_t k = 0; k < cands.size(); ++k) {
     const Cand &cd = cands[k];

@@ -21,7 +21,9 @@ def test_autotune_installs_fastest_passing_candidate(tmp_path, monkeypatch, prec
     assert not rep["cached"]
     ok = [x for x in rep["candidates"] if x["ok"]]
     assert ok, rep
-    best = min(ok, key=lambda x: x["ms"])
+    fastest = min(x["ms"] for x in ok)
+    near = [x for x in ok if x["ms"] <= fastest * 1.03]
+    best = max(near, key=lambda x: (x["klo"], x["tile"], -x["ms"]))
     assert (rep["tile"], rep["klo"], rep["jit"]) == (best["tile"], best["klo"], best["jit"])
     assert any(x["jit"] == 1 for x in rep["candidates"])
     rng = np.random.default_rng(7)
