@@ -36,7 +36,11 @@
  *
  * Gate record: int32 x 5 = type, q0, q1, src, index.
  *   type 0 RX, 1 RY, 2 RZ, 3 CNOT (q0 control, q1 target), 4 CZ;
- *   src 1 = inputs[index], 2 = weights[index].
+ *   src 1 = inputs[index], 2 = weights[index],
+ *   3 = weights[q1] * inputs[index] (trainable input scaling of the
+ *       ansatz of Sec. III-A, Eq. (7): angle lambda_j s_i; the chain rule
+ *       gives dL/dlambda_j = g s_i and dL/ds_i = g lambda_j for the angle
+ *       derivative g).
  */
 #include <complex.h>
 #include <math.h>
@@ -48,7 +52,7 @@
 typedef double complex cplx;
 
 enum { O_RX = 0, O_RY = 1, O_RZ = 2, O_CNOT = 3, O_CZ = 4 };
-enum { O_SRC_NONE = 0, O_SRC_INPUT = 1, O_SRC_WEIGHT = 2 };
+enum { O_SRC_NONE = 0, O_SRC_INPUT = 1, O_SRC_WEIGHT = 2, O_SRC_SCALED = 3 };
 
 typedef struct {
   int n;
@@ -73,7 +77,10 @@ static int check_circuit(const circ_t *c) {
     } else {
       if (g[3] == O_SRC_INPUT && (g[4] < 0 || g[4] >= c->n_inputs)) return -1;
       if (g[3] == O_SRC_WEIGHT && (g[4] < 0 || g[4] >= c->n_weights)) return -1;
-      if (g[3] != O_SRC_INPUT && g[3] != O_SRC_WEIGHT) return -1;
+      if (g[3] == O_SRC_SCALED &&
+          (g[4] < 0 || g[4] >= c->n_inputs || g[2] < 0 || g[2] >= c->n_weights))
+        return -1;
+      if (g[3] != O_SRC_INPUT && g[3] != O_SRC_WEIGHT && g[3] != O_SRC_SCALED) return -1;
     }
   }
   for (int m = 0; m < c->n_obs; ++m)
@@ -82,6 +89,7 @@ static int check_circuit(const circ_t *c) {
 }
 
 static double angle_of(const int32_t *g, const double *x_b, const double *w) {
+  if (g[3] == O_SRC_SCALED) return w[g[2]] * x_b[g[4]];
   return g[3] == O_SRC_INPUT ? x_b[g[4]] : w[g[4]];
 }
 
@@ -302,13 +310,19 @@ static int run_sample(const job_t *J, int b, int par) {
       const int32_t *gk = c->gates + 5 * k;
       if (!is_param(gk[0])) continue;
       double v = g[(int64_t)j * c->n_gates + k];
-      if (J->mode == 1) {
-        if (J->g_occ) J->g_occ[(int64_t)b * c->n_gates + k] = v;
-        if (gk[3] == O_SRC_WEIGHT) J->gw_per_sample[(int64_t)b * c->n_weights + gk[4]] += v;
-        else if (J->gx) J->gx[(int64_t)b * c->n_inputs + gk[4]] += v;
+      /* d angle / d parameter: 1, or for a scaled input the other factor */
+      double *wrow = J->mode == 1 ? J->gw_per_sample + (int64_t)b * c->n_weights
+                                  : J->jw + ((int64_t)b * M + j) * c->n_weights;
+      double *xrow = J->mode == 1 ? (J->gx ? J->gx + (int64_t)b * c->n_inputs : NULL)
+                                  : J->jx + ((int64_t)b * M + j) * c->n_inputs;
+      if (J->mode == 1 && J->g_occ) J->g_occ[(int64_t)b * c->n_gates + k] = v;
+      if (gk[3] == O_SRC_WEIGHT) {
+        wrow[gk[4]] += v;
+      } else if (gk[3] == O_SRC_INPUT) {
+        if (xrow) xrow[gk[4]] += v;
       } else {
-        if (gk[3] == O_SRC_WEIGHT) J->jw[((int64_t)b * M + j) * c->n_weights + gk[4]] += v;
-        else J->jx[((int64_t)b * M + j) * c->n_inputs + gk[4]] += v;
+        wrow[gk[2]] += v * x_b[gk[4]];
+        if (xrow) xrow[gk[4]] += v * J->w[gk[2]];
       }
     }
   }

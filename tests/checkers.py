@@ -38,6 +38,8 @@ def kron_on(n, ops: dict):
 
 
 def _angle(g, x_b, w):
+    if g[3] == W.SRC_SCALED:
+        return w[g[2]] * x_b[g[4]]
     return x_b[g[4]] if g[3] == W.SRC_INPUT else w[g[4]]
 
 
@@ -137,9 +139,68 @@ def bloch_grad(circ, x_b, w, G):
             g = circ.gates[k]
             if g[3] == W.SRC_WEIGHT:
                 gw[g[4]] += tot
-            else:
+            elif g[3] == W.SRC_INPUT:
                 gx[g[4]] += tot
+            else:  # angle w[q1] * x[idx]
+                gw[g[2]] += tot * x_b[g[4]]
+                gx[g[4]] += tot * w[g[2]]
     return gw, gx
+
+
+# --- untied circuits: every rotation occurrence its own parameter -------
+
+def angle_value(src: int, idx: int, q1: int, x_b: np.ndarray, w: np.ndarray) -> float:
+    """The number a rotation record selects (a lookup; for a scaled input the
+    product of the two slots it names)."""
+    if src == W.SRC_INPUT:
+        return float(x_b[idx])
+    if src == W.SRC_WEIGHT:
+        return float(w[idx])
+    return float(w[q1]) * float(x_b[idx])
+
+
+def untie(circ: W.Circuit, x: np.ndarray, w: np.ndarray):
+    """Give every parameterised gate occurrence its own weight slot.
+
+    Returns (circuit, weights, occ) where the new circuit reads every rotation
+    angle from its own weight slot k (in gate order) and ``occ[k]`` is the gate
+    index.  Input-fed angles are copied from the single sample ``x``.
+    Used by parameter-shift checks: the shift rule is exact only for a
+    parameter that enters exactly one exp(-i theta P / 2).
+    """
+    g = circ.gates.copy()
+    vals, occ = [], []
+    for k in range(g.shape[0]):
+        t, q0, q1, src, idx = (int(v) for v in g[k])
+        if t in W.PARAM_TYPES:
+            vals.append(angle_value(src, idx, q1, x, w))
+            g[k, 2] = 0
+            g[k, 3] = W.SRC_WEIGHT
+            g[k, 4] = len(occ)
+            occ.append(k)
+    c = W.Circuit(n=circ.n, gates=g, n_inputs=max(circ.n_inputs, 1),
+                n_weights=len(occ), masks=circ.masks.copy(),
+                name=circ.name + "_untied")
+    return c, np.array(vals, dtype=np.float64), occ
+
+
+def untie_to_inputs(circ: W.Circuit, x_b: np.ndarray, w: np.ndarray):
+    """Like `untie`, but every rotation occurrence k reads input slot k, so a
+    batch of rows can carry differently shifted angle vectors.  Returns
+    (circuit, base_row, occ) with base_row[k] the angle of occurrence k."""
+    g = circ.gates.copy()
+    vals, occ = [], []
+    for k in range(g.shape[0]):
+        t, q0, q1, src, idx = (int(v) for v in g[k])
+        if t in W.PARAM_TYPES:
+            vals.append(angle_value(src, idx, q1, x_b, w))
+            g[k, 2] = 0
+            g[k, 3] = W.SRC_INPUT
+            g[k, 4] = len(occ)
+            occ.append(k)
+    c = W.Circuit(n=circ.n, gates=g, n_inputs=len(occ), n_weights=0, masks=circ.masks.copy(),
+                name=circ.name + "_untied_inputs")
+    return c, np.array(vals, dtype=np.float64), occ
 
 
 # --- Heisenberg propagation of Z strings through CNOTs ---------------------

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+import checkers as C
 from gpu_helpers import assert_grad_close, assert_parity, run_gpu
 
 pytestmark = pytest.mark.gpu
@@ -74,7 +75,7 @@ def test_c2_adjoint_vs_parameter_shift():
     gw_ps = np.zeros_like(gw_adj)
     gx_ps = np.zeros_like(gx_adj)
     for b in range(wl.batch):
-        cu, base, occ = W.untie_to_inputs(wl.circuit, wl.inputs[b], wl.weights)
+        cu, base, occ = C.untie_to_inputs(wl.circuit, wl.inputs[b], wl.weights)
         qc = q.Circuit.from_workload(cu)
         K = len(occ)
         rows = np.repeat(base[None, :], 2 * K, axis=0)

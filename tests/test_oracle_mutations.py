@@ -24,8 +24,13 @@ MUTATIONS = {
     "bra_drops_G": ("dsum += J->G[(int64_t)b * M + m] * zsign(x, c->masks[m]);", "dsum += zsign(x, c->masks[m]);"),
     "cz_or_not_and": ("if ((x & ab) && (x & bb)) psi[x] = -psi[x];", "if ((x & ab) || (x & bb)) psi[x] = -psi[x];"),
     "last_gate_dropped": ("for (int k = 0; k < c->n_gates; ++k)\n    apply_gate", "for (int k = 0; k < c->n_gates - 1; ++k)\n    apply_gate"),
-    "grad_x_wrong_slot": ("else if (J->gx) J->gx[(int64_t)b * c->n_inputs + gk[4]] += v;",
-                          "else if (J->gx) J->gx[(int64_t)b * c->n_inputs + (gk[4] + 1) % c->n_inputs] += v;"),
+    "grad_x_wrong_slot": ("if (xrow) xrow[gk[4]] += v;\n",
+                          "if (xrow) xrow[(gk[4] + 1) % c->n_inputs] += v;\n"),
+    "scaled_angle_unscaled": ("if (g[3] == O_SRC_SCALED) return w[g[2]] * x_b[g[4]];",
+                              "if (g[3] == O_SRC_SCALED) return x_b[g[4]];"),
+    "scaled_grad_w_no_input_factor": ("wrow[gk[2]] += v * x_b[gk[4]];", "wrow[gk[2]] += v;"),
+    "scaled_grad_x_no_weight_factor": ("if (xrow) xrow[gk[4]] += v * J->w[gk[2]];",
+                                       "if (xrow) xrow[gk[4]] += v;"),
     "split_remainder_last": ("*lo = t * base + (t < rem ? t : rem);\n  *hi = *lo + base + (t < rem ? 1 : 0);",
                              "*lo = t * base + (t > T - 1 - rem ? t - (T - rem) : 0);\n  *hi = *lo + base + (t >= T - rem ? 1 : 0);"),
 }

@@ -185,7 +185,7 @@ def test_norm_and_uncompute():
 # --- parameter shift (exact) on the untied circuit -------------------------
 
 def _param_shift_occ(c, x_b, w, G_b):
-    cu, vals, occ = W.untie(c, x_b, w)
+    cu, vals, occ = C.untie(c, x_b, w)
     xb = np.asarray(x_b).reshape(1, -1)
     out = np.zeros(len(occ))
     for k in range(len(occ)):
@@ -228,7 +228,7 @@ def test_param_shift_c2_sample():
     wl = W.config_workload("c2", batch=1)
     c = wl.circuit
     _, _, _, gocc = oracle.vjp(c, wl.inputs, wl.weights, wl.grad_out, occurrences=True)
-    cu, vals, occ = W.untie(c, wl.inputs[0], wl.weights)
+    cu, vals, occ = C.untie(c, wl.inputs[0], wl.weights)
     rng = np.random.default_rng(0)
     for k in rng.choice(len(occ), size=8, replace=False):
         vp, vm = vals.copy(), vals.copy()
@@ -330,3 +330,109 @@ def test_amplitude_parallel_mode_matches_batch_mode():
     b = oracle.vjp(wl.circuit, wl.inputs, wl.weights, wl.grad_out, threads=4, par_mode=1)
     for u, v in zip(a, b):
         np.testing.assert_allclose(u, v, atol=1e-12)
+
+
+# --- trainable input scaling (Sec. III-A, Eq. (7)): angle lambda * s ---------
+
+@pytest.mark.parametrize("t", [W.RX, W.RY])
+def test_scaled_single_qubit_closed_form(t):
+    """RX/RY(lambda s) on |0>: <Z> = cos(lambda s); by the chain rule
+    d/dlambda = -s sin(lambda s) and d/ds = -lambda sin(lambda s)."""
+    c = W.Circuit(n=1, gates=np.array([[t, 0, 0, W.SRC_SCALED, 0]], np.int32),
+                  n_inputs=1, n_weights=1, masks=np.array([1], np.uint64))
+    for lam in (-1.3, 0.4, 1.0, 2.2):
+        for s in (-2.5, -0.3, 0.0, 0.9, 3.0):
+            x, w, G = np.array([[s]]), np.array([lam]), np.array([[0.7]])
+            ev, gw, gx = oracle.vjp(c, x, w, G)
+            assert abs(ev[0, 0] - math.cos(lam * s)) < 1e-14
+            assert abs(gw[0] - 0.7 * (-s * math.sin(lam * s))) < 1e-14
+            assert abs(gx[0, 0] - 0.7 * (-lam * math.sin(lam * s))) < 1e-14
+
+
+def test_scaled_product_states_match_bloch():
+    """Entangler-free circuits mixing plain and scaled angles: Bloch-vector
+    closed form and its analytic chain-rule gradient."""
+    rng = np.random.default_rng(11)
+    n, n_in, n_w = 4, 3, 5
+    g = []
+    for _ in range(18):
+        t, q = int(rng.integers(0, 3)), int(rng.integers(0, n))
+        r = rng.random()
+        if r < 0.5:
+            g.append((t, q, int(rng.integers(0, n_w)), W.SRC_SCALED, int(rng.integers(0, n_in))))
+        elif r < 0.75:
+            g.append((t, q, 0, W.SRC_WEIGHT, int(rng.integers(0, n_w))))
+        else:
+            g.append((t, q, 0, W.SRC_INPUT, int(rng.integers(0, n_in))))
+    c = W.Circuit(n=n, gates=np.array(g, np.int32), n_inputs=n_in, n_weights=n_w,
+                  masks=np.array([1, 2, 4, 8, 5, 15], np.uint64))
+    x = rng.uniform(-np.pi, np.pi, size=(3, n_in))
+    w = rng.uniform(-1.5, 1.5, size=n_w)
+    G = rng.uniform(-1, 1, size=(3, c.n_obs))
+    ev, gw, gx = oracle.vjp(c, x, w, G)
+    gw_ref = np.zeros_like(gw)
+    for b in range(3):
+        np.testing.assert_allclose(ev[b], C.bloch_expvals(c, x[b], w), atol=1e-13)
+        gwb, gxb = C.bloch_grad(c, x[b], w, G[b])
+        gw_ref += gwb
+        np.testing.assert_allclose(gx[b], gxb, atol=1e-12)
+    np.testing.assert_allclose(gw, gw_ref, atol=1e-12)
+
+
+@settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 2**31 - 1), n=st.integers(1, 5), ng=st.integers(1, 25))
+def test_scaled_brute_force_random_circuits(seed, n, ng):
+    rng = np.random.default_rng(seed)
+    c = W.random_circuit(rng, n, ng, scaled=0.5)
+    wl = W.random_workload(rng, c, 2)
+    ev = oracle.forward(c, wl.inputs, wl.weights)
+    for b in range(2):
+        np.testing.assert_allclose(ev[b], C.brute_expvals(c, wl.inputs[b], wl.weights), atol=1e-12)
+
+
+def test_paper_ansatz_parameter_count():
+    f = json.load(open(os.path.join(GOLDEN, "paper_facts.json")))["ansatz_parameters"]
+    c = W.paper_ansatz(f["n"], f["depth"])
+    assert c.n_weights == f["count"]
+    # linear in n and in d (Sec. III-A)
+    assert W.paper_ansatz(6, 3).n_weights * 2 == c.n_weights
+    assert W.paper_ansatz(12, 7).n_weights - W.paper_ansatz(12, 3).n_weights == 4 * 4 * 12
+
+
+@pytest.mark.parametrize("ent", ["chain", "ring"])
+def test_paper_ansatz_finite_differences(ent):
+    """Central differences of the forward pass (no reverse sweep involved)
+    against the adjoint VJP, for theta, lambda and the data inputs."""
+    wl = W.paper_workload(4, 2, batch=3, seed=5, entangler=ent)
+    c, x, w, G = wl.circuit, wl.inputs, wl.weights, wl.grad_out
+    _, gw, gx = oracle.vjp(c, x, w, G)
+    h = 1e-6
+    L = lambda xx, ww: float(np.sum(G * oracle.forward(c, xx, ww)))
+    for j in range(c.n_weights):
+        wp, wm = w.copy(), w.copy()
+        wp[j] += h
+        wm[j] -= h
+        assert abs((L(x, wp) - L(x, wm)) / (2 * h) - gw[j]) < 1e-8, j
+    for b in range(3):
+        for i in range(c.n_inputs):
+            xp, xm = x.copy(), x.copy()
+            xp[b, i] += h
+            xm[b, i] -= h
+            assert abs((L(xp, w) - L(xm, w)) / (2 * h) - gx[b, i]) < 1e-8, (b, i)
+
+
+def test_paper_ansatz_brute_force_and_jacobian():
+    """The ansatz state against the Kronecker-product unitary, and every row of
+    the Jacobian against the VJP with a one-hot upstream gradient."""
+    wl = W.paper_workload(4, 2, batch=2, seed=9)
+    c, x, w = wl.circuit, wl.inputs, wl.weights
+    ev = oracle.forward(c, x, w)
+    for b in range(2):
+        np.testing.assert_allclose(ev[b], C.brute_expvals(c, x[b], w), atol=1e-12)
+    _, jw, jx = oracle.jacobian(c, x, w)
+    for m in range(c.n_obs):
+        Gm = np.zeros((2, c.n_obs))
+        Gm[:, m] = 1.0
+        _, gw, gx = oracle.vjp(c, x, w, Gm)
+        np.testing.assert_allclose(jw[:, m, :].sum(axis=0), gw, atol=1e-12)
+        np.testing.assert_allclose(jx[:, m, :], gx, atol=1e-12)

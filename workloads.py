@@ -8,7 +8,9 @@ random numbers, and nothing that simulates a state.
 Gate record format (int32 x 5): ``type, q0, q1, src, index``.
 
 * ``type``: 0 RX, 1 RY, 2 RZ, 3 CNOT (q0 = control, q1 = target), 4 CZ.
-* ``src``: 0 none (entanglers), 1 input vector, 2 weight vector.
+* ``src``: 0 none (entanglers), 1 input vector, 2 weight vector, 3 weight-
+  scaled input: angle ``weights[q1] * inputs[index]`` (the trainable input
+  scaling lambda * s of the paper's ansatz, Sec. III-A Eq. (7)).
 * ``index``: slot in that vector.  Parameters are indexed in construction
   order, never alphabetically (paper Sec. II-C).
 
@@ -32,7 +34,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 RX, RY, RZ, CNOT, CZ = 0, 1, 2, 3, 4
-SRC_NONE, SRC_INPUT, SRC_WEIGHT = 0, 1, 2
+SRC_NONE, SRC_INPUT, SRC_WEIGHT, SRC_SCALED = 0, 1, 2, 3
 PARAM_TYPES = (RX, RY, RZ)
 
 
@@ -90,6 +92,67 @@ def layered_circuit(n: int, layers: int, entangler: str = "ring",
     gates = np.array(g, dtype=np.int32).reshape(-1, 5)
     return Circuit(n=n, gates=gates, n_inputs=n, n_weights=2 * n * layers,
                    masks=z_masks(n, extra_masks), name=name)
+
+
+def paper_ansatz(n: int, depth: int, entangler: str = "chain", n_obs: int | None = None,
+                 name: str = "") -> Circuit:
+    """The benchmark ansatz of Sec. III-A, Eq. (7): U = U_d ... U_1 with data
+    re-uploading and trainable input scaling.
+
+    The paper fixes only the ingredients (single-qubit rotations, nearest-
+    neighbour CNOTs, variational theta and scaling lambda, parameter count
+    linear in n and d) and the count 168 at n=12, d=3 (Tab. I caption), i.e.
+    (4d + 2) n.  The layout chosen here meets that count: block l applies
+    variational RZ(theta) and RY(theta) on every qubit, the CNOT entangler
+    (open chain i -> i+1, or ring), then the encoding RY(lambda s_q) and
+    RZ(lambda s_q) on every qubit q; a final variational RZ, RY layer closes
+    the circuit.  Weights are laid out as [theta (2n(d+1)), lambda (2nd)] so
+    that the two parameter sets can take separate hyperparameters (Sec. II-C).
+    Observables: Z on qubit q for q < n_obs (default n).
+    """
+    if entangler not in ("chain", "ring"):
+        raise ValueError(entangler)
+    n_theta = 2 * n * (depth + 1)
+    g = []
+
+    def variational(l):
+        for q in range(n):
+            g.append((RZ, q, 0, SRC_WEIGHT, l * 2 * n + q))
+        for q in range(n):
+            g.append((RY, q, 0, SRC_WEIGHT, l * 2 * n + n + q))
+
+    for l in range(depth):
+        variational(l)
+        if n >= 2:
+            last = n if entangler == "ring" and n >= 3 else n - 1
+            for i in range(last):
+                g.append((CNOT, i, (i + 1) % n, SRC_NONE, 0))
+        for q in range(n):
+            g.append((RY, q, n_theta + l * 2 * n + q, SRC_SCALED, q))
+        for q in range(n):
+            g.append((RZ, q, n_theta + l * 2 * n + n + q, SRC_SCALED, q))
+    variational(depth)
+    M = n if n_obs is None else n_obs
+    return Circuit(n=n, gates=np.array(g, dtype=np.int32).reshape(-1, 5), n_inputs=n,
+                   n_weights=n_theta + 2 * n * depth,
+                   masks=np.array([1 << (q % n) for q in range(M)], dtype=np.uint64),
+                   name=name or f"paper_n{n}_d{depth}_{entangler}")
+
+
+def paper_workload(n: int, depth: int, batch: int, seed: int, entangler: str = "chain",
+                   n_obs: int | None = None) -> Workload:
+    """Seeded inputs for `paper_ansatz`: theta ~ U(-pi, pi), lambda ~ U(0.5, 1.5)
+    (scalings near one), inputs s ~ U(-pi, pi), G ~ U(-1, 1), drawn in that
+    order."""
+    circ = paper_ansatz(n, depth, entangler, n_obs)
+    rng = np.random.default_rng(seed)
+    n_theta = 2 * n * (depth + 1)
+    th = rng.uniform(-math.pi, math.pi, size=n_theta)
+    lam = rng.uniform(0.5, 1.5, size=circ.n_weights - n_theta)
+    x = rng.uniform(-math.pi, math.pi, size=(batch, circ.n_inputs))
+    G = rng.uniform(-1.0, 1.0, size=(batch, circ.n_obs))
+    return Workload(circuit=circ, batch=batch, inputs=x, weights=np.concatenate([th, lam]),
+                    grad_out=G, meta=dict(theta=n_theta))
 
 
 def _draw(rng, circ: Circuit, batch: int):
@@ -152,15 +215,19 @@ def uneven_items(count: int = 1024, seed: int = 1004, n_range=(8, 16),
 
 
 def random_circuit(rng, n: int, n_gates: int, n_inputs: int = 3,
-                   n_weights: int = 5, n_obs: int = 3) -> Circuit:
+                   n_weights: int = 5, n_obs: int = 3, scaled: float = 0.0) -> Circuit:
     """Random gate list over all gate types and random qubit pairs, with
-    random parameter slots (parameters may be shared between gates)."""
+    random parameter slots (parameters may be shared between gates).  With
+    ``scaled`` > 0 that fraction of the rotations reads a weight-scaled input."""
     g = []
     for _ in range(n_gates):
         t = int(rng.integers(0, 5)) if n >= 2 else int(rng.integers(0, 3))
         if t in PARAM_TYPES:
             q = int(rng.integers(0, n))
-            if rng.random() < 0.4:
+            if scaled > 0 and rng.random() < scaled:
+                g.append((t, q, int(rng.integers(0, n_weights)), SRC_SCALED,
+                          int(rng.integers(0, n_inputs))))
+            elif rng.random() < 0.4:
                 g.append((t, q, 0, SRC_INPUT, int(rng.integers(0, n_inputs))))
             else:
                 g.append((t, q, 0, SRC_WEIGHT, int(rng.integers(0, n_weights))))
@@ -176,45 +243,3 @@ def random_circuit(rng, n: int, n_gates: int, n_inputs: int = 3,
 def random_workload(rng, circ: Circuit, batch: int) -> Workload:
     x, w, G = _draw(rng, circ, batch)
     return Workload(circuit=circ, batch=batch, inputs=x, weights=w, grad_out=G)
-
-
-def untie(circ: Circuit, x: np.ndarray, w: np.ndarray):
-    """Give every parameterised gate occurrence its own weight slot.
-
-    Returns (circuit, weights, occ) where the new circuit reads every rotation
-    angle from its own weight slot k (in gate order) and ``occ[k]`` is the gate
-    index.  Input-fed angles are copied from the single sample ``x``.
-    Used by parameter-shift checks: the shift rule is exact only for a
-    parameter that enters exactly one exp(-i theta P / 2).
-    """
-    g = circ.gates.copy()
-    vals, occ = [], []
-    for k in range(g.shape[0]):
-        t, q0, q1, src, idx = (int(v) for v in g[k])
-        if t in PARAM_TYPES:
-            vals.append(x[idx] if src == SRC_INPUT else w[idx])
-            g[k, 3] = SRC_WEIGHT
-            g[k, 4] = len(occ)
-            occ.append(k)
-    c = Circuit(n=circ.n, gates=g, n_inputs=max(circ.n_inputs, 1),
-                n_weights=len(occ), masks=circ.masks.copy(),
-                name=circ.name + "_untied")
-    return c, np.array(vals, dtype=np.float64), occ
-
-
-def untie_to_inputs(circ: Circuit, x_b: np.ndarray, w: np.ndarray):
-    """Like `untie`, but every rotation occurrence k reads input slot k, so a
-    batch of rows can carry differently shifted angle vectors.  Returns
-    (circuit, base_row, occ) with base_row[k] the angle of occurrence k."""
-    g = circ.gates.copy()
-    vals, occ = [], []
-    for k in range(g.shape[0]):
-        t, q0, q1, src, idx = (int(v) for v in g[k])
-        if t in PARAM_TYPES:
-            vals.append(x_b[idx] if src == SRC_INPUT else w[idx])
-            g[k, 3] = SRC_INPUT
-            g[k, 4] = len(occ)
-            occ.append(k)
-    c = Circuit(n=circ.n, gates=g, n_inputs=len(occ), n_weights=0, masks=circ.masks.copy(),
-                name=circ.name + "_untied_inputs")
-    return c, np.array(vals, dtype=np.float64), occ
