@@ -59,7 +59,7 @@ extern "C" {
                                     this (circuit, batch, precision) */
 
 enum { QTM_RX = 0, QTM_RY = 1, QTM_RZ = 2, QTM_CNOT = 3, QTM_CZ = 4 };
-enum { QTM_SRC_NONE = 0, QTM_SRC_INPUT = 1, QTM_SRC_WEIGHT = 2 };
+enum { QTM_SRC_NONE = 0, QTM_SRC_INPUT = 1, QTM_SRC_WEIGHT = 2, QTM_SRC_SCALED = 3 };
 enum { QTM_C64 = 0, QTM_C128 = 1 }; /* state amplitudes: complex float / complex double */
 
 /* Kernel path (option QTM_OPT_PATH). */
@@ -80,7 +80,12 @@ enum {
 };
 
 /* One gate.  Rotations (RX, RY, RZ): q0 = qubit, src = QTM_SRC_INPUT or
- * QTM_SRC_WEIGHT, index = slot in that vector (q1 ignored).
+ * QTM_SRC_WEIGHT, index = slot in that vector (q1 ignored); or
+ * src = QTM_SRC_SCALED: the angle is weights[q1] * inputs[index], the
+ * trainable input scaling lambda * s of the paper's ansatz (Sec. III-A,
+ * Eq. (7)); the gradients follow the chain rule (dL/dweights[q1] gains
+ * g * inputs[index], dL/dinputs[index] gains g * weights[q1] for the angle
+ * derivative g).
  * CNOT: q0 = control, q1 = target.  CZ: q0, q1 (symmetric).  src/index
  * ignored for entanglers. */
 typedef struct {

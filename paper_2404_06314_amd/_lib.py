@@ -19,7 +19,7 @@ QTM_ERR_HIP = -4
 QTM_ERR_STATE = -5
 
 QTM_RX, QTM_RY, QTM_RZ, QTM_CNOT, QTM_CZ = 0, 1, 2, 3, 4
-QTM_SRC_NONE, QTM_SRC_INPUT, QTM_SRC_WEIGHT = 0, 1, 2
+QTM_SRC_NONE, QTM_SRC_INPUT, QTM_SRC_WEIGHT, QTM_SRC_SCALED = 0, 1, 2, 3
 QTM_C64, QTM_C128 = 0, 1
 QTM_PATH_AUTO, QTM_PATH_PLAIN, QTM_PATH_FUSED = 0, 1, 2
 QTM_OPT_PATH, QTM_OPT_TILE_QUBITS, QTM_OPT_LOW_QUBITS, QTM_OPT_RENORM, QTM_OPT_TIMING = 0, 1, 2, 3, 4

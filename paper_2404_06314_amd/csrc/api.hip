@@ -175,34 +175,24 @@ int ensure_device(qtm_circuit_t c) {
   g.n_weights = d.n_weights;
   g.n_obs = (int)d.masks.size();
   g.n_occ = (int)d.occ_gate.size();
-  std::vector<int32_t> src, idx;
+  std::vector<int32_t> src, idx, widx;
   for (int k : d.occ_gate) {
     src.push_back(d.gates[k].src);
     idx.push_back(d.gates[k].index);
+    widx.push_back(d.gates[k].src == S_SCALED ? d.gates[k].q1 : 0);
   }
-  // CSR: parameter slot -> occurrences (construction order)
-  std::vector<int32_t> wp(d.n_weights + 1, 0), xp(d.n_inputs + 1, 0), wl, xl;
-  std::vector<std::vector<int32_t>> wlist(d.n_weights), xlist(d.n_inputs);
-  for (size_t k = 0; k < d.occ_gate.size(); ++k) {
-    const Gate &gt = d.gates[d.occ_gate[k]];
-    (gt.src == S_WEIGHT ? wlist[gt.index] : xlist[gt.index]).push_back((int32_t)k);
-  }
-  for (int j = 0; j < d.n_weights; ++j) {
-    wp[j + 1] = wp[j] + (int)wlist[j].size();
-    wl.insert(wl.end(), wlist[j].begin(), wlist[j].end());
-  }
-  for (int i = 0; i < d.n_inputs; ++i) {
-    xp[i + 1] = xp[i] + (int)xlist[i].size();
-    xl.insert(xl.end(), xlist[i].begin(), xlist[i].end());
-  }
+  const ParamCsr pc = param_csr(d);
   int rc;
   if ((rc = upload(&g.masks, d.masks, c->owned))) return rc;
   if ((rc = upload(&g.occ_src, src, c->owned))) return rc;
   if ((rc = upload(&g.occ_idx, idx, c->owned))) return rc;
-  if ((rc = upload(&g.w_ptr, wp, c->owned))) return rc;
-  if ((rc = upload(&g.w_list, wl, c->owned))) return rc;
-  if ((rc = upload(&g.x_ptr, xp, c->owned))) return rc;
-  if ((rc = upload(&g.x_list, xl, c->owned))) return rc;
+  if ((rc = upload(&g.occ_widx, widx, c->owned))) return rc;
+  if ((rc = upload(&g.w_ptr, pc.w_ptr, c->owned))) return rc;
+  if ((rc = upload(&g.w_list, pc.w_list, c->owned))) return rc;
+  if ((rc = upload(&g.w_fac, pc.w_fac, c->owned))) return rc;
+  if ((rc = upload(&g.x_ptr, pc.x_ptr, c->owned))) return rc;
+  if ((rc = upload(&g.x_list, pc.x_list, c->owned))) return rc;
+  if ((rc = upload(&g.x_fac, pc.x_fac, c->owned))) return rc;
   c->uploaded = true;
   return QTM_OK;
 }
@@ -393,10 +383,10 @@ int run_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
     e = launch_half_angles(d, batch, inputs, weights, (double2 *)c->cs.p, s);
     if (e == hipSuccess)
       e = precision == QTM_C64
-              ? plain_backward<float>(d, c->hinfo, batch, (double2 *)c->cs.p, psi, c->lam.p,
+              ? plain_backward<float>(d, c->hinfo, batch, (double2 *)c->cs.p, inputs, weights, psi, c->lam.p,
                                       grad_expvals, (double *)c->part.p, (double *)c->gocc.p,
                                       grad_weights, grad_inputs, s)
-              : plain_backward<double>(d, c->hinfo, batch, (double2 *)c->cs.p, psi, c->lam.p,
+              : plain_backward<double>(d, c->hinfo, batch, (double2 *)c->cs.p, inputs, weights, psi, c->lam.p,
                                        grad_expvals, (double *)c->part.p, (double *)c->gocc.p,
                                        grad_weights, grad_inputs, s);
   }
@@ -570,7 +560,8 @@ int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double
     if ((rc = run_backward(c, batch, precision, inputs, weights, (double *)c->jac_G.p, c->state_ws.p,
                            (double *)c->jac_gw.p, nullptr, s)))
       return rc;
-    if ((e = launch_scatter_jac(d, batch, (double *)c->gocc.p, m, jac_weights, jac_inputs, s)))
+    if ((e = launch_scatter_jac(d, batch, (double *)c->gocc.p, inputs, weights, m, jac_weights,
+                                  jac_inputs, s)))
       return hip_fail(e, "jacobian scatter");
   }
   return QTM_OK;

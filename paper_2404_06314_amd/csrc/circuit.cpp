@@ -63,8 +63,14 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
           err = buf;
           return QTM_ERR_INVALID_ARG;
         }
+      } else if (g.src == S_SCALED) {
+        if (g.index < 0 || g.index >= n_inputs || g.q1 < 0 || g.q1 >= n_weights) {
+          snprintf(buf, sizeof buf, "gate %d: scaled input %d / weight %d out of range", k, g.index, g.q1);
+          err = buf;
+          return QTM_ERR_INVALID_ARG;
+        }
       } else {
-        snprintf(buf, sizeof buf, "gate %d: rotation needs src INPUT or WEIGHT", k);
+        snprintf(buf, sizeof buf, "gate %d: rotation needs src INPUT, WEIGHT or SCALED", k);
         err = buf;
         return QTM_ERR_INVALID_ARG;
       }
@@ -84,7 +90,7 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
     if (!is_rotation(g.type)) {
       c.src = S_NONE;
       c.index = 0;
-    } else {
+    } else if (g.src != S_SCALED) {
       c.q1 = 0;
     }
     out.gates.push_back(c);
@@ -104,6 +110,37 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
       out.occ_gate.push_back((int32_t)k);
     }
   return QTM_OK;
+}
+
+ParamCsr param_csr(const CircuitDesc &c) {
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> wl(c.n_weights), xl(c.n_inputs);
+  for (size_t k = 0; k < c.occ_gate.size(); ++k) {
+    const Gate &g = c.gates[c.occ_gate[k]];
+    const int32_t occ = (int32_t)k;
+    if (g.src == S_WEIGHT) {
+      wl[g.index].push_back({occ, -1});
+    } else if (g.src == S_INPUT) {
+      xl[g.index].push_back({occ, -1});
+    } else {
+      wl[g.q1].push_back({occ, g.index});
+      xl[g.index].push_back({occ, g.q1});
+    }
+  }
+  ParamCsr r;
+  auto put = [](const std::vector<std::vector<std::pair<int32_t, int32_t>>> &lists,
+                std::vector<int32_t> &ptr, std::vector<int32_t> &lst, std::vector<int32_t> &fac) {
+    ptr.assign(1, 0);
+    for (const auto &l : lists) {
+      for (const auto &e : l) {
+        lst.push_back(e.first);
+        fac.push_back(e.second);
+      }
+      ptr.push_back((int32_t)lst.size());
+    }
+  };
+  put(wl, r.w_ptr, r.w_list, r.w_fac);
+  put(xl, r.x_ptr, r.x_list, r.x_fac);
+  return r;
 }
 
 // --------------------------------------------------------------------------
@@ -642,6 +679,7 @@ std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostP
       h.blk.push_back(gt.type);
       h.blk.push_back(gt.src);
       h.blk.push_back(gt.index);
+      h.blk.push_back(gt.src == S_SCALED ? gt.q1 : 0);
       h.blk.push_back(occ);
       h.occ_gslot[occ] = o.gslot;
     }

@@ -30,7 +30,7 @@
 namespace qtm {
 
 enum GateType : int32_t { G_RX = 0, G_RY = 1, G_RZ = 2, G_CNOT = 3, G_CZ = 4 };
-enum GateSrc : int32_t { S_NONE = 0, S_INPUT = 1, S_WEIGHT = 2 };
+enum GateSrc : int32_t { S_NONE = 0, S_INPUT = 1, S_WEIGHT = 2, S_SCALED = 3 };
 
 struct Gate {
   int32_t type, q0, q1, src, index;
@@ -84,6 +84,16 @@ struct CircuitDesc {
   std::vector<int32_t> gate_occ;  // gate -> occurrence or -1
 };
 
+// Parameter slot -> rotation occurrences (CSR, construction order).  A
+// weight-scaled input (S_SCALED) occurs in both lists; its entry carries the
+// slot of the other factor of the angle: in the weight list the input index
+// (d angle / d weight = inputs[b][fac]), in the input list the weight index
+// (d angle / d input = weights[fac]); -1 where the derivative is 1.
+struct ParamCsr {
+  std::vector<int32_t> w_ptr, w_list, w_fac, x_ptr, x_list, x_fac;
+};
+ParamCsr param_csr(const CircuitDesc &c);
+
 // Returns 0 or a QTM_ERR_* code with a message.
 int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_inputs,
                        int32_t n_weights, const uint64_t *masks, int32_t n_obs,
@@ -115,7 +125,7 @@ Program encode_program(const CircuitDesc &c, const Plan &p);
 struct HostPlan {
   int32_t kt = 0, klo = 0, n_blocks = 0, n_gslots = 0, max_gslots = 0, n_sweeps = 0;
   Program prog;
-  std::vector<int32_t> blk;        // per block: [q, ng, (type, src, idx, occ) x ng]
+  std::vector<int32_t> blk;        // per block: [q, ng, (type, src, idx, widx, occ) x ng]
   std::vector<int32_t> blk_off;    // block -> offset in blk
   std::vector<int32_t> occ_gslot;  // occurrence -> gradient slot
   std::vector<float> obs_sgn;      // [(M+1)][16] signs of the last forward stage

@@ -275,7 +275,7 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return launch_scatter(d, B, gocc, gw, gx, s);
+  return launch_scatter(d, B, gocc, x, w, gw, gx, s);
 }
 
 template hipError_t fused_forward<float>(const DevCircuit &, const DevPlan &, int, const double *,

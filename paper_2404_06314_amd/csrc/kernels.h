@@ -16,8 +16,10 @@ struct JitSweeps;
 struct DevCircuit {
   int n = 0, n_inputs = 0, n_weights = 0, n_obs = 0, n_occ = 0;
   uint64_t *masks = nullptr;
-  int32_t *occ_src = nullptr, *occ_idx = nullptr;
-  int32_t *w_ptr = nullptr, *w_list = nullptr, *x_ptr = nullptr, *x_list = nullptr;
+  int32_t *occ_src = nullptr, *occ_idx = nullptr, *occ_widx = nullptr;
+  // parameter slot -> occurrences with the other factor of a scaled angle
+  int32_t *w_ptr = nullptr, *w_list = nullptr, *w_fac = nullptr;
+  int32_t *x_ptr = nullptr, *x_list = nullptr, *x_fac = nullptr;
 };
 
 struct HostCircuitInfo {
@@ -53,20 +55,21 @@ hipError_t launch_half_angles(const DevCircuit &d, int B, const double *x, const
                               double2 *cs, hipStream_t s);
 hipError_t launch_obs_final(const double *part, int B, int nblk, int M, double *out,
                             bool normalise, hipStream_t s);
-hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, double *gw, double *gx,
-                          hipStream_t s);
+hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, const double *x,
+                          const double *w, double *gw, double *gx, hipStream_t s);
 size_t plain_part_doubles(const DevCircuit &d, int B);
 hipError_t launch_onehot(double *G, int B, int M, int m, hipStream_t s);
-hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, int m, double *jw,
-                              double *jx, hipStream_t s);
+hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, const double *x,
+                              const double *w, int m, double *jw, double *jx, hipStream_t s);
 
 template <typename R>
 hipError_t plain_forward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,
                          void *state, double *part, double *out, bool normalise, hipStream_t s);
 template <typename R>
 hipError_t plain_backward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,
-                          void *state, void *lam, const double *G, double *part, double *gocc,
-                          double *gw, double *gx, hipStream_t s);
+                          const double *x, const double *w, void *state, void *lam,
+                          const double *G, double *part, double *gocc, double *gw, double *gx,
+                          hipStream_t s);
 
 // Fused path workspace sizes and entry points.
 int fused_wg_per_sample(int n, int kt);

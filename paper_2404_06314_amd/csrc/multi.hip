@@ -232,7 +232,8 @@ __global__ void __launch_bounds__(256) k_multi_fwd_final(MultiStatic ms, MultiIO
 }
 
 // Per occurrence k: (px TX + py TY + pz TZ) / norm, then every input and
-// weight slot of the item sums its occurrences (construction order).
+// weight slot of the item sums its occurrences (construction order), times
+// the other factor for a weight-scaled input angle.
 __global__ void __launch_bounds__(256) k_multi_bwd_final(MultiStatic ms, MultiIO io) {
   const int64_t *I = ms.items + (int64_t)blockIdx.x * MI_WORDS;
   const int T = (int)I[MI_NTILES], nocc = (int)I[MI_NOCC];
@@ -259,15 +260,18 @@ __global__ void __launch_bounds__(256) k_multi_bwd_final(MultiStatic ms, MultiIO
   const int nw = (int)I[MI_NW], nin = (int)I[MI_NIN];
   const int32_t *wp = ms.csr + I[MI_WPTR], *wl = ms.csr + I[MI_WLIST];
   const int32_t *xp = ms.csr + I[MI_XPTR], *xl = ms.csr + I[MI_XLIST];
+  const int32_t *wf = wl + wp[nw], *xf = xl + xp[nin];
+  const double *x = io.x ? io.x + I[MI_INOFF] : nullptr;
+  const double *w = io.w ? io.w + I[MI_WOFF] : nullptr;
   for (int j = threadIdx.x; j < nw + nin; j += blockDim.x) {
     if (j < nw) {
       double acc = 0.0;
-      for (int e = wp[j]; e < wp[j + 1]; ++e) acc += gocc[wl[e]];
+      for (int e = wp[j]; e < wp[j + 1]; ++e) acc += wf[e] < 0 ? gocc[wl[e]] : gocc[wl[e]] * x[wf[e]];
       io.gw[I[MI_WOFF] + j] = bad ? NAN : acc;
     } else if (io.gx) {
       const int i = j - nw;
       double acc = 0.0;
-      for (int e = xp[i]; e < xp[i + 1]; ++e) acc += gocc[xl[e]];
+      for (int e = xp[i]; e < xp[i + 1]; ++e) acc += xf[e] < 0 ? gocc[xl[e]] : gocc[xl[e]] * w[xf[e]];
       io.gx[I[MI_INOFF] + i] = bad ? NAN : acc;
     }
   }
@@ -401,22 +405,19 @@ std::string MultiRuntime::build(const std::vector<MultiItemIn> &items_in) {
     blk.insert(blk.end(), pi.hp.blk_off.begin(), pi.hp.blk_off.end());
     pi.occg = (int64_t)occg.size();
     occg.insert(occg.end(), pi.hp.occ_gslot.begin(), pi.hp.occ_gslot.end());
-    // parameter slot -> occurrences, construction order
-    std::vector<std::vector<int32_t>> wl(d.n_weights), xl(d.n_inputs);
-    for (size_t k = 0; k < d.occ_gate.size(); ++k) {
-      const Gate &g = d.gates[d.occ_gate[k]];
-      (g.src == S_WEIGHT ? wl[g.index] : xl[g.index]).push_back((int32_t)k);
-    }
-    auto put_csr = [&](const std::vector<std::vector<int32_t>> &lists, int64_t &ptr, int64_t &lst) {
+    // parameter slot -> occurrences, construction order; each list is
+    // followed by its chain-rule factor slots (same length)
+    const ParamCsr pc = param_csr(d);
+    auto put_csr = [&](const std::vector<int32_t> &ptr_, const std::vector<int32_t> &lst_,
+                       const std::vector<int32_t> &fac_, int64_t &ptr, int64_t &lst) {
       ptr = (int64_t)csr.size();
-      int32_t acc = 0;
-      csr.push_back(0);
-      for (const auto &l : lists) csr.push_back(acc += (int32_t)l.size());
+      csr.insert(csr.end(), ptr_.begin(), ptr_.end());
       lst = (int64_t)csr.size();
-      for (const auto &l : lists) csr.insert(csr.end(), l.begin(), l.end());
+      csr.insert(csr.end(), lst_.begin(), lst_.end());
+      csr.insert(csr.end(), fac_.begin(), fac_.end());
     };
-    put_csr(wl, pi.wptr, pi.wlist);
-    put_csr(xl, pi.xptr, pi.xlist);
+    put_csr(pc.w_ptr, pc.w_list, pc.w_fac, pi.wptr, pi.wlist);
+    put_csr(pc.x_ptr, pc.x_list, pc.x_fac, pi.xptr, pi.xlist);
     // per-sweep cost estimates (tile loads + stages) for the list schedule
     seen.emplace(key, (int)progs.size());
     item_prog.push_back((int)progs.size());

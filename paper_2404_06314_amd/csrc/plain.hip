@@ -12,14 +12,18 @@ namespace qtm {
 
 constexpr int kThreads = 256;
 
-// (cos(t/2), sin(t/2)) in FP64 for every (sample, rotation occurrence).
+// (cos(t/2), sin(t/2)) in FP64 for every (sample, rotation occurrence); the
+// angle is an input, a weight, or a weight-scaled input (Eq. (7)).
 __global__ void k_half_angles(int B, int n_occ, const int32_t *__restrict__ occ_src,
-                              const int32_t *__restrict__ occ_idx, const double *__restrict__ x,
-                              int n_in, const double *__restrict__ w, double2 *__restrict__ cs) {
+                              const int32_t *__restrict__ occ_idx, const int32_t *__restrict__ occ_widx,
+                              const double *__restrict__ x, int n_in, const double *__restrict__ w,
+                              double2 *__restrict__ cs) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)B * n_occ) return;
   int b = (int)(i / n_occ), k = (int)(i % n_occ);
-  double t = occ_src[k] == 1 ? x[(int64_t)b * n_in + occ_idx[k]] : w[occ_idx[k]];
+  const int src = occ_src[k];
+  double t = src == 2 ? w[occ_idx[k]] : x[(int64_t)b * n_in + occ_idx[k]];
+  if (src == 3) t = w[occ_widx[k]] * t;
   double s, c;
   sincos(0.5 * t, &s, &c);
   cs[i] = make_double2(c, s);
@@ -230,19 +234,27 @@ __global__ void k_plain_grad_final(const double *__restrict__ part, int B, int n
   gocc[i] = acc;
 }
 
-// Scatter per-occurrence derivatives into parameter slots (fixed order):
-// grad_w[j] = sum_b sum_{k in occ(w_j)} gocc[b][k];  grad_x[b][i] = sum_{k in occ(x_i)} gocc[b][k].
+// Scatter per-occurrence angle derivatives into parameter slots (fixed
+// order), with the chain-rule factor of a scaled angle w[j] * x[b][i]:
+// grad_w[j] = sum_b sum_{k in occ(w_j)} gocc[b][k] * (x[b][fac_k] or 1);
+// grad_x[b][i] = sum_{k in occ(x_i)} gocc[b][k] * (w[fac_k] or 1).
 // dL/dw_j = sum over the batch and over the occurrences of weight j: one
 // workgroup per weight, samples over the threads, fixed-order sums.
 __global__ void __launch_bounds__(256) k_scatter_w(const double *__restrict__ gocc, int B, int n_occ,
                                                    const int32_t *__restrict__ w_ptr,
                                                    const int32_t *__restrict__ w_list,
+                                                   const int32_t *__restrict__ w_fac,
+                                                   const double *__restrict__ x, int n_in,
                                                    double *__restrict__ gw) {
   __shared__ double sh[4];
   const int j = blockIdx.x;
   double acc = 0.0;
   for (int b = threadIdx.x; b < B; b += blockDim.x)
-    for (int e = w_ptr[j]; e < w_ptr[j + 1]; ++e) acc += gocc[(int64_t)b * n_occ + w_list[e]];
+    for (int e = w_ptr[j]; e < w_ptr[j + 1]; ++e) {
+      const int f = w_fac[e];
+      const double g = gocc[(int64_t)b * n_occ + w_list[e]];
+      acc += f < 0 ? g : g * x[(int64_t)b * n_in + f];
+    }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) gw[j] = acc;
 }
@@ -250,12 +262,17 @@ __global__ void __launch_bounds__(256) k_scatter_w(const double *__restrict__ go
 // dL/dx[b][i] = sum over the occurrences of input i (per sample).
 __global__ void k_scatter_x(const double *__restrict__ gocc, int B, int n_occ,
                             const int32_t *__restrict__ x_ptr, const int32_t *__restrict__ x_list,
+                            const int32_t *__restrict__ x_fac, const double *__restrict__ w,
                             int n_in, double *__restrict__ gx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)B * n_in) return;
   const int b = (int)(i / n_in), k = (int)(i % n_in);
   double acc = 0.0;
-  for (int e = x_ptr[k]; e < x_ptr[k + 1]; ++e) acc += gocc[(int64_t)b * n_occ + x_list[e]];
+  for (int e = x_ptr[k]; e < x_ptr[k + 1]; ++e) {
+    const int f = x_fac[e];
+    const double g = gocc[(int64_t)b * n_occ + x_list[e]];
+    acc += f < 0 ? g : g * w[f];
+  }
   gx[i] = acc;
 }
 
@@ -269,9 +286,11 @@ __global__ void k_onehot(double *__restrict__ G, int B, int M, int m) {
 // rotation occurrences (no sum over the batch).
 __global__ void k_scatter_jac(const double *__restrict__ gocc, int B, int n_occ,
                               const int32_t *__restrict__ w_ptr, const int32_t *__restrict__ w_list,
-                              int n_w, const int32_t *__restrict__ x_ptr,
-                              const int32_t *__restrict__ x_list, int n_in, int m, int M,
-                              double *__restrict__ jw, double *__restrict__ jx) {
+                              const int32_t *__restrict__ w_fac, int n_w,
+                              const int32_t *__restrict__ x_ptr, const int32_t *__restrict__ x_list,
+                              const int32_t *__restrict__ x_fac, int n_in,
+                              const double *__restrict__ x, const double *__restrict__ w, int m,
+                              int M, double *__restrict__ jw, double *__restrict__ jx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int per = n_w + (jx ? n_in : 0);
   if (i >= (int64_t)B * per) return;
@@ -279,11 +298,17 @@ __global__ void k_scatter_jac(const double *__restrict__ gocc, int B, int n_occ,
   const double *g = gocc + (int64_t)b * n_occ;
   double acc = 0.0;
   if (j < n_w) {
-    for (int e = w_ptr[j]; e < w_ptr[j + 1]; ++e) acc += g[w_list[e]];
+    for (int e = w_ptr[j]; e < w_ptr[j + 1]; ++e) {
+      const int f = w_fac[e];
+      acc += f < 0 ? g[w_list[e]] : g[w_list[e]] * x[(int64_t)b * n_in + f];
+    }
     jw[((int64_t)b * M + m) * n_w + j] = acc;
   } else {
     const int k = j - n_w;
-    for (int e = x_ptr[k]; e < x_ptr[k + 1]; ++e) acc += g[x_list[e]];
+    for (int e = x_ptr[k]; e < x_ptr[k + 1]; ++e) {
+      const int f = x_fac[e];
+      acc += f < 0 ? g[x_list[e]] : g[x_list[e]] * w[f];
+    }
     jx[((int64_t)b * M + m) * n_in + k] = acc;
   }
 }
@@ -296,8 +321,8 @@ static inline unsigned nb(int64_t work) { return (unsigned)((work + kThreads - 1
 hipError_t launch_half_angles(const DevCircuit &d, int B, const double *x, const double *w,
                               double2 *cs, hipStream_t s) {
   if (d.n_occ == 0) return hipSuccess;
-  k_half_angles<<<nb((int64_t)B * d.n_occ), kThreads, 0, s>>>(B, d.n_occ, d.occ_src, d.occ_idx, x,
-                                                              d.n_inputs, w, cs);
+  k_half_angles<<<nb((int64_t)B * d.n_occ), kThreads, 0, s>>>(B, d.n_occ, d.occ_src, d.occ_idx,
+                                                              d.occ_widx, x, d.n_inputs, w, cs);
   return hipGetLastError();
 }
 
@@ -335,8 +360,9 @@ hipError_t plain_forward(const DevCircuit &d, const HostCircuitInfo &h, int B, c
 
 template <typename R>
 hipError_t plain_backward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,
-                          void *state, void *lam_buf, const double *G, double *part, double *gocc,
-                          double *gw, double *gx, hipStream_t s) {
+                          const double *x, const double *w, void *state, void *lam_buf,
+                          const double *G, double *part, double *gocc, double *gw, double *gx,
+                          hipStream_t s) {
   Cx<R> *psi = (Cx<R> *)state, *lam = (Cx<R> *)lam_buf;
   const int n = d.n;
   const int64_t dim = (int64_t)1 << n;
@@ -357,7 +383,7 @@ hipError_t plain_backward(const DevCircuit &d, const HostCircuitInfo &h, int B, 
   }
   if (d.n_occ > 0)
     k_plain_grad_final<<<nb((int64_t)B * d.n_occ), kThreads, 0, s>>>(part, B, d.n_occ, nblk, gocc);
-  return launch_scatter(d, B, gocc, gw, gx, s);
+  return launch_scatter(d, B, gocc, x, w, gw, gx, s);
 }
 
 static inline unsigned red_threads(int64_t n) { return n >= 256 ? 256u : 64u; }
@@ -369,16 +395,17 @@ hipError_t launch_obs_final(const double *part, int B, int nblk, int M, double *
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, double *gw, double *gx,
-                          hipStream_t s) {
+hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, const double *x,
+                          const double *w, double *gw, double *gx, hipStream_t s) {
   if (d.n_weights > 0) {
-    k_scatter_w<<<d.n_weights, red_threads(B), 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, gw);
+    k_scatter_w<<<d.n_weights, red_threads(B), 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, d.w_fac,
+                                                       x, d.n_inputs, gw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (gx && d.n_inputs > 0)
     k_scatter_x<<<nb((int64_t)B * d.n_inputs), kThreads, 0, s>>>(gocc, B, d.n_occ, d.x_ptr, d.x_list,
-                                                                d.n_inputs, gx);
+                                                                d.x_fac, w, d.n_inputs, gx);
   return hipGetLastError();
 }
 
@@ -387,12 +414,13 @@ hipError_t launch_onehot(double *G, int B, int M, int m, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, int m, double *jw,
-                              double *jx, hipStream_t s) {
+hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, const double *x,
+                              const double *w, int m, double *jw, double *jx, hipStream_t s) {
   const int64_t work = (int64_t)B * (d.n_weights + (jx ? d.n_inputs : 0));
   if (work == 0) return hipSuccess;
-  k_scatter_jac<<<nb(work), kThreads, 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, d.n_weights, d.x_ptr,
-                                              d.x_list, d.n_inputs, m, d.n_obs, jw, jx);
+  k_scatter_jac<<<nb(work), kThreads, 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, d.w_fac,
+                                              d.n_weights, d.x_ptr, d.x_list, d.x_fac, d.n_inputs, x,
+                                              w, m, d.n_obs, jw, jx);
   return hipGetLastError();
 }
 
@@ -410,10 +438,10 @@ template hipError_t plain_forward<double>(const DevCircuit &, const HostCircuitI
                                           const double2 *, void *, double *, double *, bool,
                                           hipStream_t);
 template hipError_t plain_backward<float>(const DevCircuit &, const HostCircuitInfo &, int,
-                                          const double2 *, void *, void *, const double *,
+                                          const double2 *, const double *, const double *, void *, void *, const double *,
                                           double *, double *, double *, double *, hipStream_t);
 template hipError_t plain_backward<double>(const DevCircuit &, const HostCircuitInfo &, int,
-                                           const double2 *, void *, void *, const double *,
+                                           const double2 *, const double *, const double *, void *, void *, const double *,
                                            double *, double *, double *, double *, hipStream_t);
 
 }  // namespace qtm

@@ -58,23 +58,25 @@ __device__ __forceinline__ MD md_pauli(int type) {
   return r;
 }
 
-// blk record: [q, ng, (type, src, idx, occ) x ng]
-
 // One fused block of one sample: U = G_last ... G_first into *mat and, if
 // coef is set, the (px, py, pz) of every rotation j at coef[3 * occ_j].
-// blk record: [q, ng, (type, src, idx, occ) x ng]; x is the sample's input row.
+// blk record: [q, ng, (type, src, idx, widx, occ) x ng]; x is the sample's
+// input row.  The angle is x[idx] (src 1), w[idx] (src 2) or the scaled
+// input w[widx] * x[idx] (src 3, Eq. (7)).
+constexpr int kBlkGate = 5;
 template <typename R>
 __device__ __forceinline__ void prep_block(const int32_t *__restrict__ r, const double *__restrict__ x,
                                            const double *__restrict__ w, M2<R> *__restrict__ mat,
                                            double *__restrict__ coef) {
   const int ng = r[1];
   auto ang = [&](int g) {
-    const int32_t *e = r + 2 + 4 * g;
+    const int32_t *e = r + 2 + kBlkGate * g;
+    if (e[1] == 3) return w[e[3]] * x[e[2]];
     return e[1] == 1 ? x[e[2]] : w[e[2]];
   };
   MD U;
   U.m[0][0] = {1, 0}; U.m[0][1] = {0, 0}; U.m[1][0] = {0, 0}; U.m[1][1] = {1, 0};
-  for (int g = 0; g < ng; ++g) U = md_mul(md_rot(r[2 + 4 * g], ang(g)), U);
+  for (int g = 0; g < ng; ++g) U = md_mul(md_rot(r[2 + kBlkGate * g], ang(g)), U);
   M2<R> o;
   o.a = {(R)U.m[0][0].x, (R)U.m[0][0].y};
   o.b = {(R)U.m[0][1].x, (R)U.m[0][1].y};
@@ -85,9 +87,9 @@ __device__ __forceinline__ void prep_block(const int32_t *__restrict__ r, const 
   MD A;
   A.m[0][0] = {1, 0}; A.m[0][1] = {0, 0}; A.m[1][0] = {0, 0}; A.m[1][1] = {1, 0};
   for (int g = ng - 1; g >= 0; --g) {
-    const int32_t *e = r + 2 + 4 * g;
+    const int32_t *e = r + 2 + kBlkGate * g;
     MD P = md_mul(md_mul(A, md_pauli(e[0])), md_adj(A));
-    double *cf = coef + (int64_t)e[3] * 3;
+    double *cf = coef + (int64_t)e[4] * 3;
     cf[0] = P.m[1][0].x;
     cf[1] = P.m[1][0].y;
     cf[2] = P.m[0][0].x;

@@ -53,6 +53,9 @@ def make(qtm, n, gates, n_in=0, n_w=0, masks=(1,)):
     (2, [[1, 0, 0, 2, 3]], 0, 3, [1], -1),                     # weight index out of range
     (2, [[0, 0, 0, 1, 1]], 1, 0, [1], -1),                     # input index out of range
     (2, [[0, 0, 0, 0, 0]], 1, 0, [1], -1),                     # rotation without source
+    (2, [[1, 0, 2, 3, 0]], 1, 2, [1], -1),                     # scaled: weight slot out of range
+    (2, [[1, 0, 0, 3, 1]], 1, 2, [1], -1),                     # scaled: input slot out of range
+    (2, [[1, 0, -1, 3, 0]], 1, 2, [1], -1),                    # scaled: negative weight slot
     (2, [[7, 0, 1, 0, 0]], 0, 0, [1], -2),                     # unknown gate type
     (2, [], 0, 0, [4], -1),                                    # mask bit >= n
     (2, [], 0, 0, [], -1),                                     # no observable
@@ -164,3 +167,14 @@ def test_specialised_kernels_compile_without_a_device(qtm):
             c.jit_compile(prec)
             src = c.jit_source(prec, 1, 0)
             assert "qtm_jit_bwd" in src and "u1_" in src
+
+
+def test_paper_ansatz_plans_and_compiles(qtm):
+    """The paper's ansatz (weight-scaled inputs) plans like any circuit: the
+    plan's gate order gives the oracle's results, and its specialised
+    kernels compile without a device."""
+    for ent in ("chain", "ring"):
+        circ = W.paper_ansatz(9, 2, ent)
+        _check_plan(qtm, circ, tile=5, klo=2)
+    c = qtm.Circuit.from_workload(W.paper_ansatz(12, 3))
+    c.jit_compile("c64")
