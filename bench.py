@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--paper-sweep", default="", choices=["", "fig1", "fig2", "tab1", "all"],
+                    help="time the paper's benchmark shapes (Eq. (7) ansatz with input scaling) "
+                         "instead of the default workload; one JSON line per shape")
     ap.add_argument("--digest", default="",
                     help="print the digest of the sources of this kernel (traffic records refer to it)")
     args = ap.parse_args()
@@ -152,6 +155,8 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 3 copies of 1 GiB")
         return
+    if args.paper_sweep:
+        return bench_paper_shapes(args)
     if args.config == "c4":
         return bench_uneven(args)
     wl = W.config_workload(args.config)
@@ -291,6 +296,65 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# The paper's benchmark shapes for its Eq. (7) ansatz (batch 48 throughout):
+# Fig. 1 sweeps the qubit count at depth 3 with Z on every qubit, Fig. 2 the
+# depth at 12 qubits, Tab. I the number of observables at 12 qubits, depth 3.
+PAPER_SHAPES = {
+    "fig1": [(n, 3, 48, n) for n in range(4, 19, 2)],
+    "fig2": [(12, d, 48, 12) for d in range(1, 12)],
+    "tab1": [(12, 3, 48, m) for m in (1, 2, 4, 8, 12, 16, 24, 32)],
+}
+
+
+def bench_paper_shapes(args):
+    """Forward and adjoint-gradient times of the paper's ansatz at its own
+    benchmark shapes (complex64, fused path, default tiles; the specialised
+    kernels unless --jit 0).  Forward and backward are timed separately with
+    events on the launch stream."""
+    import torch
+    import workloads as W
+    import paper_2404_06314_amd as q
+
+    sweeps = list(PAPER_SHAPES) if args.paper_sweep == "all" else [args.paper_sweep]
+    prec = args.precision or "c64"
+    dev = torch.device("cuda:0")
+    for sw in sweeps:
+        for i, (n, d, B, M) in enumerate(PAPER_SHAPES[sw]):
+            wl = W.paper_workload(n, d, B, seed=500 + 37 * i + n, n_obs=M)
+            c = q.Circuit.from_workload(wl.circuit)
+            if args.jit:
+                c.set_option(q.QTM_OPT_JIT, 1)
+            x = torch.as_tensor(wl.inputs, device=dev)
+            w = torch.as_tensor(wl.weights, device=dev)
+            G = torch.as_tensor(wl.grad_out, device=dev)
+            state = c.alloc_state(B, prec)
+            for _ in range(max(args.warmup, 1)):
+                c.forward(x, w, prec, state=state)
+                c.backward(x, w, G, prec, state=state)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            tf = tb = 0.0
+            for _ in range(args.steps):
+                ev[0].record()
+                c.forward(x, w, prec, state=state)
+                ev[1].record()
+                c.backward(x, w, G, prec, state=state)
+                ev[2].record()
+                ev[2].synchronize()
+                tf += ev[0].elapsed_time(ev[1])
+                tb += ev[1].elapsed_time(ev[2])
+            tf /= args.steps
+            tb /= args.steps
+            line = {"sweep": sw, "n_qubits": n, "depth": d, "batch": B, "observables": M,
+                    "parameters": wl.circuit.n_weights, "gates": wl.circuit.n_gates,
+                    "ms_forward": round(tf, 4), "ms_backward": round(tb, 4),
+                    "evals_per_s": round(B / ((tf + tb) / 1e3), 1), "dtype": prec,
+                    "specialised_kernels": bool(args.jit)}
+            print(json.dumps(line), flush=True)
+            log(f"{sw} n={n} d={d} M={M}: fwd {tf:.3f} ms, bwd {tb:.3f} ms")
+            c.close()
 
 
 def bench_uneven(args):

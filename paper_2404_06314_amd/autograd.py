@@ -43,16 +43,80 @@ class QuantumLayer(torch.nn.Module):
 
     Weights are initialised uniformly in [0, 2 pi) like the paper's
     ``variational_params_initial="uniform"`` (Sec. II-D) unless given.
+
+    ``param_sets`` splits the weight vector, in slot order, into separately
+    registered parameters (Sec. II-C: the variational theta and the input
+    scaling lambda take their own initialisation and optimiser
+    hyperparameters).  Each entry is (name, size, init) with init one of
+    "uniform" (U[0, 2 pi)), "ones", "zeros", a number (constant) or a tensor
+    of that size; the sizes must add up to the circuit's weight count.
     """
 
-    def __init__(self, circuit: Circuit, precision="c64", weights=None, device="cuda"):
+    def __init__(self, circuit: Circuit, precision="c64", weights=None, device="cuda",
+                 param_sets=None):
         super().__init__()
         self.circuit = circuit
         self.precision = precision
-        if weights is None:
-            weights = torch.rand(circuit.n_weights, dtype=torch.float64) * (2 * math.pi)
-        self.weights = torch.nn.Parameter(torch.as_tensor(weights, dtype=torch.float64).to(device))
+        if param_sets is None:
+            if weights is None:
+                weights = torch.rand(circuit.n_weights, dtype=torch.float64) * (2 * math.pi)
+            param_sets = [("weights", circuit.n_weights, weights)]
+        elif weights is not None:
+            raise ValueError("give either weights or param_sets")
+        if sum(int(s) for _, s, _ in param_sets) != circuit.n_weights:
+            raise ValueError("param_sets sizes must add up to the circuit's weight count")
+        self._sets = []
+        for name, size, init in param_sets:
+            t = _initial(int(size), init).to(device)
+            self.register_parameter(name, torch.nn.Parameter(t))
+            self._sets.append(name)
+
+    @classmethod
+    def eq7(cls, n: int, depth: int, entangler="chain", observables=None, precision="c64",
+            device="cuda", theta_init="uniform", lambda_init="ones"):
+        """The paper's benchmark ansatz (Eq. (7)) with parameter sets
+        ``theta`` and ``lambda``; observables: Z masks (default Z on every
+        qubit)."""
+        from .ansatz import eq7_gates, z_observables
+        gates, n_th, n_lam = eq7_gates(n, depth, entangler)
+        masks = z_observables(n) if observables is None else observables
+        circ = Circuit(n, gates, n, n_th + n_lam, masks)
+        return cls(circ, precision, device=device,
+                   param_sets=[("theta", n_th, theta_init), ("lambda", n_lam, lambda_init)])
+
+    @property
+    def weights_vector(self):
+        """All weights in slot order (a view when there is one set)."""
+        ps = [getattr(self, n) for n in self._sets]
+        return ps[0] if len(ps) == 1 else torch.cat(ps)
+
+    def param_groups(self, **hyper):
+        """Optimiser groups, one per parameter set: ``param_groups(theta=dict(lr=0.01),
+        lambda_=dict(lr=0.1))`` (a trailing underscore may be used for names that
+        are Python keywords)."""
+        groups = []
+        for n in self._sets:
+            h = hyper.get(n, hyper.get(n + "_", {}))
+            groups.append(dict(params=[getattr(self, n)], **h))
+        return groups
 
     def forward(self, inputs):
-        return QtmFunction.apply(inputs.to(torch.float64), self.weights, self.circuit,
+        return QtmFunction.apply(inputs.to(torch.float64), self.weights_vector, self.circuit,
                                  self.precision)
+
+
+def _initial(size: int, init):
+    if isinstance(init, str):
+        if init == "uniform":
+            return torch.rand(size, dtype=torch.float64) * (2 * math.pi)
+        if init == "ones":
+            return torch.ones(size, dtype=torch.float64)
+        if init == "zeros":
+            return torch.zeros(size, dtype=torch.float64)
+        raise ValueError(f"unknown init {init!r}")
+    if isinstance(init, (int, float)):
+        return torch.full((size,), float(init), dtype=torch.float64)
+    t = torch.as_tensor(init, dtype=torch.float64).reshape(-1).clone()
+    if t.numel() != size:
+        raise ValueError(f"initial values have {t.numel()} entries, expected {size}")
+    return t

@@ -138,3 +138,15 @@ def test_autograd_function():
     np.testing.assert_allclose(out.detach().cpu().numpy(), ev, atol=1e-12)
     np.testing.assert_allclose(w.grad.cpu().numpy(), gw, atol=1e-10)
     np.testing.assert_allclose(x.grad.cpu().numpy(), gx, atol=1e-10)
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_deep_circuit_without_mid_circuit_renormalisation(precision):
+    """64 layers (3584 gates) at n = 14: the complex64 state is never rescaled
+    mid-circuit; the one FP64 division by the norm at the end keeps <Z> and
+    the gradients within tolerance (rescaling by a scalar commutes with every
+    later gate, so a periodic rescale would change only rounding)."""
+    rng = np.random.default_rng(64)
+    wl = W.random_workload(rng, W.layered_circuit(14, 64, "ring"), 4)
+    got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, precision)
+    assert_parity(got, _ref(wl), precision, f"n14 L64 {precision}")

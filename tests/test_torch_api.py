@@ -1,0 +1,84 @@
+"""Torch layer: parameter sets (Sec. II-C: theta and lambda with their own
+initialisation and optimiser hyperparameters) and the Eq. (7) ansatz
+builder.  Construction runs on the host; the forward/backward check runs on
+the GPU against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+
+@pytest.mark.parametrize("n,d,ent", [(1, 2, "chain"), (2, 1, "ring"), (3, 3, "ring"),
+                                     (12, 3, "chain"), (7, 0, "chain")])
+def test_eq7_gates_match_the_test_workload_generator(n, d, ent):
+    from paper_2404_06314_amd.ansatz import eq7_gates
+    g, n_th, n_lam = eq7_gates(n, d, ent)
+    ref = W.paper_ansatz(n, d, ent)
+    assert np.array_equal(g, ref.gates)
+    assert n_th + n_lam == ref.n_weights
+
+
+def test_layer_parameter_sets_on_host():
+    from paper_2404_06314_amd.autograd import QuantumLayer
+    layer = QuantumLayer.eq7(12, 3, device="cpu")
+    names = [n for n, _ in layer.named_parameters()]
+    assert names == ["theta", "lambda"]
+    assert layer.theta.numel() == 2 * 12 * 4 and layer.get_parameter("lambda").numel() == 2 * 12 * 3
+    assert layer.theta.numel() + layer.get_parameter("lambda").numel() == 168
+    assert torch.all(layer.get_parameter("lambda") == 1.0)
+    assert torch.all((layer.theta >= 0) & (layer.theta < 2 * np.pi))
+    w = layer.weights_vector
+    assert torch.equal(w[:96], layer.theta) and torch.equal(w[96:], layer.get_parameter("lambda"))
+    groups = layer.param_groups(theta=dict(lr=0.01), lambda_=dict(lr=0.1))
+    assert [g["lr"] for g in groups] == [0.01, 0.1]
+    opt = torch.optim.Adam(groups)
+    assert len(opt.param_groups) == 2
+
+
+def test_layer_argument_errors():
+    from paper_2404_06314_amd.autograd import QuantumLayer
+    from paper_2404_06314_amd.ansatz import eq7_gates
+    import paper_2404_06314_amd as q
+    g, a, b = eq7_gates(3, 1)
+    c = q.Circuit(3, g, 3, a + b, [1, 2, 4])
+    with pytest.raises(ValueError):
+        QuantumLayer(c, device="cpu", param_sets=[("theta", a, "uniform")])
+    with pytest.raises(ValueError):
+        QuantumLayer(c, device="cpu", param_sets=[("theta", a, "gauss"), ("lam", b, 1.0)])
+    with pytest.raises(ValueError):
+        QuantumLayer(c, device="cpu", param_sets=[("theta", a, np.zeros(a + 1)), ("lam", b, 1.0)])
+    with pytest.raises(ValueError):
+        QuantumLayer(c, device="cpu", weights=np.zeros(a + b), param_sets=[("w", a + b, 0.0)])
+    with pytest.raises(ValueError):
+        eq7_gates(3, 1, "star")
+    layer = QuantumLayer(c, device="cpu", weights=np.arange(a + b, dtype=float))
+    assert torch.equal(layer.weights_vector, torch.arange(a + b, dtype=torch.float64))
+
+
+@pytest.mark.gpu
+def test_layer_gradients_per_set_match_the_oracle():
+    import oracle
+    from paper_2404_06314_amd.autograd import QuantumLayer
+    wl = W.paper_workload(8, 2, 6, seed=77)
+    n_th = wl.meta["theta"]
+    layer = QuantumLayer.eq7(8, 2, device="cuda", theta_init=wl.weights[:n_th],
+                             lambda_init=wl.weights[n_th:])
+    x = torch.tensor(wl.inputs, device="cuda", requires_grad=True)
+    G = torch.as_tensor(wl.grad_out, device="cuda")
+    ev = layer(x)
+    (ev * G).sum().backward()
+    rev, rgw, rgx = oracle.vjp(wl.circuit, wl.inputs, wl.weights, wl.grad_out)
+    assert np.max(np.abs(ev.detach().cpu().numpy() - rev)) <= 1e-5
+    for got, ref in ((layer.theta.grad, rgw[:n_th]), (layer.get_parameter("lambda").grad, rgw[n_th:]),
+                     (x.grad, rgx)):
+        got = got.cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref)) + 1e-6
+    # one optimiser step with separate learning rates moves each set by its own rate
+    opt = torch.optim.SGD(layer.param_groups(theta=dict(lr=0.0), lambda_=dict(lr=0.1)))
+    th0 = layer.theta.detach().clone()
+    lam0 = layer.get_parameter("lambda").detach().clone()
+    opt.step()
+    assert torch.equal(layer.theta.detach(), th0)
+    np.testing.assert_allclose((lam0 - layer.get_parameter("lambda").detach()).cpu().numpy(),
+                               0.1 * rgw[n_th:], rtol=0, atol=1e-5 * np.max(np.abs(rgw)) + 1e-7)

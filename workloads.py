@@ -108,7 +108,9 @@ def paper_ansatz(n: int, depth: int, entangler: str = "chain", n_obs: int | None
     RZ(lambda s_q) on every qubit q; a final variational RZ, RY layer closes
     the circuit.  Weights are laid out as [theta (2n(d+1)), lambda (2nd)] so
     that the two parameter sets can take separate hyperparameters (Sec. II-C).
-    Observables: Z on qubit q for q < n_obs (default n).
+    Observables: Z on qubit q for the first min(n_obs, n) (default n); beyond
+    n (Tab. I goes to 32 observables on 12 qubits without saying which), the
+    two-qubit strings Z_i Z_(i+s) mod n for s = 1, 2, ... and i = 0..n-1.
     """
     if entangler not in ("chain", "ring"):
         raise ValueError(entangler)
@@ -133,10 +135,15 @@ def paper_ansatz(n: int, depth: int, entangler: str = "chain", n_obs: int | None
             g.append((RZ, q, n_theta + l * 2 * n + n + q, SRC_SCALED, q))
     variational(depth)
     M = n if n_obs is None else n_obs
+    masks = [1 << q for q in range(min(M, n))]
+    for k in range(M - n):
+        i, s = k % n, 1 + k // n
+        if n < 2 or s >= n:
+            raise ValueError(f"{M} observables is too many for {n} qubits")
+        masks.append((1 << i) | (1 << ((i + s) % n)))
     return Circuit(n=n, gates=np.array(g, dtype=np.int32).reshape(-1, 5), n_inputs=n,
-                   n_weights=n_theta + 2 * n * depth,
-                   masks=np.array([1 << (q % n) for q in range(M)], dtype=np.uint64),
-                   name=name or f"paper_n{n}_d{depth}_{entangler}")
+                   n_weights=n_theta + 2 * n * depth, masks=np.array(masks, dtype=np.uint64),
+                   name=name or f"paper_n{n}_d{depth}_{entangler}_M{M}")
 
 
 def paper_workload(n: int, depth: int, batch: int, seed: int, entangler: str = "chain",
