@@ -42,7 +42,7 @@ def _load():
         lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i = ctypes.c_int
-        common = [i, P, i, i, i, P, i, i, P, P]
+        common = [i, P, i, i, i, P, P, i, i, P, P]
         lib.qtm_oracle_forward.argtypes = common + [P, i, i]
         lib.qtm_oracle_vjp.argtypes = common + [P, P, P, P, P, i, i]
         lib.qtm_oracle_jacobian.argtypes = common + [P, P, P, i, i]
@@ -58,6 +58,12 @@ def _load():
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _xmasks(circ):
+    """X-parts of the observables' Pauli strings, or None (all Z strings)."""
+    xm = getattr(circ, "xmasks", None)
+    return None if xm is None else np.ascontiguousarray(xm, dtype=np.uint64)
 
 
 def _prep(circ, x, w):
@@ -79,10 +85,11 @@ def forward(circ, x, w, threads: int | None = None, par_mode: int = 0):
     """Expectation values (B, M)."""
     lib = _load()
     gates, masks, x, w = _prep(circ, x, w)
+    xm = _xmasks(circ)
     B = x.shape[0]
     out = np.zeros((B, circ.n_obs))
     rc = lib.qtm_oracle_forward(circ.n, _ptr(gates), circ.n_gates, circ.n_inputs,
-                                circ.n_weights, _ptr(masks), circ.n_obs, B,
+                                circ.n_weights, _ptr(masks), _ptr(xm), circ.n_obs, B,
                                 _ptr(x), _ptr(w), _ptr(out),
                                 threads or default_threads(), par_mode)
     if rc:
@@ -95,6 +102,7 @@ def vjp(circ, x, w, G, threads: int | None = None, par_mode: int = 0,
     """Returns (expvals (B,M), grad_w (n_w,), grad_x (B,n_in)[, g_occ (B,n_gates)])."""
     lib = _load()
     gates, masks, x, w = _prep(circ, x, w)
+    xm = _xmasks(circ)
     B = x.shape[0]
     G = np.ascontiguousarray(G, dtype=np.float64).reshape(B, circ.n_obs)
     out = np.zeros((B, circ.n_obs))
@@ -102,7 +110,7 @@ def vjp(circ, x, w, G, threads: int | None = None, par_mode: int = 0,
     gx = np.zeros((B, max(circ.n_inputs, 1)))
     gocc = np.zeros((B, max(circ.n_gates, 1))) if occurrences else None
     rc = lib.qtm_oracle_vjp(circ.n, _ptr(gates), circ.n_gates, circ.n_inputs,
-                            circ.n_weights, _ptr(masks), circ.n_obs, B,
+                            circ.n_weights, _ptr(masks), _ptr(xm), circ.n_obs, B,
                             _ptr(x), _ptr(w), _ptr(G), _ptr(out), _ptr(gw), _ptr(gx),
                             _ptr(gocc), threads or default_threads(), par_mode)
     if rc:
@@ -117,12 +125,13 @@ def jacobian(circ, x, w, threads: int | None = None, par_mode: int = 0):
     """Returns (expvals (B,M), J_w (B,M,n_w), J_x (B,M,n_in))."""
     lib = _load()
     gates, masks, x, w = _prep(circ, x, w)
+    xm = _xmasks(circ)
     B = x.shape[0]
     out = np.zeros((B, circ.n_obs))
     jw = np.zeros((B, circ.n_obs, max(circ.n_weights, 1)))
     jx = np.zeros((B, circ.n_obs, max(circ.n_inputs, 1)))
     rc = lib.qtm_oracle_jacobian(circ.n, _ptr(gates), circ.n_gates, circ.n_inputs,
-                                 circ.n_weights, _ptr(masks), circ.n_obs, B,
+                                 circ.n_weights, _ptr(masks), _ptr(xm), circ.n_obs, B,
                                  _ptr(x), _ptr(w), _ptr(out), _ptr(jw), _ptr(jx),
                                  threads or default_threads(), par_mode)
     if rc:

@@ -54,6 +54,9 @@ typedef double complex cplx;
 enum { O_RX = 0, O_RY = 1, O_RZ = 2, O_CNOT = 3, O_CZ = 4 };
 enum { O_SRC_NONE = 0, O_SRC_INPUT = 1, O_SRC_WEIGHT = 2, O_SRC_SCALED = 3 };
 
+/* Observable m is the Pauli string with X-part xmasks[m] and Z-part
+ * masks[m]: on qubit q the factor is I (bits 0, 0), X (1, 0), Y (1, 1) or
+ * Z (0, 1).  xmasks may be NULL (every observable a Z string). */
 typedef struct {
   int n;
   const int32_t *gates;
@@ -62,7 +65,10 @@ typedef struct {
   int n_weights;
   const uint64_t *masks;
   int n_obs;
+  const uint64_t *xmasks;
 } circ_t;
+
+static uint64_t xmask_of(const circ_t *c, int m) { return c->xmasks ? c->xmasks[m] : 0; }
 
 static int is_param(int type) { return type == O_RX || type == O_RY || type == O_RZ; }
 
@@ -84,7 +90,7 @@ static int check_circuit(const circ_t *c) {
     }
   }
   for (int m = 0; m < c->n_obs; ++m)
-    if (c->n < 64 && (c->masks[m] >> c->n) != 0) return -1;
+    if (c->n < 64 && ((c->masks[m] | xmask_of(c, m)) >> c->n) != 0) return -1;
   return 0;
 }
 
@@ -193,15 +199,46 @@ static double zsign(int64_t x, uint64_t mask) {
   return (__builtin_popcountll((uint64_t)x & mask) & 1) ? -1.0 : 1.0;
 }
 
-/* <psi|O_m|psi> for every observable (Eq. (3)). */
-static void expvals(const circ_t *c, const cplx *psi, double *out, int par) {
+/* v <- P v for the Pauli string (xm, zm): the tensor product of one Pauli
+ * matrix per qubit, X = [[0, 1], [1, 0]], Y = [[0, -i], [i, 0]],
+ * Z = [[1, 0], [0, -1]], each applied as a one-qubit gate. */
+static void apply_pauli(cplx *v, int n, uint64_t xm, uint64_t zm, int par) {
+  for (int q = 0; q < n; ++q) {
+    const int xb = (int)((xm >> q) & 1), zb = (int)((zm >> q) & 1);
+    if (!xb && !zb) continue;
+    cplx u[2][2];
+    if (xb && zb) {
+      u[0][0] = 0;  u[0][1] = -I;
+      u[1][0] = I;  u[1][1] = 0;
+    } else if (xb) {
+      u[0][0] = 0;  u[0][1] = 1;
+      u[1][0] = 1;  u[1][1] = 0;
+    } else {
+      u[0][0] = 1;  u[0][1] = 0;
+      u[1][0] = 0;  u[1][1] = -1;
+    }
+    apply_1q(v, n, q, u, par);
+  }
+}
+
+/* <psi|O_m|psi> for every observable (Eq. (3)).  A Z string is the
+ * diagonal sum over |psi_x|^2 with signs; a string with X or Y factors is
+ * Re <psi|P psi> with P applied to a copy (tmp, 2^n entries). */
+static void expvals(const circ_t *c, const cplx *psi, double *out, cplx *tmp, int par) {
   const int64_t dim = (int64_t)1 << c->n;
   for (int m = 0; m < c->n_obs; ++m) {
     double acc = 0.0;
+    if (xmask_of(c, m)) {
+      memcpy(tmp, psi, sizeof(cplx) * dim);
+      apply_pauli(tmp, c->n, xmask_of(c, m), c->masks[m], par);
 #pragma omp parallel for if (par) reduction(+ : acc) schedule(static)
-    for (int64_t x = 0; x < dim; ++x) {
-      double p = creal(psi[x]) * creal(psi[x]) + cimag(psi[x]) * cimag(psi[x]);
-      acc += zsign(x, c->masks[m]) * p;
+      for (int64_t x = 0; x < dim; ++x) acc += creal(conj(psi[x]) * tmp[x]);
+    } else {
+#pragma omp parallel for if (par) reduction(+ : acc) schedule(static)
+      for (int64_t x = 0; x < dim; ++x) {
+        double p = creal(psi[x]) * creal(psi[x]) + cimag(psi[x]) * cimag(psi[x]);
+        acc += zsign(x, c->masks[m]) * p;
+      }
     }
     out[m] = acc;
   }
@@ -276,31 +313,43 @@ static int run_sample(const job_t *J, int b, int par) {
   const double *x_b = J->x + (int64_t)b * c->n_inputs;
   const int M = c->n_obs;
   cplx *phi = malloc(sizeof(cplx) * dim);
-  if (!phi) return -2;
+  cplx *mu = malloc(sizeof(cplx) * dim);
+  if (!phi || !mu) return -2;
   evolve(c, x_b, J->w, phi, par);
-  if (J->out) expvals(c, phi, J->out + (int64_t)b * M, par);
+  if (J->out) expvals(c, phi, J->out + (int64_t)b * M, mu, par);
   if (J->mode == 0) {
     free(phi);
+    free(mu);
     return 0;
   }
   int n_bra = J->mode == 1 ? 1 : M;
-  cplx *mu = malloc(sizeof(cplx) * dim);
   cplx **lam = malloc(sizeof(cplx *) * (n_bra > 0 ? n_bra : 1));
   double *g = calloc((size_t)(n_bra > 0 ? n_bra : 1) * (c->n_gates > 0 ? c->n_gates : 1), sizeof(double));
-  int ok = mu && lam && g;
+  int ok = lam && g;
   for (int j = 0; ok && j < n_bra; ++j) ok = (lam[j] = malloc(sizeof(cplx) * dim)) != NULL;
   if (!ok) return -2; /* test infrastructure: leak on OOM is acceptable */
-  /* bras: lambda = (sum_m G_m O_m) phi  or  lambda_m = O_m phi */
+  /* bras: lambda = (sum_m G_m O_m) phi  or  lambda_m = O_m phi; the Z
+   * strings as one diagonal, every string with X or Y factors added as
+   * G_m (P_m phi) (P_m applied to a copy of phi in mu) */
   for (int j = 0; j < n_bra; ++j) {
 #pragma omp parallel for if (par) schedule(static)
     for (int64_t x = 0; x < dim; ++x) {
       double dsum = 0.0;
       if (J->mode == 1) {
-        for (int m = 0; m < M; ++m) dsum += J->G[(int64_t)b * M + m] * zsign(x, c->masks[m]);
-      } else {
+        for (int m = 0; m < M; ++m)
+          if (!xmask_of(c, m)) dsum += J->G[(int64_t)b * M + m] * zsign(x, c->masks[m]);
+      } else if (!xmask_of(c, j)) {
         dsum = zsign(x, c->masks[j]);
       }
       lam[j][x] = dsum * phi[x];
+    }
+    for (int m = 0; m < M; ++m) {
+      if (!xmask_of(c, m) || (J->mode == 2 && m != j)) continue;
+      const double gm = J->mode == 1 ? J->G[(int64_t)b * M + m] : 1.0;
+      memcpy(mu, phi, sizeof(cplx) * dim);
+      apply_pauli(mu, c->n, xmask_of(c, m), c->masks[m], par);
+#pragma omp parallel for if (par) schedule(static)
+      for (int64_t x = 0; x < dim; ++x) lam[j][x] += gm * mu[x];
     }
   }
   reverse_sweep(c, x_b, J->w, phi, lam, n_bra, mu, g, par);
@@ -354,10 +403,10 @@ static int run_batch(const job_t *J, int B, int threads, int par_mode) {
 }
 
 int qtm_oracle_forward(int n, const int32_t *gates, int n_gates, int n_inputs,
-                       int n_weights, const uint64_t *masks, int n_obs, int B,
+                       int n_weights, const uint64_t *masks, const uint64_t *xmasks, int n_obs, int B,
                        const double *x, const double *w, double *out,
                        int threads, int par_mode) {
-  circ_t c = {n, gates, n_gates, n_inputs, n_weights, masks, n_obs};
+  circ_t c = {n, gates, n_gates, n_inputs, n_weights, masks, n_obs, xmasks};
   if (check_circuit(&c) || B < 0 || !out) return -1;
   job_t J = {&c, x, w, NULL, out, NULL, NULL, NULL, NULL, NULL, 0};
   return run_batch(&J, B, threads, par_mode);
@@ -368,11 +417,11 @@ int qtm_oracle_forward(int n, const int32_t *gates, int n_gates, int n_inputs,
  * out (expectation values), grad_x and g_occ ([B][n_gates], per gate
  * occurrence) may be NULL. */
 int qtm_oracle_vjp(int n, const int32_t *gates, int n_gates, int n_inputs,
-                   int n_weights, const uint64_t *masks, int n_obs, int B,
+                   int n_weights, const uint64_t *masks, const uint64_t *xmasks, int n_obs, int B,
                    const double *x, const double *w, const double *G,
                    double *out, double *grad_w, double *grad_x, double *g_occ,
                    int threads, int par_mode) {
-  circ_t c = {n, gates, n_gates, n_inputs, n_weights, masks, n_obs};
+  circ_t c = {n, gates, n_gates, n_inputs, n_weights, masks, n_obs, xmasks};
   if (check_circuit(&c) || B < 0 || !grad_w || !G) return -1;
   double *gws = calloc((size_t)(B > 0 ? B : 1) * (n_weights > 0 ? n_weights : 1), sizeof(double));
   if (!gws) return -2;
@@ -393,10 +442,10 @@ int qtm_oracle_vjp(int n, const int32_t *gates, int n_gates, int n_inputs,
 /* Full Jacobian (B, M, |Theta|) of Sec. II-B: jw [B][M][n_weights],
  * jx [B][M][n_inputs]; out may be NULL. */
 int qtm_oracle_jacobian(int n, const int32_t *gates, int n_gates, int n_inputs,
-                        int n_weights, const uint64_t *masks, int n_obs, int B,
+                        int n_weights, const uint64_t *masks, const uint64_t *xmasks, int n_obs, int B,
                         const double *x, const double *w, double *out,
                         double *jw, double *jx, int threads, int par_mode) {
-  circ_t c = {n, gates, n_gates, n_inputs, n_weights, masks, n_obs};
+  circ_t c = {n, gates, n_gates, n_inputs, n_weights, masks, n_obs, xmasks};
   if (check_circuit(&c) || B < 0 || !jw || !jx) return -1;
   memset(jw, 0, sizeof(double) * (size_t)B * n_obs * n_weights);
   memset(jx, 0, sizeof(double) * (size_t)B * n_obs * n_inputs);
@@ -408,7 +457,7 @@ int qtm_oracle_jacobian(int n, const int32_t *gates, int n_gates, int n_inputs,
 int qtm_oracle_state(int n, const int32_t *gates, int n_gates, int n_inputs,
                      int n_weights, const double *x_b, const double *w,
                      double *state) {
-  circ_t c = {n, gates, n_gates, n_inputs, n_weights, NULL, 0};
+  circ_t c = {n, gates, n_gates, n_inputs, n_weights, NULL, 0, NULL};
   if (check_circuit(&c) || !state) return -1;
   const int64_t dim = (int64_t)1 << n;
   cplx *psi = malloc(sizeof(cplx) * dim);
@@ -427,7 +476,7 @@ int qtm_oracle_state(int n, const int32_t *gates, int n_gates, int n_inputs,
 int qtm_oracle_uncompute(int n, const int32_t *gates, int n_gates, int n_inputs,
                          int n_weights, const double *x_b, const double *w,
                          double *amp0) {
-  circ_t c = {n, gates, n_gates, n_inputs, n_weights, NULL, 0};
+  circ_t c = {n, gates, n_gates, n_inputs, n_weights, NULL, 0, NULL};
   if (check_circuit(&c) || !amp0) return -1;
   const int64_t dim = (int64_t)1 << n;
   cplx *psi = malloc(sizeof(cplx) * dim);

@@ -69,9 +69,26 @@ def zstring(n, mask):
     return kron_on(n, {q: PZ for q in range(n) if (int(mask) >> q) & 1})
 
 
+def pauli_string(n, xmask, zmask):
+    """Kronecker product of X, Y, Z factors: X where only the X bit is set, Z
+    where only the Z bit is, Y where both are."""
+    ops = {}
+    for q in range(n):
+        xb, zb = (int(xmask) >> q) & 1, (int(zmask) >> q) & 1
+        if xb or zb:
+            ops[q] = PY if (xb and zb) else (PX if xb else PZ)
+    return kron_on(n, ops)
+
+
+def observables(circ):
+    xm = circ.xmasks if getattr(circ, "xmasks", None) is not None else np.zeros_like(circ.masks)
+    return list(zip(xm, circ.masks))
+
+
 def brute_expvals(circ, x_b, w):
     psi = brute_state(circ, x_b, w)
-    return np.array([np.real(np.vdot(psi, zstring(circ.n, m) @ psi)) for m in circ.masks])
+    return np.array([np.real(np.vdot(psi, pauli_string(circ.n, xm, zm) @ psi))
+                     for xm, zm in observables(circ)])
 
 
 # --- Bloch-vector closed forms for product states -------------------------
@@ -103,11 +120,24 @@ def bloch_vectors(circ, x_b, w):
     return r
 
 
+def _axis(xm, zm, q):
+    """Bloch component (0 x, 1 y, 2 z) a Pauli factor on qubit q reads, or None."""
+    xb, zb = (int(xm) >> q) & 1, (int(zm) >> q) & 1
+    if not (xb or zb):
+        return None
+    return 1 if (xb and zb) else (0 if xb else 2)
+
+
 def bloch_expvals(circ, x_b, w, masks=None):
+    """<P> of a product state is the product over the string's factors of the
+    matching Bloch components."""
     r = bloch_vectors(circ, x_b, w)
-    masks = circ.masks if masks is None else masks
-    return np.array([np.prod([r[q][2] for q in range(circ.n) if (int(m) >> q) & 1])
-                     for m in masks])
+    obs = observables(circ) if masks is None else [(0, m) for m in masks]
+    out = []
+    for xm, zm in obs:
+        out.append(np.prod([r[q][_axis(xm, zm, q)] for q in range(circ.n)
+                            if _axis(xm, zm, q) is not None]))
+    return np.array(out)
 
 
 def bloch_grad(circ, x_b, w, G):
@@ -129,13 +159,14 @@ def bloch_grad(circ, x_b, w, G):
                     v = so3_deriv(int(circ.gates[k][0]), _angle(circ.gates[k], x_b, w)) @ v
                 else:
                     v = M @ v
-            dz = v[2]
             tot = 0.0
-            for m, Gm in zip(circ.masks, G):
-                if not (int(m) >> q) & 1:
+            for (xm, zm), Gm in zip(observables(circ), G):
+                a = _axis(xm, zm, q)
+                if a is None:
                     continue
-                others = np.prod([r[p][2] for p in range(n) if p != q and (int(m) >> p) & 1])
-                tot += Gm * dz * others
+                others = np.prod([r[p][_axis(xm, zm, p)] for p in range(n)
+                                  if p != q and _axis(xm, zm, p) is not None])
+                tot += Gm * v[a] * others
             g = circ.gates[k]
             if g[3] == W.SRC_WEIGHT:
                 gw[g[4]] += tot

@@ -31,6 +31,10 @@ MUTATIONS = {
     "scaled_grad_w_no_input_factor": ("wrow[gk[2]] += v * x_b[gk[4]];", "wrow[gk[2]] += v;"),
     "scaled_grad_x_no_weight_factor": ("if (xrow) xrow[gk[4]] += v * J->w[gk[2]];",
                                        "if (xrow) xrow[gk[4]] += v;"),
+    "pauli_y_conjugated": ("u[0][0] = 0;  u[0][1] = -I;\n      u[1][0] = I;",
+                           "u[0][0] = 0;  u[0][1] = I;\n      u[1][0] = -I;"),
+    "pauli_x_taken_as_z": ("} else if (xb) {", "} else if (0) {"),
+    "pauli_bra_drops_G": ("lam[j][x] += gm * mu[x];", "lam[j][x] += mu[x];"),
     "split_remainder_last": ("*lo = t * base + (t < rem ? t : rem);\n  *hi = *lo + base + (t < rem ? 1 : 0);",
                              "*lo = t * base + (t > T - 1 - rem ? t - (T - rem) : 0);\n  *hi = *lo + base + (t >= T - rem ? 1 : 0);"),
 }

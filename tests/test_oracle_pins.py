@@ -436,3 +436,93 @@ def test_paper_ansatz_brute_force_and_jacobian():
         _, gw, gx = oracle.vjp(c, x, w, Gm)
         np.testing.assert_allclose(jw[:, m, :].sum(axis=0), gw, atol=1e-12)
         np.testing.assert_allclose(jx[:, m, :], gx, atol=1e-12)
+
+
+# --- Pauli-string observables with X and Y factors ---------------------------
+
+def test_pauli_single_qubit_closed_forms():
+    """RY(t)|0> has Bloch vector (sin t, 0, cos t); RX(t)|0> has (0, -sin t, cos t)."""
+    for t_type, want_x, want_y in ((W.RY, math.sin, lambda t: 0.0),
+                                   (W.RX, lambda t: 0.0, lambda t: -math.sin(t))):
+        c = W.with_observables(
+            W.Circuit(n=1, gates=np.array([[t_type, 0, 0, W.SRC_WEIGHT, 0]], np.int32),
+                      n_inputs=0, n_weights=1, masks=np.array([1], np.uint64)),
+            [{0: "X"}, {0: "Y"}, {0: "Z"}])
+        for t in (-2.7, -0.4, 0.0, 1.1, 2.9):
+            ev, gw, _ = oracle.vjp(c, np.zeros((1, 0)), np.array([t]), np.array([[1.0, 0.0, 0.0]]))
+            np.testing.assert_allclose(ev[0], [want_x(t), want_y(t), math.cos(t)], atol=1e-14)
+            h = 1e-6
+            assert abs(gw[0] - (want_x(t + h) - want_x(t - h)) / (2 * h)) < 1e-8
+            _, gw, _ = oracle.vjp(c, np.zeros((1, 0)), np.array([t]), np.array([[0.0, 1.0, 0.0]]))
+            assert abs(gw[0] - (want_y(t + h) - want_y(t - h)) / (2 * h)) < 1e-8
+
+
+def test_pauli_bell_state():
+    """RY(pi/2) then CNOT(0 -> 1) makes (|00> + |11>) / sqrt 2: <XX> = 1,
+    <YY> = -1, <ZZ> = 1, <XY> = <X_0> = <Y_1> = 0."""
+    c = W.with_observables(
+        W.Circuit(n=2, gates=np.array([[W.RY, 0, 0, W.SRC_WEIGHT, 0], [W.CNOT, 0, 1, 0, 0]], np.int32),
+                  n_inputs=0, n_weights=1, masks=np.array([1], np.uint64)),
+        [{0: "X", 1: "X"}, {0: "Y", 1: "Y"}, {0: "Z", 1: "Z"}, {0: "X", 1: "Y"}, {0: "X"}, {1: "Y"}])
+    ev = oracle.forward(c, np.zeros((1, 0)), np.array([math.pi / 2]))
+    np.testing.assert_allclose(ev[0], [1, -1, 1, 0, 0, 0], atol=1e-14)
+
+
+def test_pauli_product_states_match_bloch():
+    rng = np.random.default_rng(19)
+    n = 5
+    base = W.layered_circuit(n, 2, "none")
+    c = W.with_observables(base, W.random_pauli_strings(rng, n, 12, max_weight=4))
+    x = rng.uniform(-np.pi, np.pi, size=(3, n))
+    w = rng.uniform(-np.pi, np.pi, size=c.n_weights)
+    G = rng.uniform(-1, 1, size=(3, c.n_obs))
+    ev, gw, gx = oracle.vjp(c, x, w, G)
+    gw_ref = np.zeros_like(gw)
+    for b in range(3):
+        np.testing.assert_allclose(ev[b], C.bloch_expvals(c, x[b], w), atol=1e-13)
+        gwb, gxb = C.bloch_grad(c, x[b], w, G[b])
+        gw_ref += gwb
+        np.testing.assert_allclose(gx[b], gxb, atol=1e-12)
+    np.testing.assert_allclose(gw, gw_ref, atol=1e-12)
+
+
+@settings(max_examples=30, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 2**31 - 1), n=st.integers(1, 5), ng=st.integers(0, 25))
+def test_pauli_brute_force_random_circuits(seed, n, ng):
+    rng = np.random.default_rng(seed)
+    c = W.with_observables(W.random_circuit(rng, n, ng), W.random_pauli_strings(rng, n, 4))
+    wl = W.random_workload(rng, c, 2)
+    ev = oracle.forward(c, wl.inputs, wl.weights)
+    for b in range(2):
+        np.testing.assert_allclose(ev[b], C.brute_expvals(c, wl.inputs[b], wl.weights), atol=1e-12)
+
+
+def test_pauli_finite_differences_and_jacobian():
+    """Entangled circuit, mixed Z / X / Y strings: the adjoint VJP against
+    central differences of the forward, and every Jacobian row against the
+    VJP with a one-hot upstream gradient."""
+    rng = np.random.default_rng(23)
+    c = W.with_observables(W.layered_circuit(4, 3, "ring"),
+                           [{0: "Z"}, {1: "X"}, {2: "Y", 3: "X"}, {0: "Y", 1: "Z", 3: "Y"}, {3: "Z", 0: "Z"}])
+    wl = W.random_workload(rng, c, 3)
+    x, w, G = wl.inputs, wl.weights, wl.grad_out
+    _, gw, gx = oracle.vjp(c, x, w, G)
+    h = 1e-6
+    L = lambda xx, ww: float(np.sum(G * oracle.forward(c, xx, ww)))
+    for j in range(c.n_weights):
+        wp, wm = w.copy(), w.copy()
+        wp[j] += h
+        wm[j] -= h
+        assert abs((L(x, wp) - L(x, wm)) / (2 * h) - gw[j]) < 1e-8, j
+    for i in range(c.n_inputs):
+        xp, xm = x.copy(), x.copy()
+        xp[1, i] += h
+        xm[1, i] -= h
+        assert abs((L(xp, w) - L(xm, w)) / (2 * h) - gx[1, i]) < 1e-8, i
+    _, jw, jx = oracle.jacobian(c, x, w)
+    for m in range(c.n_obs):
+        Gm = np.zeros((3, c.n_obs))
+        Gm[:, m] = 1.0
+        _, gwm, gxm = oracle.vjp(c, x, w, Gm)
+        np.testing.assert_allclose(jw[:, m, :].sum(axis=0), gwm, atol=1e-12)
+        np.testing.assert_allclose(jx[:, m, :], gxm, atol=1e-12)

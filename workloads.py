@@ -44,8 +44,9 @@ class Circuit:
     gates: np.ndarray          # int32 [G, 5]
     n_inputs: int
     n_weights: int
-    masks: np.ndarray          # uint64 [M]
+    masks: np.ndarray          # uint64 [M]: Z-parts of the observables' Pauli strings
     name: str = ""
+    xmasks: np.ndarray | None = None  # uint64 [M]: X-parts (None: every observable a Z string)
 
     @property
     def n_gates(self) -> int:
@@ -64,6 +65,41 @@ class Workload:
     weights: np.ndarray        # float64 [n_weights]
     grad_out: np.ndarray       # float64 [B, M]
     meta: dict = field(default_factory=dict)
+
+
+def pauli(ops: dict) -> tuple[int, int]:
+    """(X-part, Z-part) bitmasks of the Pauli string with factor ops[q] in
+    {"X", "Y", "Z"} on qubit q (identity elsewhere): X sets the X bit, Z the
+    Z bit, Y both."""
+    xm = zm = 0
+    for q, p in ops.items():
+        if p not in ("X", "Y", "Z"):
+            raise ValueError(p)
+        if p in ("X", "Y"):
+            xm |= 1 << int(q)
+        if p in ("Y", "Z"):
+            zm |= 1 << int(q)
+    return xm, zm
+
+
+def with_observables(circ: Circuit, strings) -> Circuit:
+    """The same circuit with the given observables (a list of ops dicts for
+    `pauli`)."""
+    xz = [pauli(o) for o in strings]
+    return Circuit(n=circ.n, gates=circ.gates, n_inputs=circ.n_inputs, n_weights=circ.n_weights,
+                   masks=np.array([z for _, z in xz], dtype=np.uint64),
+                   xmasks=np.array([x for x, _ in xz], dtype=np.uint64),
+                   name=circ.name + "_pauli")
+
+
+def random_pauli_strings(rng, n: int, count: int, max_weight: int = 3):
+    """Random Pauli strings (ops dicts) of weight 1..max_weight."""
+    out = []
+    for _ in range(count):
+        k = int(rng.integers(1, min(max_weight, n) + 1))
+        qs = rng.choice(n, size=k, replace=False)
+        out.append({int(q): "XYZ"[int(rng.integers(0, 3))] for q in qs})
+    return out
 
 
 def z_masks(n: int, extra=()) -> np.ndarray:
