@@ -102,6 +102,22 @@ typedef struct qtm_multi_s *qtm_multi_t;
 int qtm_circuit_create(int32_t n_qubits, const qtm_gate *gates, int32_t n_gates,
                        int32_t n_inputs, int32_t n_weights, const uint64_t *obs_zmask,
                        int32_t n_obs, qtm_circuit_t *out);
+
+/* As qtm_circuit_create, with observables that are general Pauli strings
+ * (the paper admits any observable, Sec. II-A; its benchmarks use Z only).
+ * Observable m has, on qubit q, the factor I, X, Z or Y for bits
+ * (obs_xmask[m], obs_zmask[m]) at q = (0, 0), (1, 0), (0, 1) or (1, 1).
+ * obs_xmask may be NULL (every observable a Z string: qtm_circuit_create).
+ * Neither mask may have a bit >= n_qubits.  Z strings are evaluated inside
+ * the sweeps; each string with X or Y factors costs one more read pass over
+ * the final states in the forward and adds its term to the backward's
+ * initial bra (one more read of the states and a write of the bra), and
+ * the final states are then always stored (in the workspace when
+ * qtm_forward gets state = NULL).  In an uneven batch (qtm_multi_create)
+ * such circuits run one by one after the persistent kernels. */
+int qtm_circuit_create_pauli(int32_t n_qubits, const qtm_gate *gates, int32_t n_gates,
+                             int32_t n_inputs, int32_t n_weights, const uint64_t *obs_xmask,
+                             const uint64_t *obs_zmask, int32_t n_obs, qtm_circuit_t *out);
 int qtm_circuit_destroy(qtm_circuit_t c);
 
 /* Tune the kernel path of a circuit (see QTM_OPT_*). */

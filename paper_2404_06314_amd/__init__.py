@@ -47,16 +47,31 @@ def _stream_ptr(stream=None):
 
 
 class Circuit:
-    """A validated circuit handle (gate list + Z-string observables)."""
+    """A validated circuit handle (gate list + Pauli-string observables).
 
-    def __init__(self, n_qubits: int, gates, n_inputs: int, n_weights: int, masks):
+    ``masks`` are the observables' Z-parts; ``xmasks`` (optional) their
+    X-parts: on qubit q the factor is X for bits (1, 0), Y for (1, 1), Z for
+    (0, 1).  Without ``xmasks`` every observable is a Z string."""
+
+    def __init__(self, n_qubits: int, gates, n_inputs: int, n_weights: int, masks, xmasks=None):
         lib = _lib.load()
         g = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 5))
         m = np.ascontiguousarray(np.asarray(masks, dtype=np.uint64).reshape(-1))
         h = ctypes.c_void_p()
-        _lib.check(lib.qtm_circuit_create(n_qubits, g.ctypes.data_as(ctypes.c_void_p), g.shape[0],
-                                          n_inputs, n_weights, m.ctypes.data_as(ctypes.c_void_p),
-                                          m.shape[0], ctypes.byref(h)))
+        if xmasks is None:
+            _lib.check(lib.qtm_circuit_create(n_qubits, g.ctypes.data_as(ctypes.c_void_p), g.shape[0],
+                                              n_inputs, n_weights, m.ctypes.data_as(ctypes.c_void_p),
+                                              m.shape[0], ctypes.byref(h)))
+            xm = None
+        else:
+            xm = np.ascontiguousarray(np.asarray(xmasks, dtype=np.uint64).reshape(-1))
+            if xm.shape != m.shape:
+                raise ValueError("xmasks and masks must have the same length")
+            _lib.check(lib.qtm_circuit_create_pauli(
+                n_qubits, g.ctypes.data_as(ctypes.c_void_p), g.shape[0], n_inputs, n_weights,
+                xm.ctypes.data_as(ctypes.c_void_p), m.ctypes.data_as(ctypes.c_void_p), m.shape[0],
+                ctypes.byref(h)))
+        self.xmasks = xm
         self._h = h
         self.n = int(n_qubits)
         self.gates = g
@@ -67,8 +82,10 @@ class Circuit:
 
     @classmethod
     def from_workload(cls, circ):
-        """From a ``workloads.Circuit``-like object (n, gates, n_inputs, n_weights, masks)."""
-        return cls(circ.n, circ.gates, circ.n_inputs, circ.n_weights, circ.masks)
+        """From a ``workloads.Circuit``-like object (n, gates, n_inputs, n_weights, masks
+        and optionally xmasks)."""
+        return cls(circ.n, circ.gates, circ.n_inputs, circ.n_weights, circ.masks,
+                   getattr(circ, "xmasks", None))
 
     @property
     def handle(self):

@@ -32,6 +32,7 @@ _I64 = ctypes.c_int64
 _SZ = ctypes.c_size_t
 SIGNATURES = {
     "qtm_circuit_create": (ctypes.c_int, [_I32, _P, _I32, _I32, _I32, _P, _I32, _P]),
+    "qtm_circuit_create_pauli": (ctypes.c_int, [_I32, _P, _I32, _I32, _I32, _P, _P, _I32, _P]),
     "qtm_circuit_destroy": (ctypes.c_int, [_P]),
     "qtm_set_option": (ctypes.c_int, [_P, _I32, _I64]),
     "qtm_state_bytes": (ctypes.c_int, [_P, _I32, _I32, _P]),

@@ -138,13 +138,13 @@ struct qtm_circuit_s {
   std::map<std::pair<int, int>, HostPlan> hplans;
   int jit = 0;  // QTM_OPT_JIT
   std::map<std::tuple<int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision)
-  DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm;
+  DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm, part_pauli;
   DevBuf jac_state, jac_G, jac_gw, jac_out;
 
   ~qtm_circuit_s() {
     for (void *p : owned) (void)hipFree(p);
     for (DevBuf *b : {&cs, &part, &gocc, &lam, &state_ws, &mats, &coef, &part_obs, &part_grad,
-                      &part_norm, &jac_state, &jac_G, &jac_gw, &jac_out})
+                      &part_norm, &part_pauli, &jac_state, &jac_G, &jac_gw, &jac_out})
       b->release();
   }
 };
@@ -152,7 +152,7 @@ struct qtm_circuit_s {
 struct qtm_multi_s {
   std::vector<qtm_circuit_t> items;
   std::vector<int64_t> in_off, w_off, out_off, st_off;
-  std::vector<int32_t> narrow;  // items below 4 qubits: per-item plain path
+  std::vector<int32_t> narrow;  // items run one by one: below 4 qubits, or X / Y observables
   MultiRuntime *rt = nullptr;   // every other item: persistent kernels
   std::unique_ptr<EventTimer> timer;
   ~qtm_multi_s() { multi_runtime_destroy(rt); }
@@ -182,7 +182,19 @@ int ensure_device(qtm_circuit_t c) {
     widx.push_back(d.gates[k].src == S_SCALED ? d.gates[k].q1 : 0);
   }
   const ParamCsr pc = param_csr(d);
+  std::vector<int32_t> nd_idx;
+  std::vector<uint64_t> nd_x, nd_z;
+  for (size_t m = 0; m < d.pauli_x.size(); ++m)
+    if (d.pauli_x[m]) {
+      nd_idx.push_back((int32_t)m);
+      nd_x.push_back(d.pauli_x[m]);
+      nd_z.push_back(d.pauli_z[m]);
+    }
+  g.n_nd = (int)nd_idx.size();
   int rc;
+  if ((rc = upload(&g.nd_idx, nd_idx, c->owned))) return rc;
+  if ((rc = upload(&g.nd_x, nd_x, c->owned))) return rc;
+  if ((rc = upload(&g.nd_z, nd_z, c->owned))) return rc;
   if ((rc = upload(&g.masks, d.masks, c->owned))) return rc;
   if ((rc = upload(&g.occ_src, src, c->owned))) return rc;
   if ((rc = upload(&g.occ_idx, idx, c->owned))) return rc;
@@ -269,6 +281,7 @@ JitSpec jit_spec(qtm_circuit_t c, int precision, const HostPlan &hp) {
   sp.M = (int)c->desc.masks.size();
   sp.n_blocks = hp.n_blocks;
   sp.masks = c->desc.masks;
+  sp.seed_add = c->desc.has_offdiag();
   sp.hp = &hp;
   return sp;
 }
@@ -316,8 +329,30 @@ int check_common(qtm_circuit_t c, int32_t batch, int32_t precision) {
 
 size_t elem_bytes(int precision) { return precision == QTM_C128 ? 16 : 8; }
 
+int forward_sweeps(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, const double *w,
+                   double *out, void *state, bool keep, hipStream_t s);
+
+// Forward pass: the sweeps (or per-gate kernels) with the diagonal
+// observables, then the observables with X or Y factors.
 int do_forward(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, const double *w,
                double *out, void *state, bool keep, hipStream_t s) {
+  const DevCircuit &d = c->dev;
+  int rc;
+  if (d.n_nd > 0) {
+    // observables with X or Y factors are read from the stored final states
+    keep = true;
+    if ((rc = c->part_pauli.ensure(pauli_part_doubles(d, B) * sizeof(double)))) return rc;
+  }
+  if ((rc = forward_sweeps(c, B, prec, x, w, out, state, keep, s))) return rc;
+  hipError_t e = prec == QTM_C64
+                     ? launch_pauli_expval<float>(d, B, state, (double *)c->part_pauli.p, out, s)
+                     : launch_pauli_expval<double>(d, B, state, (double *)c->part_pauli.p, out, s);
+  if (e != hipSuccess) return hip_fail(e, "pauli observables launch");
+  return QTM_OK;
+}
+
+int forward_sweeps(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, const double *w,
+                   double *out, void *state, bool keep, hipStream_t s) {
   const DevCircuit &d = c->dev;
   int rc;
   if (use_fused(c)) {
@@ -405,13 +440,20 @@ const char *qtm_version(void) { return "qtm 0.1 (gfx950)"; }
 int qtm_circuit_create(int32_t n_qubits, const qtm_gate *gates, int32_t n_gates, int32_t n_inputs,
                        int32_t n_weights, const uint64_t *obs_zmask, int32_t n_obs,
                        qtm_circuit_t *out) {
+  return qtm_circuit_create_pauli(n_qubits, gates, n_gates, n_inputs, n_weights, nullptr, obs_zmask,
+                                  n_obs, out);
+}
+
+int qtm_circuit_create_pauli(int32_t n_qubits, const qtm_gate *gates, int32_t n_gates,
+                             int32_t n_inputs, int32_t n_weights, const uint64_t *obs_xmask,
+                             const uint64_t *obs_zmask, int32_t n_obs, qtm_circuit_t *out) {
   if (!out) return fail(QTM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   std::unique_ptr<qtm_circuit_s> c(new (std::nothrow) qtm_circuit_s());
   if (!c) return fail(QTM_ERR_WORKSPACE, "out of host memory");
   std::string err;
   int rc = validate_and_build(n_qubits, reinterpret_cast<const Gate *>(gates), n_gates, n_inputs,
-                              n_weights, obs_zmask, n_obs, c->desc, err);
+                              n_weights, obs_zmask, obs_xmask, n_obs, c->desc, err);
   if (rc) return fail(rc, err);
   c->hinfo.gates = c->desc.gates;
   c->hinfo.gate_occ = c->desc.gate_occ;
@@ -698,6 +740,7 @@ int qtm_autotune(qtm_circuit_t c, int32_t batch, int32_t precision, void *stream
     mix(sz, sizeof sz);
     mix(c->desc.gates.data(), c->desc.gates.size() * sizeof(Gate));
     mix(c->desc.masks.data(), c->desc.masks.size() * sizeof(uint64_t));
+    mix(c->desc.pauli_x.data(), c->desc.pauli_x.size() * sizeof(uint64_t));
     char buf[40];
     snprintf(buf, sizeof buf, "n%d_%016llx", info.n, (unsigned long long)h);
     info.signature = buf;
@@ -732,7 +775,7 @@ int qtm_multi_create(const qtm_circuit_t *items, int32_t count, qtm_multi_t *out
     m->w_off.push_back(wo);
     m->out_off.push_back(oo);
     m->st_off.push_back(so);
-    if (c->desc.n >= kMinTileQubits) {
+    if (c->desc.n >= kMinTileQubits && !c->desc.has_offdiag()) {
       const int kt = default_kt(c, QTM_C64);
       const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
       wide.push_back(MultiItemIn{&c->desc, kt, klo, io, wo, oo, so / 8});

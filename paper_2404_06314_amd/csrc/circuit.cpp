@@ -11,8 +11,8 @@
 namespace qtm {
 
 int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_inputs,
-                       int32_t n_weights, const uint64_t *masks, int32_t n_obs,
-                       CircuitDesc &out, std::string &err) {
+                       int32_t n_weights, const uint64_t *masks, const uint64_t *xmasks,
+                       int32_t n_obs, CircuitDesc &out, std::string &err) {
   char buf[256];
   if (n > 30) {
     err = "n_qubits > 30 is not supported";
@@ -96,12 +96,15 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
     out.gates.push_back(c);
   }
   for (int32_t m = 0; m < n_obs; ++m) {
-    if (n < 64 && (masks[m] >> n) != 0) {
+    const uint64_t xm = xmasks ? xmasks[m] : 0;
+    if (n < 64 && ((masks[m] | xm) >> n) != 0) {
       snprintf(buf, sizeof buf, "observable %d: mask has a bit >= n_qubits", m);
       err = buf;
       return QTM_ERR_INVALID_ARG;
     }
-    out.masks.push_back(masks[m]);
+    out.masks.push_back(xm ? 0 : masks[m]);
+    out.pauli_x.push_back(xm);
+    out.pauli_z.push_back(masks[m]);
   }
   out.gate_occ.assign(out.gates.size(), -1);
   for (size_t k = 0; k < out.gates.size(); ++k)

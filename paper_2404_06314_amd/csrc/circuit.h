@@ -78,7 +78,17 @@ struct Plan {
 struct CircuitDesc {
   int32_t n = 0, n_inputs = 0, n_weights = 0;
   std::vector<Gate> gates;
+  // Observables as Pauli strings (X-part, Z-part; Y sets both bits).  masks
+  // is what the sweeps and the diagonal kernels evaluate: the Z-part of a
+  // Z string, and 0 (the identity) for a string with X or Y factors, whose
+  // value and bra term the off-diagonal Pauli kernels supply.
   std::vector<uint64_t> masks;
+  std::vector<uint64_t> pauli_x, pauli_z;
+  bool has_offdiag() const {
+    for (uint64_t x : pauli_x)
+      if (x) return true;
+    return false;
+  }
   // parameter occurrences (rotations) in gate order
   std::vector<int32_t> occ_gate;  // occurrence -> gate index
   std::vector<int32_t> gate_occ;  // gate -> occurrence or -1
@@ -96,8 +106,8 @@ ParamCsr param_csr(const CircuitDesc &c);
 
 // Returns 0 or a QTM_ERR_* code with a message.
 int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_inputs,
-                       int32_t n_weights, const uint64_t *masks, int32_t n_obs,
-                       CircuitDesc &out, std::string &err);
+                       int32_t n_weights, const uint64_t *zmasks, const uint64_t *xmasks,
+                       int32_t n_obs, CircuitDesc &out, std::string &err);
 
 // Plan the fused path for tile size kt (<= n) with klo contiguous low qubits.
 Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo);

@@ -207,6 +207,7 @@ static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const do
     a.M = d.n_obs;
     a.G = G;
     a.seed_sgn = p.seed_sgn;
+    a.seed_add = sw == 0 && d.n_nd > 0;
     a.part_grad = part_grad;
     a.n_gslots = p.n_gslots > 0 ? p.n_gslots : 1;
     a.part_norm = part_norm;
@@ -264,6 +265,8 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
                           double *gx, hipStream_t s, SweepTimer *tm, const JitSweeps *js) {
   hipError_t e = prep<R>(d, p, B, x, w, mats, coef, s);
   if (e != hipSuccess) return e;
+  // bra term of observables with X or Y factors, added in the first sweep
+  if ((e = launch_pauli_seed<R>(d, B, state, lam, G, false, s)) != hipSuccess) return e;
 #define BWD_CALL(K) e = run_bwd<R, K>(d, p, B, G, mats, state, lam, part_grad, part_norm, s, tm, js)
   QTM_KT_DISPATCH(p.kt, BWD_CALL)
 #undef BWD_CALL

@@ -27,6 +27,7 @@ struct JitSpec {
   bool dbl = false;   // complex128 (else complex64)
   int M = 0;          // observables
   int n_blocks = 0;   // fused blocks (matrix table stride per sample)
+  bool seed_add = false;  // backward: lam holds a bra term to add in the first sweep
   std::vector<uint64_t> masks;
   const HostPlan *hp = nullptr;
 };

@@ -20,6 +20,10 @@ struct DevCircuit {
   // parameter slot -> occurrences with the other factor of a scaled angle
   int32_t *w_ptr = nullptr, *w_list = nullptr, *w_fac = nullptr;
   int32_t *x_ptr = nullptr, *x_list = nullptr, *x_fac = nullptr;
+  // observables with X or Y factors: their indices and Pauli strings
+  int n_nd = 0;
+  int32_t *nd_idx = nullptr;
+  uint64_t *nd_x = nullptr, *nd_z = nullptr;
 };
 
 struct HostCircuitInfo {
@@ -58,6 +62,16 @@ hipError_t launch_obs_final(const double *part, int B, int nblk, int M, double *
 hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, const double *x,
                           const double *w, double *gw, double *gx, hipStream_t s);
 size_t plain_part_doubles(const DevCircuit &d, int B);
+// Observables with X or Y factors, from the final states: out[b][idx_j]
+// (normalised).  part: pauli_part_doubles(d, B) doubles.
+size_t pauli_part_doubles(const DevCircuit &d, int B);
+template <typename R>
+hipError_t launch_pauli_expval(const DevCircuit &d, int B, const void *state, double *part, double *out,
+                               hipStream_t s);
+// Their bra term (see k_pauli_seed), written to lam or added to it.
+template <typename R>
+hipError_t launch_pauli_seed(const DevCircuit &d, int B, const void *psi, void *lam, const double *G,
+                             bool accumulate, hipStream_t s);
 hipError_t launch_onehot(double *G, int B, int M, int m, hipStream_t s);
 hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, const double *x,
                               const double *w, int m, double *jw, double *jx, hipStream_t s);

@@ -204,6 +204,7 @@ __global__ void __launch_bounds__(kMultiNT, 2) k_multi_bwd(MultiStatic ms, Multi
     a.M = (int)I[MI_M];
     a.G = io.G + I[MI_OUTOFF];
     a.seed_sgn = ms.ssg + I[MI_SSG];
+    a.seed_add = 0;
     a.part_grad = ms.part_grad + I[MI_PGRAD];
     a.n_gslots = (int)I[MI_NGS];
     a.part_norm = ms.part_norm + I[MI_PNORM];

@@ -150,8 +150,6 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// out[b][m] = sum over partial blocks, in block order; divided by the norm
-// when `normalise` is set.
 // <Z_m> of sample b: sum over the partial rows of column m, divided by the
 // sum of column M (the norm).  One workgroup per (m, b), fixed-order sums.
 __global__ void __launch_bounds__(256) k_obs_final(const double *__restrict__ part, int nblk, int M,
@@ -314,6 +312,125 @@ __global__ void k_scatter_jac(const double *__restrict__ gocc, int B, int n_occ,
 }
 
 // ---------------------------------------------------------------------------
+// Pauli strings with X or Y factors (Sec. II-A: any observable).  For the
+// string (xm, zm), P|y> = i^nY (-1)^popcount(y & zm) |y ^ xm> with nY the
+// number of Y factors, so <P> = i^nY sum_x conj(psi_x) s(x ^ xm) psi_(x ^ xm),
+// s(v) = (-1)^popcount(v & zm).  With p the lowest qubit of xm, the pair
+// (x, y = x ^ xm), bit p of x clear, contributes i^nY [a s(y) + conj(a) s(x)]
+// for a = conj(psi_x) psi_y; s(x) s(y) = (-1)^nY, so this is
+// (-1)^(nY/2) s(x) 2 Re a for even nY and (-1)^((nY+1)/2) s(y) 2 Im a for odd.
+
+__device__ __forceinline__ uint64_t insert_zero_bit(uint64_t i, int p) {
+  const uint64_t lo = i & ((1ull << p) - 1);
+  return ((i >> p) << (p + 1)) | lo;
+}
+
+// Per (sample, block) FP64 partial sums of every off-diagonal string's pair
+// terms, then (column n_nd) of |psi|^2: part[b][block][n_nd + 1].
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+    k_pauli_partial(const Cx<R> *__restrict__ st, int n, int n_nd, const uint64_t *__restrict__ px,
+                    const uint64_t *__restrict__ pz, double *__restrict__ part, int nblk) {
+  __shared__ double red[kThreads / 64];
+  const int b = blockIdx.y;
+  const int64_t half = (int64_t)1 << (n - 1);
+  const Cx<R> *s = st + ((int64_t)b << n);
+  for (int j = 0; j <= n_nd; ++j) {
+    double acc = 0.0;
+    if (j < n_nd) {
+      const uint64_t xm = px[j], zm = pz[j];
+      const int p = __ffsll((unsigned long long)xm) - 1;
+      const int ny = __popcll(xm & zm);
+      const double sgn = ((ny + 1) >> 1) & 1 ? -1.0 : 1.0;  // (-1)^(nY/2) or (-1)^((nY+1)/2)
+      for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < half;
+           i += (int64_t)nblk * kThreads) {
+        const uint64_t x = insert_zero_bit((uint64_t)i, p), y = x ^ xm;
+        const double ax = s[x].x, bx = s[x].y, ay = s[y].x, by = s[y].y;
+        if (ny & 1) {
+          const double im = ax * by - bx * ay;
+          acc += parity_u64(y & zm) ? -sgn * 2.0 * im : sgn * 2.0 * im;
+        } else {
+          const double re = ax * ay + bx * by;
+          acc += parity_u64(x & zm) ? -sgn * 2.0 * re : sgn * 2.0 * re;
+        }
+      }
+    } else {
+      for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < half;
+           i += (int64_t)nblk * kThreads) {
+        const Cx<R> u = s[2 * i], v = s[2 * i + 1];
+        acc += (double)u.x * u.x + (double)u.y * u.y + (double)v.x * v.x + (double)v.y * v.y;
+      }
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int wv = 0; wv < kThreads / 64; ++wv) t += red[wv];
+      part[((int64_t)b * nblk + blockIdx.x) * (n_nd + 1) + j] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// out[b][idx_j] = (sum of column j) / (sum of column n_nd), fixed order;
+// one workgroup per (string, sample).
+__global__ void __launch_bounds__(256) k_pauli_final(const double *__restrict__ part, int nblk, int n_nd,
+                                                     const int32_t *__restrict__ idx, int M,
+                                                     double *__restrict__ out) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x, b = blockIdx.y;
+  const double *p = part + (int64_t)b * nblk * (n_nd + 1);
+  double acc = 0.0, nrm = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+    acc += p[(int64_t)k * (n_nd + 1) + j];
+    nrm += p[(int64_t)k * (n_nd + 1) + n_nd];
+  }
+  acc = block_sum(acc, sh);
+  nrm = block_sum(nrm, sh);
+  if (threadIdx.x == 0) out[(int64_t)b * M + idx[j]] = acc / nrm;
+}
+
+// Bra term of the off-diagonal strings: sum_j G[b][idx_j] (P_j psi)_x minus
+// (sum_j G[b][idx_j]) psi_x, the latter cancelling what the diagonal seed
+// adds for their identity masks.  Written to lam, or added to it.
+template <typename R>
+__global__ void k_pauli_seed(const Cx<R> *__restrict__ psi, Cx<R> *__restrict__ lam, int B, int n,
+                             int n_nd, const int32_t *__restrict__ idx, const uint64_t *__restrict__ px,
+                             const uint64_t *__restrict__ pz, const double *__restrict__ G, int M,
+                             int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ((int64_t)B << n)) return;
+  const int b = (int)(i >> n);
+  const uint64_t x = (uint64_t)i & ((1ull << n) - 1);
+  const Cx<R> *s = psi + ((int64_t)b << n);
+  double re = 0.0, im = 0.0, gsum = 0.0;
+  for (int j = 0; j < n_nd; ++j) {
+    const double g = G[(int64_t)b * M + idx[j]];
+    gsum += g;
+    const uint64_t y = x ^ px[j];
+    double vr = s[y].x, vi = s[y].y;
+    if (parity_u64(y & pz[j])) {
+      vr = -vr;
+      vi = -vi;
+    }
+    switch (__popcll(px[j] & pz[j]) & 3) {  // times i^nY
+      case 0: re += g * vr; im += g * vi; break;
+      case 1: re -= g * vi; im += g * vr; break;
+      case 2: re -= g * vr; im -= g * vi; break;
+      default: re += g * vi; im -= g * vr; break;
+    }
+  }
+  re -= gsum * (double)s[x].x;
+  im -= gsum * (double)s[x].y;
+  if (accumulate) {
+    re += (double)lam[i].x;
+    im += (double)lam[i].y;
+  }
+  lam[i] = Cx<R>{(R)re, (R)im};
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 
 static inline unsigned nb(int64_t work) { return (unsigned)((work + kThreads - 1) / kThreads); }
@@ -367,6 +484,8 @@ hipError_t plain_backward(const DevCircuit &d, const HostCircuitInfo &h, int B, 
   const int n = d.n;
   const int64_t dim = (int64_t)1 << n;
   k_plain_seed<R><<<nb((int64_t)B * dim), kThreads, 0, s>>>(psi, lam, B, n, d.masks, d.n_obs, G);
+  hipError_t e0 = launch_pauli_seed<R>(d, B, psi, lam, G, true, s);
+  if (e0 != hipSuccess) return e0;
   const int nblk = plain_nblk(B, dim / 2);
   for (int k = (int)h.gates.size() - 1; k >= 0; --k) {
     const Gate &g = h.gates[k];
@@ -423,6 +542,45 @@ hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, co
                                               w, m, d.n_obs, jw, jx);
   return hipGetLastError();
 }
+
+static int pauli_nblk(const DevCircuit &d, int B) { return plain_nblk(B, (int64_t)1 << (d.n - 1)); }
+
+size_t pauli_part_doubles(const DevCircuit &d, int B) {
+  return (size_t)B * pauli_nblk(d, B) * (d.n_nd + 1);
+}
+
+template <typename R>
+hipError_t launch_pauli_expval(const DevCircuit &d, int B, const void *state, double *part, double *out,
+                               hipStream_t s) {
+  if (d.n_nd == 0) return hipSuccess;
+  const int nblk = pauli_nblk(d, B);
+  k_pauli_partial<R><<<dim3(nblk, B), kThreads, 0, s>>>((const Cx<R> *)state, d.n, d.n_nd, d.nd_x,
+                                                       d.nd_z, part, nblk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_pauli_final<<<dim3(d.n_nd, B), red_threads(nblk), 0, s>>>(part, nblk, d.n_nd, d.nd_idx, d.n_obs,
+                                                             out);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_pauli_seed(const DevCircuit &d, int B, const void *psi, void *lam, const double *G,
+                             bool accumulate, hipStream_t s) {
+  if (d.n_nd == 0) return hipSuccess;
+  k_pauli_seed<R><<<nb((int64_t)B << d.n), kThreads, 0, s>>>((const Cx<R> *)psi, (Cx<R> *)lam, B, d.n,
+                                                            d.n_nd, d.nd_idx, d.nd_x, d.nd_z, G,
+                                                            d.n_obs, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+template hipError_t launch_pauli_expval<float>(const DevCircuit &, int, const void *, double *, double *,
+                                               hipStream_t);
+template hipError_t launch_pauli_expval<double>(const DevCircuit &, int, const void *, double *, double *,
+                                                hipStream_t);
+template hipError_t launch_pauli_seed<float>(const DevCircuit &, int, const void *, void *, const double *,
+                                             bool, hipStream_t);
+template hipError_t launch_pauli_seed<double>(const DevCircuit &, int, const void *, void *, const double *,
+                                              bool, hipStream_t);
 
 size_t plain_part_doubles(const DevCircuit &d, int B) {
   const int64_t dim = (int64_t)1 << d.n;

@@ -488,6 +488,7 @@ struct BwdArgs {
   int M;
   const double *G;         // [B][M]
   const double *seed_sgn;  // [M][16]
+  int seed_add;            // first sweep: lam holds a bra term to add to D psi
   double *part_grad;       // [B][n_gslots][gridDim.x][3]
   int n_gslots;
   double *part_norm;       // [B][gridDim.x]
