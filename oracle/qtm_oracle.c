@@ -36,6 +36,10 @@
  *
  * Gate record: int32 x 5 = type, q0, q1, src, index.
  *   type 0 RX, 1 RY, 2 RZ, 3 CNOT (q0 control, q1 target), 4 CZ;
+ *   fixed one-qubit gates on q0: 5 H, 6 X, 7 Y, 8 Z, 9 S, 10 S^dag, 11 T,
+ *   12 T^dag, 13 SX (square root of X);
+ *   controlled rotations 14 CRX, 15 CRY, 16 CRZ: q0 control, q1 target, the
+ *   rotation applied where the control bit is 1 (src 1 or 2 only);
  *   src 1 = inputs[index], 2 = weights[index],
  *   3 = weights[q1] * inputs[index] (trainable input scaling of the
  *       ansatz of Sec. III-A, Eq. (7): angle lambda_j s_i; the chain rule
@@ -51,7 +55,8 @@
 
 typedef double complex cplx;
 
-enum { O_RX = 0, O_RY = 1, O_RZ = 2, O_CNOT = 3, O_CZ = 4 };
+enum { O_RX = 0, O_RY = 1, O_RZ = 2, O_CNOT = 3, O_CZ = 4, O_H = 5, O_SX = 13, O_CRX = 14,
+       O_CRZ = 16 };
 enum { O_SRC_NONE = 0, O_SRC_INPUT = 1, O_SRC_WEIGHT = 2, O_SRC_SCALED = 3 };
 
 /* Observable m is the Pauli string with X-part xmasks[m] and Z-part
@@ -70,17 +75,23 @@ typedef struct {
 
 static uint64_t xmask_of(const circ_t *c, int m) { return c->xmasks ? c->xmasks[m] : 0; }
 
-static int is_param(int type) { return type == O_RX || type == O_RY || type == O_RZ; }
+static int is_rot(int type) { return type == O_RX || type == O_RY || type == O_RZ; }
+static int is_crot(int type) { return type >= O_CRX && type <= O_CRZ; }
+static int is_fixed(int type) { return type >= O_H && type <= O_SX; }
+static int is_param(int type) { return is_rot(type) || is_crot(type); }
 
 static int check_circuit(const circ_t *c) {
   if (c->n < 1 || c->n > 30 || c->n_gates < 0 || c->n_obs < 0) return -1;
   for (int k = 0; k < c->n_gates; ++k) {
     const int32_t *g = c->gates + 5 * k;
-    if (g[0] < 0 || g[0] > 4) return -1;
+    if (g[0] < 0 || g[0] > O_CRZ) return -1;
     if (g[1] < 0 || g[1] >= c->n) return -1;
-    if (!is_param(g[0])) {
+    if (is_fixed(g[0])) continue;
+    if (!is_rot(g[0])) {
       if (g[2] < 0 || g[2] >= c->n || g[2] == g[1]) return -1;
-    } else {
+    }
+    if (is_crot(g[0]) && g[3] != O_SRC_INPUT && g[3] != O_SRC_WEIGHT) return -1;
+    if (is_param(g[0])) {
       if (g[3] == O_SRC_INPUT && (g[4] < 0 || g[4] >= c->n_inputs)) return -1;
       if (g[3] == O_SRC_WEIGHT && (g[4] < 0 || g[4] >= c->n_weights)) return -1;
       if (g[3] == O_SRC_SCALED &&
@@ -129,6 +140,25 @@ static void rot_deriv(int type, double t, cplx d[2][2]) {
   }
 }
 
+/* Matrices of the fixed one-qubit gates, from their definitions. */
+static void fixed_matrix(int type, cplx u[2][2]) {
+  const double r = 1.0 / sqrt(2.0);
+  u[0][0] = 1; u[0][1] = 0; u[1][0] = 0; u[1][1] = 1;
+  switch (type) {
+    case 5:  u[0][0] = r; u[0][1] = r; u[1][0] = r; u[1][1] = -r; break;   /* H */
+    case 6:  u[0][0] = 0; u[0][1] = 1; u[1][0] = 1; u[1][1] = 0; break;    /* X */
+    case 7:  u[0][0] = 0; u[0][1] = -I; u[1][0] = I; u[1][1] = 0; break;   /* Y */
+    case 8:  u[1][1] = -1; break;                                         /* Z */
+    case 9:  u[1][1] = I; break;                                          /* S */
+    case 10: u[1][1] = -I; break;                                         /* S^dag */
+    case 11: u[1][1] = (1 + I) * r; break;                                /* T: e^{i pi/4} */
+    case 12: u[1][1] = (1 - I) * r; break;                                /* T^dag */
+    default:                                                              /* SX */
+      u[0][0] = (1 + I) / 2; u[0][1] = (1 - I) / 2;
+      u[1][0] = (1 - I) / 2; u[1][1] = (1 + I) / 2;
+  }
+}
+
 static void dagger(cplx u[2][2], cplx out[2][2]) {
   out[0][0] = conj(u[0][0]); out[0][1] = conj(u[1][0]);
   out[1][0] = conj(u[0][1]); out[1][1] = conj(u[1][1]);
@@ -142,6 +172,18 @@ static void apply_1q(cplx *psi, int n, int q, cplx u[2][2], int par) {
 #pragma omp parallel for if (par) schedule(static)
   for (int64_t x = 0; x < dim; ++x) {
     if (x & bit) continue;
+    cplx a = psi[x], b = psi[x | bit];
+    psi[x] = u[0][0] * a + u[0][1] * b;
+    psi[x | bit] = u[1][0] * a + u[1][1] * b;
+  }
+}
+
+/* As apply_1q on qubit q, only where bit ctl is 1 (a controlled gate). */
+static void apply_1q_ctl(cplx *psi, int n, int ctl, int q, cplx u[2][2], int par) {
+  const int64_t dim = (int64_t)1 << n, bit = (int64_t)1 << q, cb = (int64_t)1 << ctl;
+#pragma omp parallel for if (par) schedule(static)
+  for (int64_t x = 0; x < dim; ++x) {
+    if ((x & bit) || !(x & cb)) continue;
     cplx a = psi[x], b = psi[x | bit];
     psi[x] = u[0][0] * a + u[0][1] * b;
     psi[x | bit] = u[1][0] * a + u[1][1] * b;
@@ -170,14 +212,24 @@ static void apply_cz(cplx *psi, int n, int a, int b, int par) {
 /* Apply gate k (inverse = 1 applies its adjoint). */
 static void apply_gate(cplx *psi, int n, const int32_t *g, const double *x_b,
                        const double *w, int inverse, int par) {
-  if (is_param(g[0])) {
+  if (is_rot(g[0]) || is_fixed(g[0])) {
     cplx u[2][2], ud[2][2];
-    rot_matrix(g[0], angle_of(g, x_b, w), u);
+    if (is_rot(g[0])) rot_matrix(g[0], angle_of(g, x_b, w), u);
+    else fixed_matrix(g[0], u);
     if (inverse) {
       dagger(u, ud);
       apply_1q(psi, n, g[1], ud, par);
     } else {
       apply_1q(psi, n, g[1], u, par);
+    }
+  } else if (is_crot(g[0])) {
+    cplx u[2][2], ud[2][2];
+    rot_matrix(g[0] - O_CRX, angle_of(g, x_b, w), u);
+    if (inverse) {
+      dagger(u, ud);
+      apply_1q_ctl(psi, n, g[1], g[2], ud, par);
+    } else {
+      apply_1q_ctl(psi, n, g[1], g[2], u, par);
     }
   } else if (g[0] == O_CNOT) {
     apply_cnot(psi, n, g[1], g[2], par); /* self-inverse */
@@ -270,9 +322,19 @@ static void reverse_sweep(const circ_t *c, const double *x_b, const double *w,
     apply_gate(phi, c->n, g, x_b, w, 1, par);
     if (is_param(g[0])) {
       cplx d[2][2];
-      rot_deriv(g[0], angle_of(g, x_b, w), d);
       memcpy(mu, phi, sizeof(cplx) * dim);
-      apply_1q(mu, c->n, g[1], d, par);
+      if (is_rot(g[0])) {
+        rot_deriv(g[0], angle_of(g, x_b, w), d);
+        apply_1q(mu, c->n, g[1], d, par);
+      } else {
+        /* d/dt of |0><0| (x) I + |1><1| (x) R(t) on (control, target) is
+         * |1><1| (x) dR/dt: zero where the control bit is 0 */
+        const int64_t cb = (int64_t)1 << g[1];
+        rot_deriv(g[0] - O_CRX, angle_of(g, x_b, w), d);
+        for (int64_t x = 0; x < dim; ++x)
+          if (!(x & cb)) mu[x] = 0;
+        apply_1q_ctl(mu, c->n, g[1], g[2], d, par);
+      }
       for (int j = 0; j < n_bra; ++j)
         g_occ[(int64_t)j * c->n_gates + k] = two_re_inner(lam[j], mu, dim, par);
     } else {

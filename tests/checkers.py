@@ -30,6 +30,13 @@ I2 = np.eye(2, dtype=complex)
 P0 = np.array([[1, 0], [0, 0]], dtype=complex)
 P1 = np.array([[0, 0], [0, 1]], dtype=complex)
 PAULI = {W.RX: PX, W.RY: PY, W.RZ: PZ}
+_R2 = 1 / math.sqrt(2)
+FIXED = {
+    W.H: np.array([[1, 1], [1, -1]]) * _R2, W.X: PX, W.Y: PY, W.Z: PZ,
+    W.S: np.diag([1, 1j]), W.SDG: np.diag([1, -1j]),
+    W.T: np.diag([1, np.exp(0.25j * np.pi)]), W.TDG: np.diag([1, np.exp(-0.25j * np.pi)]),
+    W.SX: sla.sqrtm(PX),
+}
 
 
 def kron_on(n, ops: dict):
@@ -51,6 +58,12 @@ def brute_unitary(circ, x_b, w):
         if t in W.PARAM_TYPES:
             th = _angle(g, x_b, w)
             G = kron_on(n, {q0: sla.expm(-0.5j * th * PAULI[t])})
+        elif t in W.FIXED_TYPES:
+            G = kron_on(n, {q0: FIXED[t]})
+        elif t in W.CONTROLLED_TYPES:
+            th = _angle(g, x_b, w)
+            R = sla.expm(-0.5j * th * PAULI[t - W.CRX])
+            G = kron_on(n, {q0: P0}) + kron_on(n, {q0: P1, q1: R})
         elif t == W.CNOT:
             G = kron_on(n, {q0: P0}) + kron_on(n, {q0: P1, q1: PX})
         else:

@@ -35,6 +35,11 @@ MUTATIONS = {
                            "u[0][0] = 0;  u[0][1] = I;\n      u[1][0] = -I;"),
     "pauli_x_taken_as_z": ("} else if (xb) {", "} else if (0) {"),
     "pauli_bra_drops_G": ("lam[j][x] += gm * mu[x];", "lam[j][x] += mu[x];"),
+    "h_sign_on_wrong_entry": ("case 5:  u[0][0] = r; u[0][1] = r; u[1][0] = r; u[1][1] = -r;",
+                              "case 5:  u[0][0] = r; u[0][1] = -r; u[1][0] = r; u[1][1] = r;"),
+    "s_phase_conjugated": ("case 9:  u[1][1] = I;", "case 9:  u[1][1] = -I;"),
+    "crot_control_ignored": ("if ((x & bit) || !(x & cb)) continue;", "if (x & bit) continue;"),
+    "crot_derivative_unmasked": ("          if (!(x & cb)) mu[x] = 0;\n", "          (void)cb;\n"),
     "split_remainder_last": ("*lo = t * base + (t < rem ? t : rem);\n  *hi = *lo + base + (t < rem ? 1 : 0);",
                              "*lo = t * base + (t > T - 1 - rem ? t - (T - rem) : 0);\n  *hi = *lo + base + (t >= T - rem ? 1 : 0);"),
 }

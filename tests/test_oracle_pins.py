@@ -526,3 +526,98 @@ def test_pauli_finite_differences_and_jacobian():
         _, gwm, gxm = oracle.vjp(c, x, w, Gm)
         np.testing.assert_allclose(jw[:, m, :].sum(axis=0), gwm, atol=1e-12)
         np.testing.assert_allclose(jx[:, m, :], gxm, atol=1e-12)
+
+
+# --- fixed one-qubit gates and controlled rotations --------------------------
+
+def _circ(n, gates, n_inputs=0, n_weights=1, strings=None):
+    c = W.Circuit(n=n, gates=np.array(gates, np.int32).reshape(-1, 5), n_inputs=n_inputs,
+                  n_weights=n_weights, masks=np.array([1], np.uint64))
+    return W.with_observables(c, strings) if strings else c
+
+
+def test_fixed_gate_closed_forms():
+    """Textbook facts: H|0> = |+>, S H|0> = |+i>, T T = S, X and Y flip Z,
+    SX SX = X, Z H|0> = |->."""
+    none = np.zeros((1, 0))
+    w = np.zeros(1)
+    axes = [{0: "X"}, {0: "Y"}, {0: "Z"}]
+    cases = [
+        ([[W.H, 0, 0, 0, 0]], [1, 0, 0]),
+        ([[W.H, 0, 0, 0, 0], [W.S, 0, 0, 0, 0]], [0, 1, 0]),
+        ([[W.H, 0, 0, 0, 0], [W.SDG, 0, 0, 0, 0]], [0, -1, 0]),
+        ([[W.H, 0, 0, 0, 0], [W.T, 0, 0, 0, 0], [W.T, 0, 0, 0, 0]], [0, 1, 0]),
+        ([[W.H, 0, 0, 0, 0], [W.TDG, 0, 0, 0, 0], [W.TDG, 0, 0, 0, 0]], [0, -1, 0]),
+        ([[W.H, 0, 0, 0, 0], [W.T, 0, 0, 0, 0]], [math.sqrt(0.5), math.sqrt(0.5), 0]),
+        ([[W.X, 0, 0, 0, 0]], [0, 0, -1]),
+        ([[W.Y, 0, 0, 0, 0]], [0, 0, -1]),
+        ([[W.SX, 0, 0, 0, 0], [W.SX, 0, 0, 0, 0]], [0, 0, -1]),
+        ([[W.SX, 0, 0, 0, 0]], [0, -1, 0]),
+        ([[W.H, 0, 0, 0, 0], [W.Z, 0, 0, 0, 0]], [-1, 0, 0]),
+    ]
+    for gates, want in cases:
+        ev = oracle.forward(_circ(1, gates, strings=axes), none, w)
+        np.testing.assert_allclose(ev[0], want, atol=1e-14, err_msg=str(gates))
+
+
+def test_controlled_rotation_closed_forms():
+    """CRY(t) with the control in |1>: <Z_t> = cos t; control in |0>: 1 and no
+    gradient; control in |+> (H): (1 + cos t) / 2 with derivative -sin t / 2.
+    CRZ(t) between |+> states: <X_t> = (1 + cos t) / 2 (the target's Bloch
+    vector turns by t about z where the control is 1)."""
+    for t in (-2.2, -0.5, 0.3, 1.7, 3.0):
+        w = np.array([t])
+        z1 = [{1: "Z"}]
+        ev = oracle.forward(_circ(2, [[W.X, 0, 0, 0, 0], [W.CRY, 0, 1, W.SRC_WEIGHT, 0]], strings=z1),
+                            np.zeros((1, 0)), w)
+        assert abs(ev[0, 0] - math.cos(t)) < 1e-14
+        ev, gw, _ = oracle.vjp(_circ(2, [[W.CRY, 0, 1, W.SRC_WEIGHT, 0]], strings=z1),
+                               np.zeros((1, 0)), w, np.ones((1, 1)))
+        assert abs(ev[0, 0] - 1) < 1e-14 and abs(gw[0]) < 1e-15
+        ev, gw, _ = oracle.vjp(_circ(2, [[W.H, 0, 0, 0, 0], [W.CRY, 0, 1, W.SRC_WEIGHT, 0]], strings=z1),
+                               np.zeros((1, 0)), w, np.ones((1, 1)))
+        assert abs(ev[0, 0] - (1 + math.cos(t)) / 2) < 1e-14
+        assert abs(gw[0] + math.sin(t) / 2) < 1e-14
+        ev, gw, _ = oracle.vjp(_circ(2, [[W.H, 0, 0, 0, 0], [W.H, 1, 0, 0, 0],
+                                         [W.CRZ, 0, 1, W.SRC_WEIGHT, 0]], strings=[{1: "X"}]),
+                               np.zeros((1, 0)), w, np.ones((1, 1)))
+        assert abs(ev[0, 0] - (1 + math.cos(t)) / 2) < 1e-14
+        assert abs(gw[0] + math.sin(t) / 2) < 1e-14
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 2**31 - 1), n=st.integers(1, 5), ng=st.integers(0, 30))
+def test_extended_gates_brute_force(seed, n, ng):
+    rng = np.random.default_rng(seed)
+    c = W.with_observables(W.random_circuit(rng, n, ng, extended=0.5), W.random_pauli_strings(rng, n, 3))
+    wl = W.random_workload(rng, c, 2)
+    for b in range(2):
+        psi = oracle.state(c, wl.inputs[b], wl.weights)
+        np.testing.assert_allclose(psi, C.brute_state(c, wl.inputs[b], wl.weights), atol=1e-12)
+    ev = oracle.forward(c, wl.inputs, wl.weights)
+    for b in range(2):
+        np.testing.assert_allclose(ev[b], C.brute_expvals(c, wl.inputs[b], wl.weights), atol=1e-12)
+
+
+def test_extended_gates_finite_differences():
+    """Random circuits with fixed gates and controlled rotations (parameters
+    shared between gates): the adjoint VJP against central differences."""
+    rng = np.random.default_rng(71)
+    for n in (2, 4, 5):
+        c = W.with_observables(W.random_circuit(rng, n, 40, n_inputs=3, n_weights=4, extended=0.5),
+                               W.random_pauli_strings(rng, n, 3))
+        wl = W.random_workload(rng, c, 2)
+        x, w, G = wl.inputs, wl.weights, wl.grad_out
+        _, gw, gx = oracle.vjp(c, x, w, G)
+        h = 1e-6
+        L = lambda xx, ww: float(np.sum(G * oracle.forward(c, xx, ww)))
+        for j in range(c.n_weights):
+            wp, wm = w.copy(), w.copy()
+            wp[j] += h
+            wm[j] -= h
+            assert abs((L(x, wp) - L(x, wm)) / (2 * h) - gw[j]) < 1e-8, (n, j)
+        for i in range(c.n_inputs):
+            xp, xm = x.copy(), x.copy()
+            xp[0, i] += h
+            xm[0, i] -= h
+            assert abs((L(xp, w) - L(xm, w)) / (2 * h) - gx[0, i]) < 1e-8, (n, i)

@@ -7,7 +7,10 @@ random numbers, and nothing that simulates a state.
 
 Gate record format (int32 x 5): ``type, q0, q1, src, index``.
 
-* ``type``: 0 RX, 1 RY, 2 RZ, 3 CNOT (q0 = control, q1 = target), 4 CZ.
+* ``type``: 0 RX, 1 RY, 2 RZ, 3 CNOT (q0 = control, q1 = target), 4 CZ;
+  fixed one-qubit gates on q0: 5 H, 6 X, 7 Y, 8 Z, 9 S, 10 S^dag, 11 T,
+  12 T^dag, 13 SX; controlled rotations 14 CRX, 15 CRY, 16 CRZ (q0 =
+  control, q1 = target, src 1 or 2).
 * ``src``: 0 none (entanglers), 1 input vector, 2 weight vector, 3 weight-
   scaled input: angle ``weights[q1] * inputs[index]`` (the trainable input
   scaling lambda * s of the paper's ansatz, Sec. III-A Eq. (7)).
@@ -34,6 +37,10 @@ from dataclasses import dataclass, field
 import numpy as np
 
 RX, RY, RZ, CNOT, CZ = 0, 1, 2, 3, 4
+H, X, Y, Z, S, SDG, T, TDG, SX = 5, 6, 7, 8, 9, 10, 11, 12, 13
+CRX, CRY, CRZ = 14, 15, 16
+FIXED_TYPES = (H, X, Y, Z, S, SDG, T, TDG, SX)
+CONTROLLED_TYPES = (CRX, CRY, CRZ)
 SRC_NONE, SRC_INPUT, SRC_WEIGHT, SRC_SCALED = 0, 1, 2, 3
 PARAM_TYPES = (RX, RY, RZ)
 
@@ -258,12 +265,26 @@ def uneven_items(count: int = 1024, seed: int = 1004, n_range=(8, 16),
 
 
 def random_circuit(rng, n: int, n_gates: int, n_inputs: int = 3,
-                   n_weights: int = 5, n_obs: int = 3, scaled: float = 0.0) -> Circuit:
+                   n_weights: int = 5, n_obs: int = 3, scaled: float = 0.0,
+                   extended: float = 0.0) -> Circuit:
     """Random gate list over all gate types and random qubit pairs, with
     random parameter slots (parameters may be shared between gates).  With
-    ``scaled`` > 0 that fraction of the rotations reads a weight-scaled input."""
+    ``scaled`` > 0 that fraction of the rotations reads a weight-scaled input;
+    with ``extended`` > 0 that fraction of the gates is a fixed one-qubit gate
+    or (n >= 2) a controlled rotation."""
     g = []
     for _ in range(n_gates):
+        if extended > 0 and rng.random() < extended:
+            if n >= 2 and rng.random() < 0.4:
+                t = int(rng.choice(CONTROLLED_TYPES))
+                a, b = rng.choice(n, size=2, replace=False)
+                if rng.random() < 0.4:
+                    g.append((t, int(a), int(b), SRC_INPUT, int(rng.integers(0, n_inputs))))
+                else:
+                    g.append((t, int(a), int(b), SRC_WEIGHT, int(rng.integers(0, n_weights))))
+            else:
+                g.append((int(rng.choice(FIXED_TYPES)), int(rng.integers(0, n)), 0, SRC_NONE, 0))
+            continue
         t = int(rng.integers(0, 5)) if n >= 2 else int(rng.integers(0, 3))
         if t in PARAM_TYPES:
             q = int(rng.integers(0, n))
