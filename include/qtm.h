@@ -39,8 +39,8 @@
  * throws; qtm_last_error() gives a message for the calling thread's last
  * failure.
  */
-#ifndef QTM_H
-#define QTM_H
+#ifndef QTM_PUBLIC_HEADER_
+#define QTM_PUBLIC_HEADER_
 
 #include <stddef.h>
 #include <stdint.h>
@@ -59,6 +59,18 @@ extern "C" {
                                     this (circuit, batch, precision) */
 
 enum { QTM_RX = 0, QTM_RY = 1, QTM_RZ = 2, QTM_CNOT = 3, QTM_CZ = 4 };
+/* Fixed one-qubit gates (on q0): Hadamard, Pauli X, Y, Z, S = diag(1, i),
+ * S^dag, T = diag(1, e^{i pi/4}), T^dag, SX = sqrt(X) = [[1+i, 1-i],
+ * [1-i, 1+i]] / 2.  They fuse into the per-wire blocks of the fused path. */
+enum { QTM_H = 5, QTM_X = 6, QTM_Y = 7, QTM_Z = 8, QTM_S = 9, QTM_SDG = 10, QTM_T = 11,
+       QTM_TDG = 12, QTM_SX = 13 };
+/* Controlled rotations: q0 = control, q1 = target, src = QTM_SRC_INPUT or
+ * QTM_SRC_WEIGHT; the rotation exp(-i t P / 2) acts on the target where the
+ * control bit is 1.  Circuits with them run on the per-gate path
+ * (QTM_PATH_FUSED returns QTM_ERR_UNSUPPORTED for them, and so do the
+ * fused-plan diagnostics and qtm_autotune); in an uneven batch they run one
+ * by one after the persistent kernels. */
+enum { QTM_CRX = 14, QTM_CRY = 15, QTM_CRZ = 16 };
 enum { QTM_SRC_NONE = 0, QTM_SRC_INPUT = 1, QTM_SRC_WEIGHT = 2, QTM_SRC_SCALED = 3 };
 enum { QTM_C64 = 0, QTM_C128 = 1 }; /* state amplitudes: complex float / complex double */
 
@@ -95,7 +107,8 @@ typedef struct {
 typedef struct qtm_circuit_s *qtm_circuit_t;
 typedef struct qtm_multi_s *qtm_multi_t;
 
-/* Validate and copy a circuit (host arrays).  1 <= n_qubits <= 30;
+/* Validate and copy a circuit (host arrays).  1 <= n_qubits <= 30; gate
+ * types as above (an unknown type is QTM_ERR_UNSUPPORTED);
  * obs_zmask[m] must have no bit >= n_qubits and n_obs >= 1.  Gates are
  * applied in list order (paper Eq. (7): the ansatz is a product of layers).
  * *out receives a new handle on success. */
@@ -264,4 +277,4 @@ const char *qtm_version(void);
 #ifdef __cplusplus
 }
 #endif
-#endif /* QTM_H */
+#endif /* QTM_PUBLIC_HEADER_ */

@@ -19,6 +19,8 @@ QTM_ERR_HIP = -4
 QTM_ERR_STATE = -5
 
 QTM_RX, QTM_RY, QTM_RZ, QTM_CNOT, QTM_CZ = 0, 1, 2, 3, 4
+QTM_H, QTM_X, QTM_Y, QTM_Z, QTM_S, QTM_SDG, QTM_T, QTM_TDG, QTM_SX = range(5, 14)
+QTM_CRX, QTM_CRY, QTM_CRZ = 14, 15, 16
 QTM_SRC_NONE, QTM_SRC_INPUT, QTM_SRC_WEIGHT, QTM_SRC_SCALED = 0, 1, 2, 3
 QTM_C64, QTM_C128 = 0, 1
 QTM_PATH_AUTO, QTM_PATH_PLAIN, QTM_PATH_FUSED = 0, 1, 2

@@ -152,7 +152,8 @@ struct qtm_circuit_s {
 struct qtm_multi_s {
   std::vector<qtm_circuit_t> items;
   std::vector<int64_t> in_off, w_off, out_off, st_off;
-  std::vector<int32_t> narrow;  // items run one by one: below 4 qubits, or X / Y observables
+  std::vector<int32_t> narrow;  // items run one by one: below 4 qubits, X / Y observables or
+                                // controlled rotations
   MultiRuntime *rt = nullptr;   // every other item: persistent kernels
   std::unique_ptr<EventTimer> timer;
   ~qtm_multi_s() { multi_runtime_destroy(rt); }
@@ -218,6 +219,8 @@ int default_kt(const qtm_circuit_s *c, int precision) {
 
 // Host plan for (kt, klo) of this precision (planned once, kept).
 int get_host_plan(qtm_circuit_t c, int precision, const HostPlan **out) {
+  if (c->desc.has_crot())
+    return fail(QTM_ERR_UNSUPPORTED, "controlled rotations run on the per-gate path only");
   const int kt = default_kt(c, precision);
   const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
   auto key = std::make_pair(kt, klo);
@@ -311,7 +314,7 @@ int get_jit(qtm_circuit_t c, int precision, bool load, const JitSweeps **out) {
 
 bool use_fused(const qtm_circuit_s *c) {
   if (c->path == QTM_PATH_PLAIN) return false;
-  return c->desc.n >= kMinTileQubits;
+  return c->desc.n >= kMinTileQubits && !c->desc.has_crot();
 }
 
 int check_common(qtm_circuit_t c, int32_t batch, int32_t precision) {
@@ -321,6 +324,8 @@ int check_common(qtm_circuit_t c, int32_t batch, int32_t precision) {
     return fail(QTM_ERR_INVALID_ARG, "precision must be QTM_C64 or QTM_C128");
   if (c->path == QTM_PATH_FUSED && c->desc.n < kMinTileQubits)
     return fail(QTM_ERR_UNSUPPORTED, "the fused path needs at least 4 qubits");
+  if (c->path == QTM_PATH_FUSED && c->desc.has_crot())
+    return fail(QTM_ERR_UNSUPPORTED, "controlled rotations run on the per-gate path only");
   size_t amps = (size_t)batch << c->desc.n;
   if (amps / (size_t)batch != ((size_t)1 << c->desc.n))
     return fail(QTM_ERR_INVALID_ARG, "batch too large");
@@ -642,6 +647,8 @@ int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *la
 int qtm_plan_json(qtm_circuit_t c, int32_t precision, char *buf, size_t len, size_t *needed) {
   if (!c) return fail(QTM_ERR_INVALID_ARG, "NULL circuit");
   if (c->desc.n < kMinTileQubits) return fail(QTM_ERR_UNSUPPORTED, "no fused plan below 4 qubits");
+  if (c->desc.has_crot())
+    return fail(QTM_ERR_UNSUPPORTED, "controlled rotations run on the per-gate path only");
   const int kt = default_kt(c, precision);
   const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
   Plan plan = make_plan(c->desc, kt, klo);
@@ -724,6 +731,8 @@ int qtm_autotune(qtm_circuit_t c, int32_t batch, int32_t precision, void *stream
   int rc = check_common(c, batch, precision);
   if (rc) return rc;
   if (c->desc.n < kMinTileQubits) return fail(QTM_ERR_UNSUPPORTED, "no fused path below 4 qubits");
+  if (c->desc.has_crot())
+    return fail(QTM_ERR_UNSUPPORTED, "controlled rotations run on the per-gate path only");
   TuneInfo info;
   info.n = c->desc.n;
   info.n_inputs = c->desc.n_inputs;
@@ -775,7 +784,7 @@ int qtm_multi_create(const qtm_circuit_t *items, int32_t count, qtm_multi_t *out
     m->w_off.push_back(wo);
     m->out_off.push_back(oo);
     m->st_off.push_back(so);
-    if (c->desc.n >= kMinTileQubits && !c->desc.has_offdiag()) {
+    if (c->desc.n >= kMinTileQubits && !c->desc.has_offdiag() && !c->desc.has_crot()) {
       const int kt = default_kt(c, QTM_C64);
       const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
       wide.push_back(MultiItemIn{&c->desc, kt, klo, io, wo, oo, so / 8});

@@ -40,7 +40,7 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
   out.n_weights = n_weights;
   for (int32_t k = 0; k < n_gates; ++k) {
     const Gate &g = gates[k];
-    if (g.type < 0 || g.type > 4) {
+    if (g.type < 0 || g.type > G_CRZ) {
       snprintf(buf, sizeof buf, "gate %d: unknown type %d", k, g.type);
       err = buf;
       return QTM_ERR_UNSUPPORTED;
@@ -50,7 +50,12 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
       err = buf;
       return QTM_ERR_INVALID_ARG;
     }
-    if (is_rotation(g.type)) {
+    if (is_param(g.type)) {
+      if (is_crot(g.type) && g.src != S_INPUT && g.src != S_WEIGHT) {
+        snprintf(buf, sizeof buf, "gate %d: a controlled rotation needs src INPUT or WEIGHT", k);
+        err = buf;
+        return QTM_ERR_INVALID_ARG;
+      }
       if (g.src == S_INPUT) {
         if (g.index < 0 || g.index >= n_inputs) {
           snprintf(buf, sizeof buf, "gate %d: input index %d out of range", k, g.index);
@@ -74,7 +79,8 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
         err = buf;
         return QTM_ERR_INVALID_ARG;
       }
-    } else {
+    }
+    if (!is_rotation(g.type) && !is_fixed(g.type)) {  // CNOT, CZ, controlled rotations
       if (g.q1 < 0 || g.q1 >= n) {
         snprintf(buf, sizeof buf, "gate %d: qubit %d out of range", k, g.q1);
         err = buf;
@@ -87,12 +93,11 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
       }
     }
     Gate c = g;
-    if (!is_rotation(g.type)) {
+    if (!is_param(g.type)) {
       c.src = S_NONE;
       c.index = 0;
-    } else if (g.src != S_SCALED) {
-      c.q1 = 0;
     }
+    if (is_fixed(g.type) || (is_rotation(g.type) && g.src != S_SCALED)) c.q1 = 0;
     out.gates.push_back(c);
   }
   for (int32_t m = 0; m < n_obs; ++m) {
@@ -108,7 +113,7 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
   }
   out.gate_occ.assign(out.gates.size(), -1);
   for (size_t k = 0; k < out.gates.size(); ++k)
-    if (is_rotation(out.gates[k].type)) {
+    if (is_param(out.gates[k].type)) {
       out.gate_occ[k] = (int32_t)out.occ_gate.size();
       out.occ_gate.push_back((int32_t)k);
     }
@@ -177,7 +182,7 @@ static std::vector<FOp> fuse(const CircuitDesc &c) {
   std::vector<int> open(c.n, -1);
   for (size_t k = 0; k < c.gates.size(); ++k) {
     const Gate &g = c.gates[k];
-    if (is_rotation(g.type)) {
+    if (is_rotation(g.type) || is_fixed(g.type)) {
       int q = g.q0;
       if (open[q] < 0) {
         FOp o;
@@ -189,8 +194,8 @@ static std::vector<FOp> fuse(const CircuitDesc &c) {
       }
       FOp &o = ops[open[q]];
       o.gates.push_back((int32_t)k);
-      o.has_param = true;
-      if (g.type != G_RZ) o.diagonal = false;
+      if (is_rotation(g.type)) o.has_param = true;
+      if (!is_diag1(g.type)) o.diagonal = false;
     } else {
       open[g.q0] = -1;
       open[g.q1] = -1;
@@ -684,7 +689,7 @@ std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostP
       h.blk.push_back(gt.index);
       h.blk.push_back(gt.src == S_SCALED ? gt.q1 : 0);
       h.blk.push_back(occ);
-      h.occ_gslot[occ] = o.gslot;
+      if (occ >= 0) h.occ_gslot[occ] = o.gslot;
     }
   }
   // Z-string signs of the register bits of the last forward stage (the

@@ -29,7 +29,13 @@
 
 namespace qtm {
 
-enum GateType : int32_t { G_RX = 0, G_RY = 1, G_RZ = 2, G_CNOT = 3, G_CZ = 4 };
+enum GateType : int32_t {
+  G_RX = 0, G_RY = 1, G_RZ = 2, G_CNOT = 3, G_CZ = 4,
+  // fixed one-qubit gates
+  G_H = 5, G_X = 6, G_Y = 7, G_Z = 8, G_S = 9, G_SDG = 10, G_T = 11, G_TDG = 12, G_SX = 13,
+  // controlled rotations: q0 control, q1 target
+  G_CRX = 14, G_CRY = 15, G_CRZ = 16
+};
 enum GateSrc : int32_t { S_NONE = 0, S_INPUT = 1, S_WEIGHT = 2, S_SCALED = 3 };
 
 struct Gate {
@@ -37,6 +43,11 @@ struct Gate {
 };
 
 inline bool is_rotation(int t) { return t == G_RX || t == G_RY || t == G_RZ; }
+inline bool is_fixed(int t) { return t >= G_H && t <= G_SX; }
+inline bool is_crot(int t) { return t >= G_CRX && t <= G_CRZ; }
+inline bool is_param(int t) { return is_rotation(t) || is_crot(t); }
+// diagonal in the computational basis (commutes with CZ and CNOT controls)
+inline bool is_diag1(int t) { return t == G_RZ || t == G_Z || t == G_S || t == G_SDG || t == G_T || t == G_TDG; }
 
 // Fused-op kinds (host) and device op codes.
 enum FKind : int32_t { FK_BLOCK = 0, FK_CNOT = 1, FK_CZ = 2 };
@@ -84,6 +95,11 @@ struct CircuitDesc {
   // value and bra term the off-diagonal Pauli kernels supply.
   std::vector<uint64_t> masks;
   std::vector<uint64_t> pauli_x, pauli_z;
+  bool has_crot() const {
+    for (const Gate &g : gates)
+      if (is_crot(g.type)) return true;
+    return false;
+  }
   bool has_offdiag() const {
     for (uint64_t x : pauli_x)
       if (x) return true;

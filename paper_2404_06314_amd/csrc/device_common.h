@@ -141,6 +141,28 @@ __device__ __forceinline__ float dpp_sum_to_lane63(float v) {
 }
 
 __device__ __forceinline__ int parity_u64(uint64_t v) { return __popcll(v) & 1; }
+
+// Matrix of a fixed one-qubit gate (type 5 H, 6 X, 7 Y, 8 Z, 9 S, 10 S^dag,
+// 11 T, 12 T^dag, 13 SX), row-major re[4] / im[4] in FP64.
+__device__ __forceinline__ void fixed_gate(int type, double (&re)[4], double (&im)[4]) {
+  const double r = 0.70710678118654752440;  // 1 / sqrt 2
+  for (int k = 0; k < 4; ++k) re[k] = im[k] = 0.0;
+  re[0] = re[3] = 1.0;
+  switch (type) {
+    case 5: re[0] = re[1] = re[2] = r; re[3] = -r; break;
+    case 6: re[0] = re[3] = 0.0; re[1] = re[2] = 1.0; break;
+    case 7: re[0] = re[3] = 0.0; im[1] = -1.0; im[2] = 1.0; break;
+    case 8: re[3] = -1.0; break;
+    case 9: re[3] = 0.0; im[3] = 1.0; break;
+    case 10: re[3] = 0.0; im[3] = -1.0; break;
+    case 11: re[3] = r; im[3] = r; break;
+    case 12: re[3] = r; im[3] = -r; break;
+    default:  // SX
+      re[0] = re[1] = re[2] = re[3] = 0.5;
+      im[0] = im[3] = 0.5;
+      im[1] = im[2] = -0.5;
+  }
+}
 __device__ __forceinline__ int parity_u32(uint32_t v) { return __popc(v) & 1; }
 
 }  // namespace qtm

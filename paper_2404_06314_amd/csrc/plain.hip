@@ -60,9 +60,31 @@ __global__ void k_plain_init(Cx<R> *__restrict__ st, int64_t total, int64_t dim)
 }
 
 template <typename R>
+__device__ __forceinline__ M2<R> fixed_m2(int type, bool adjoint) {
+  double re[4], im[4];
+  fixed_gate(type, re, im);
+  M2<R> m;
+  if (adjoint) {
+    m.a = {(R)re[0], (R)-im[0]};
+    m.b = {(R)re[2], (R)-im[2]};
+    m.c = {(R)re[1], (R)-im[1]};
+    m.d = {(R)re[3], (R)-im[3]};
+  } else {
+    m.a = {(R)re[0], (R)im[0]};
+    m.b = {(R)re[1], (R)im[1]};
+    m.c = {(R)re[2], (R)im[2]};
+    m.d = {(R)re[3], (R)im[3]};
+  }
+  return m;
+}
+
+// One-qubit gate on q for every (sample, pair): a rotation (type 0-2, angle
+// of occurrence occ) or a fixed gate (type 5-13); with ctl >= 0 only on the
+// pairs whose bit ctl is 1 (a controlled rotation).
+template <typename R>
 __global__ void k_plain_1q(Cx<R> *__restrict__ a, Cx<R> *__restrict__ a2, int B, int n, int q,
                            int type, int occ, const double2 *__restrict__ cs, int n_occ,
-                           int adjoint) {
+                           int adjoint, int ctl) {
   const int64_t half = (int64_t)1 << (n - 1);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)B * half) return;
@@ -70,7 +92,9 @@ __global__ void k_plain_1q(Cx<R> *__restrict__ a, Cx<R> *__restrict__ a2, int B,
   int64_t p = i % half;
   int64_t lo = p & (((int64_t)1 << q) - 1);
   int64_t x0 = ((p >> q) << (q + 1)) | lo, x1 = x0 | ((int64_t)1 << q);
-  M2<R> m = rot_m2<R>(type, cs[(int64_t)b * n_occ + occ], adjoint != 0);
+  if (ctl >= 0 && !((x0 >> ctl) & 1)) return;
+  M2<R> m = type <= 2 ? rot_m2<R>(type, cs[(int64_t)b * n_occ + occ], adjoint != 0)
+                      : fixed_m2<R>(type, adjoint != 0);
   int64_t base = (int64_t)b << n;
   Cx<R> v0 = a[base + x0], v1 = a[base + x1];
   apply_m2(m, v0, v1);
@@ -185,11 +209,13 @@ __global__ void k_plain_seed(const Cx<R> *__restrict__ psi, Cx<R> *__restrict__ 
   lam[i] = Cx<R>{(R)(d * (double)psi[i].x), (R)(d * (double)psi[i].y)};
 }
 
-// g = Im <lambda| P_q |psi> for P = X, Y, Z (type 0, 1, 2), per-block FP64 partials.
+// g = Im <lambda| P_q |psi> for P = X, Y, Z (type 0, 1, 2), per-block FP64
+// partials; with ctl >= 0 the generator is |1><1|_ctl (x) P_q (a controlled
+// rotation), so only pairs whose bit ctl is 1 contribute.
 template <typename R>
 __global__ void __launch_bounds__(kThreads)
     k_plain_grad(const Cx<R> *__restrict__ psi, const Cx<R> *__restrict__ lam, int n, int q,
-                 int type, int occ, int n_occ, double *__restrict__ part, int nblk) {
+                 int type, int occ, int n_occ, double *__restrict__ part, int nblk, int ctl) {
   __shared__ double red[kThreads / 64];
   const int b = blockIdx.y;
   const int64_t half = (int64_t)1 << (n - 1);
@@ -199,6 +225,7 @@ __global__ void __launch_bounds__(kThreads)
        p += (int64_t)nblk * kThreads) {
     int64_t lo = p & (((int64_t)1 << q) - 1);
     int64_t x0 = ((p >> q) << (q + 1)) | lo, x1 = x0 | ((int64_t)1 << q);
+    if (ctl >= 0 && !((x0 >> ctl) & 1)) continue;
     double p0r = psi[base + x0].x, p0i = psi[base + x0].y;
     double p1r = psi[base + x1].x, p1i = psi[base + x1].y;
     double l0r = lam[base + x0].x, l0i = lam[base + x0].y;
@@ -460,9 +487,12 @@ hipError_t plain_forward(const DevCircuit &d, const HostCircuitInfo &h, int B, c
   k_plain_init<R><<<nb((int64_t)B * dim), kThreads, 0, s>>>(st, (int64_t)B * dim, dim);
   for (size_t k = 0; k < h.gates.size(); ++k) {
     const Gate &g = h.gates[k];
-    if (is_rotation(g.type))
+    if (is_rotation(g.type) || is_fixed(g.type))
       k_plain_1q<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(st, nullptr, B, n, g.q0, g.type,
-                                                                    h.gate_occ[k], cs, d.n_occ, 0);
+                                                                    h.gate_occ[k], cs, d.n_occ, 0, -1);
+    else if (is_crot(g.type))
+      k_plain_1q<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(
+          st, nullptr, B, n, g.q1, g.type - G_CRX, h.gate_occ[k], cs, d.n_occ, 0, g.q0);
     else if (g.type == G_CNOT)
       k_plain_cnot<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(st, nullptr, B, n, g.q0, g.q1);
     else
@@ -489,11 +519,17 @@ hipError_t plain_backward(const DevCircuit &d, const HostCircuitInfo &h, int B, 
   const int nblk = plain_nblk(B, dim / 2);
   for (int k = (int)h.gates.size() - 1; k >= 0; --k) {
     const Gate &g = h.gates[k];
-    if (is_rotation(g.type)) {
-      k_plain_grad<R><<<dim3(nblk, B), kThreads, 0, s>>>(psi, lam, n, g.q0, g.type, h.gate_occ[k],
-                                                         d.n_occ, part, nblk);
-      k_plain_1q<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(psi, lam, B, n, g.q0, g.type,
-                                                                    h.gate_occ[k], cs, d.n_occ, 1);
+    if (is_rotation(g.type) || is_crot(g.type)) {
+      // a controlled rotation acts on its target q1 where the control q0 is 1
+      const bool ctl = is_crot(g.type);
+      const int q = ctl ? g.q1 : g.q0, t = ctl ? g.type - G_CRX : g.type, c = ctl ? g.q0 : -1;
+      k_plain_grad<R><<<dim3(nblk, B), kThreads, 0, s>>>(psi, lam, n, q, t, h.gate_occ[k], d.n_occ,
+                                                         part, nblk, c);
+      k_plain_1q<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(psi, lam, B, n, q, t,
+                                                                    h.gate_occ[k], cs, d.n_occ, 1, c);
+    } else if (is_fixed(g.type)) {
+      k_plain_1q<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(psi, lam, B, n, g.q0, g.type, -1,
+                                                                    cs, d.n_occ, 1, -1);
     } else if (g.type == G_CNOT) {
       k_plain_cnot<R><<<nb((int64_t)B * (dim / 2)), kThreads, 0, s>>>(psi, lam, B, n, g.q0, g.q1);
     } else {

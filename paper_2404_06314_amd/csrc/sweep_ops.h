@@ -49,6 +49,16 @@ __device__ __forceinline__ MD md_rot(int type, double t) {
   }
   return r;
 }
+__device__ __forceinline__ MD md_fixed(int type) {
+  double re[4], im[4];
+  fixed_gate(type, re, im);
+  MD r;
+  for (int k = 0; k < 4; ++k) r.m[k >> 1][k & 1] = {re[k], im[k]};
+  return r;
+}
+// Matrix of gate record entry e: a rotation (types 0-2) at angle t, or a
+// fixed gate (types 5-13).
+__device__ __forceinline__ MD md_gate(int type, double t) { return type <= 2 ? md_rot(type, t) : md_fixed(type); }
 __device__ __forceinline__ MD md_pauli(int type) {
   MD r;
   r.m[0][0] = r.m[0][1] = r.m[1][0] = r.m[1][1] = {0, 0};
@@ -62,7 +72,8 @@ __device__ __forceinline__ MD md_pauli(int type) {
 // coef is set, the (px, py, pz) of every rotation j at coef[3 * occ_j].
 // blk record: [q, ng, (type, src, idx, widx, occ) x ng]; x is the sample's
 // input row.  The angle is x[idx] (src 1), w[idx] (src 2) or the scaled
-// input w[widx] * x[idx] (src 3, Eq. (7)).
+// input w[widx] * x[idx] (src 3, Eq. (7)); fixed gates have src 0 and
+// occ -1.
 constexpr int kBlkGate = 5;
 template <typename R>
 __device__ __forceinline__ void prep_block(const int32_t *__restrict__ r, const double *__restrict__ x,
@@ -71,12 +82,13 @@ __device__ __forceinline__ void prep_block(const int32_t *__restrict__ r, const 
   const int ng = r[1];
   auto ang = [&](int g) {
     const int32_t *e = r + 2 + kBlkGate * g;
+    if (e[1] == 0) return 0.0;
     if (e[1] == 3) return w[e[3]] * x[e[2]];
     return e[1] == 1 ? x[e[2]] : w[e[2]];
   };
   MD U;
   U.m[0][0] = {1, 0}; U.m[0][1] = {0, 0}; U.m[1][0] = {0, 0}; U.m[1][1] = {1, 0};
-  for (int g = 0; g < ng; ++g) U = md_mul(md_rot(r[2 + kBlkGate * g], ang(g)), U);
+  for (int g = 0; g < ng; ++g) U = md_mul(md_gate(r[2 + kBlkGate * g], ang(g)), U);
   M2<R> o;
   o.a = {(R)U.m[0][0].x, (R)U.m[0][0].y};
   o.b = {(R)U.m[0][1].x, (R)U.m[0][1].y};
@@ -88,12 +100,14 @@ __device__ __forceinline__ void prep_block(const int32_t *__restrict__ r, const 
   A.m[0][0] = {1, 0}; A.m[0][1] = {0, 0}; A.m[1][0] = {0, 0}; A.m[1][1] = {1, 0};
   for (int g = ng - 1; g >= 0; --g) {
     const int32_t *e = r + 2 + kBlkGate * g;
-    MD P = md_mul(md_mul(A, md_pauli(e[0])), md_adj(A));
-    double *cf = coef + (int64_t)e[4] * 3;
-    cf[0] = P.m[1][0].x;
-    cf[1] = P.m[1][0].y;
-    cf[2] = P.m[0][0].x;
-    A = md_mul(A, md_rot(e[0], ang(g)));
+    if (e[4] >= 0) {
+      MD P = md_mul(md_mul(A, md_pauli(e[0])), md_adj(A));
+      double *cf = coef + (int64_t)e[4] * 3;
+      cf[0] = P.m[1][0].x;
+      cf[1] = P.m[1][0].y;
+      cf[2] = P.m[0][0].x;
+    }
+    A = md_mul(A, md_gate(e[0], ang(g)));
   }
 }
 

@@ -56,7 +56,12 @@ def make(qtm, n, gates, n_in=0, n_w=0, masks=(1,)):
     (2, [[1, 0, 2, 3, 0]], 1, 2, [1], -1),                     # scaled: weight slot out of range
     (2, [[1, 0, 0, 3, 1]], 1, 2, [1], -1),                     # scaled: input slot out of range
     (2, [[1, 0, -1, 3, 0]], 1, 2, [1], -1),                    # scaled: negative weight slot
-    (2, [[7, 0, 1, 0, 0]], 0, 0, [1], -2),                     # unknown gate type
+    (2, [[17, 0, 1, 0, 0]], 0, 0, [1], -2),                    # unknown gate type
+    (2, [[5, 2, 0, 0, 0]], 0, 0, [1], -1),                     # fixed gate qubit out of range
+    (2, [[14, 0, 0, 2, 0]], 0, 1, [1], -1),                    # controlled rotation, control == target
+    (2, [[15, 0, 2, 2, 0]], 0, 1, [1], -1),                    # controlled rotation, target out of range
+    (2, [[16, 0, 1, 3, 0]], 1, 1, [1], -1),                    # controlled rotation with a scaled input
+    (2, [[14, 0, 1, 2, 1]], 0, 1, [1], -1),                    # controlled rotation, weight out of range
     (2, [], 0, 0, [4], -1),                                    # mask bit >= n
     (2, [], 0, 0, [], -1),                                     # no observable
 ])
@@ -178,3 +183,21 @@ def test_paper_ansatz_plans_and_compiles(qtm):
         _check_plan(qtm, circ, tile=5, klo=2)
     c = qtm.Circuit.from_workload(W.paper_ansatz(12, 3))
     c.jit_compile("c64")
+
+
+def test_fixed_gates_fuse_into_blocks_and_controlled_rotations_stay_per_gate(qtm):
+    """Fixed one-qubit gates plan like rotations (the plan's gate order gives
+    the oracle's results); a circuit with a controlled rotation has no fused
+    plan and reports why."""
+    rng = np.random.default_rng(3)
+    g = W.random_circuit(rng, 6, 50, extended=0.5)
+    fixed_only = W.Circuit(n=6, gates=g.gates[[int(t) not in W.CONTROLLED_TYPES for t in g.gates[:, 0]]],
+                           n_inputs=g.n_inputs, n_weights=g.n_weights, masks=g.masks)
+    assert any(int(t) in W.FIXED_TYPES for t in fixed_only.gates[:, 0])
+    _check_plan(qtm, fixed_only, tile=4, klo=2)
+    with_cr = W.Circuit(n=6, gates=np.concatenate([fixed_only.gates, [[W.CRY, 1, 4, W.SRC_WEIGHT, 0]]]).astype(np.int32),
+                        n_inputs=g.n_inputs, n_weights=g.n_weights, masks=g.masks)
+    c = qtm.Circuit.from_workload(with_cr)
+    with pytest.raises(qtm.QtmError) as ei:
+        c.plan("c64")
+    assert ei.value.code == -2 and "per-gate" in str(ei.value)
