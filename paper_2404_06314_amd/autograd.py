@@ -120,3 +120,30 @@ def _initial(size: int, init):
     if t.numel() != size:
         raise ValueError(f"initial values have {t.numel()} entries, expected {size}")
     return t
+
+
+# The paper's module name for a circuit with trainable weights (Sec. II-D).
+QuantumModule = QuantumLayer
+
+
+class HybridModule(torch.nn.Module):
+    """End-to-end differentiable hybrid model (Sec. II-C): a classical fully
+    connected pre-processing layer (input_size -> n_qubits) whose outputs are
+    the data s encoded in the circuit, the Eq. (7) quantum layer with Z on
+    every qubit (parameter sets theta and lambda), and a classical fully
+    connected post-processing layer (n_qubits -> output_size).  The gradient
+    reaches the pre-processing layer through dL/dinputs of the adjoint pass.
+    """
+
+    def __init__(self, input_size: int, output_size: int, n_qubits: int, depth: int,
+                 entangler="chain", precision="c64", device="cuda", theta_init="uniform",
+                 lambda_init="ones"):
+        super().__init__()
+        self.pre = torch.nn.Linear(input_size, n_qubits, dtype=torch.float64, device=device)
+        self.quantum = QuantumLayer.eq7(n_qubits, depth, entangler=entangler, precision=precision,
+                                        device=device, theta_init=theta_init,
+                                        lambda_init=lambda_init)
+        self.post = torch.nn.Linear(n_qubits, output_size, dtype=torch.float64, device=device)
+
+    def forward(self, x):
+        return self.post(self.quantum(self.pre(x.to(torch.float64))))

@@ -109,3 +109,36 @@ def test_c3_repeats_are_bitwise_identical(precision):
         got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, precision)
         for a, b in zip(first, got):
             assert np.array_equal(a, b), f"c3 {precision}: run {rep} differs from run 0"
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_max_qubits_n30_closed_form(precision):
+    """The largest circuit the library accepts (30 qubits, 8 GiB of complex64
+    amplitudes per sample): one RX / RY / RZ layer, a CZ ladder, then a CNOT
+    ring.  The CZs commute with every Z string and the CNOT ring maps a Z
+    string S to the Z string S' (Heisenberg picture), so <Z_S> is the product
+    of the z parts of the single-qubit Bloch vectors over S', and so is its
+    gradient (Bloch closed form), independent of the oracle."""
+    n, B = 30, 2
+    rng = np.random.default_rng(30)
+    single = W.layered_circuit(n, 1, "none")
+    ladder = [[W.CZ, i, i + 1, 0, 0] for i in range(n - 1)]
+    ring = [(i, (i + 1) % n) for i in range(n)]
+    gates = np.concatenate([single.gates, np.array(ladder, np.int32),
+                            np.array([[W.CNOT, c, t, 0, 0] for c, t in ring], np.int32)])
+    masks = [1 << q for q in range(0, n, 3)] + [(1 << 29) | 1, 0b1011 << 10]
+    circ = W.Circuit(n=n, gates=gates.astype(np.int32), n_inputs=n, n_weights=single.n_weights,
+                     masks=np.array(masks, np.uint64))
+    x = rng.uniform(-np.pi, np.pi, size=(B, n))
+    w = rng.uniform(-np.pi, np.pi, size=single.n_weights)
+    G = rng.uniform(-1, 1, size=(B, len(masks)))
+    got = run_gpu(circ, x, w, G, precision)
+    mapped = np.array([C.heisenberg_mask(int(m), ring) for m in masks], np.uint64)
+    prod = W.Circuit(n=n, gates=single.gates, n_inputs=n, n_weights=single.n_weights, masks=mapped)
+    ev = np.stack([C.bloch_expvals(prod, x[b], w) for b in range(B)])
+    gw = np.zeros(single.n_weights)
+    gx = np.zeros((B, n))
+    for b in range(B):
+        gwb, gx[b] = C.bloch_grad(prod, x[b], w, G[b])
+        gw += gwb
+    assert_parity(got, (ev, gw, gx), precision, f"n30 {precision}")

@@ -82,3 +82,46 @@ def test_layer_gradients_per_set_match_the_oracle():
     assert torch.equal(layer.theta.detach(), th0)
     np.testing.assert_allclose((lam0 - layer.get_parameter("lambda").detach()).cpu().numpy(),
                                0.1 * rgw[n_th:], rtol=0, atol=1e-5 * np.max(np.abs(rgw)) + 1e-7)
+
+
+def test_hybrid_module_shapes_on_host():
+    from paper_2404_06314_amd.autograd import HybridModule, QuantumModule, QuantumLayer
+    assert QuantumModule is QuantumLayer
+    m = HybridModule(7, 3, n_qubits=5, depth=2, device="cpu")
+    names = [n for n, _ in m.named_parameters()]
+    assert names == ["pre.weight", "pre.bias", "quantum.theta", "quantum.lambda", "post.weight",
+                     "post.bias"]
+    assert m.pre.weight.shape == (5, 7) and m.post.weight.shape == (3, 5)
+    assert m.quantum.circuit.n_inputs == 5 and m.quantum.circuit.n_obs == 5
+
+
+@pytest.mark.gpu
+def test_hybrid_module_gradients_match_the_oracle_chain_rule():
+    """Loss sum(y * R) through pre -> circuit -> post: every parameter's
+    gradient against the chain rule with the oracle's VJP for the circuit."""
+    import oracle
+    from paper_2404_06314_amd.autograd import HybridModule
+    torch.manual_seed(3)
+    m = HybridModule(6, 4, n_qubits=6, depth=2, device="cuda")
+    x = torch.randn(5, 6, dtype=torch.float64, device="cuda")
+    R = torch.randn(5, 4, dtype=torch.float64, device="cuda")
+    y = m(x)
+    (y * R).sum().backward()
+    # reference on the CPU
+    Wp, bp = m.pre.weight.detach().cpu().numpy(), m.pre.bias.detach().cpu().numpy()
+    Wq, bq = m.post.weight.detach().cpu().numpy(), m.post.bias.detach().cpu().numpy()
+    w = m.quantum.weights_vector.detach().cpu().numpy()
+    xc, Rc = x.cpu().numpy(), R.cpu().numpy()
+    a = xc @ Wp.T + bp
+    circ = W.paper_ansatz(6, 2)
+    q, _, _ = oracle.vjp(circ, a, w, np.zeros((5, 6)))
+    np.testing.assert_allclose(y.detach().cpu().numpy(), q @ Wq.T + bq, atol=1e-5)
+    Gq = Rc @ Wq
+    _, gw, ga = oracle.vjp(circ, a, w, Gq)
+    n_th = 2 * 6 * 3
+    want = {"post.weight": Rc.T @ q, "post.bias": Rc.sum(0), "quantum.theta": gw[:n_th],
+            "quantum.lambda": gw[n_th:], "pre.weight": ga.T @ xc, "pre.bias": ga.sum(0)}
+    for name, p in m.named_parameters():
+        got = p.grad.cpu().numpy()
+        ref = want[name]
+        assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref)) + 1e-6, name
