@@ -128,6 +128,16 @@ __device__ __forceinline__ float dpp_add(float x) {
   return x + __builtin_bit_cast(float, o);
 }
 
+// Sum of a float over each row of 16 lanes with DPP (every lane of the row
+// ends up holding its row's sum).  Every lane must be active.
+__device__ __forceinline__ float dpp_sum_row(float v) {
+  v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  return v;
+}
+
 // Sum of a float over all 64 lanes with DPP row operations (no LDS traffic);
 // the total ends up in lane 63.  Every lane must be active.
 __device__ __forceinline__ float dpp_sum_to_lane63(float v) {
