@@ -79,11 +79,14 @@ def sweep_bytes(n_sweeps: int, kind: int) -> int:
     return 3 + 4 * (n_sweeps - 2) + 2
 
 
-def block_ops(plan) -> int:
-    """Number of fused single-qubit blocks (U1 ops) in the encoded program."""
+def block_ops(plan, kind: int = 0) -> int:
+    """Number of fused single-qubit blocks the program applies as matrices:
+    every block in the forward (kind 0); in the backward (kind 1) the blocks
+    it un-applies, i.e. without the last block on each qubit, whose un-apply
+    the method does not need (op code 4: transition-matrix sums only)."""
     code = plan["code"]
     n = 0
-    for off in plan["sweep_off_fwd"]:
+    for off in plan["sweep_off_fwd" if kind == 0 else "sweep_off_bwd"]:
         nst = code[off]
         for s in range(nst):
             so = code[off + 90 + s]
@@ -234,9 +237,9 @@ def main():
         gbs = per_launch_bytes / avg_s / 1e9
         # algorithmic matrix-core work: every fused block is a 2x2 complex
         # gate on each of the B * 2^(n-1) pairs = 16 real MACs (32 flop) per
-        # pair, applied to psi in the forward and to psi and lambda in the
-        # backward
-        nblk = block_ops(plan)
+        # pair, applied to psi in the forward and un-applied on psi and
+        # lambda in the backward (except each qubit's last block there)
+        nblk = block_ops(plan, kind)
         flop_step = B * (1 << (circ.n - 1)) * nblk * 32 * (2 if kind == 1 else 1)
         per_launch_flop = flop_step / S
         tfs = per_launch_flop / avg_s / 1e12
@@ -414,7 +417,7 @@ def bench_uneven(args):
     flop = 0
     for c, wl in zip(circs, items):
         plan = c.plan("c64")
-        flop += (1 << (wl.circuit.n - 1)) * block_ops(plan) * 32 * (2 if kind == 1 else 1)
+        flop += (1 << (wl.circuit.n - 1)) * block_ops(plan, kind) * 32 * (2 if kind == 1 else 1)
     tfs = flop / avg_s / 1e12
     name = "k_multi_bwd" if kind == 1 else "k_multi_fwd"
     log(f"{name}: {launches} launches, avg {avg_s * 1e6:.1f} us, {flop / 1e9:.2f} GFLOP per launch "

@@ -485,8 +485,9 @@ static uint32_t pdep_bits(uint32_t v, const int *pos, int npos) {
 static int parity32(uint32_t v) { return __builtin_popcount(v) & 1; }
 
 static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, bool backward,
-                         std::vector<int32_t> &code, std::vector<int32_t> &thr,
-                         std::vector<int32_t> &sweep_offs, int32_t &max_gs) {
+                         const std::vector<char> &first_on_wire, std::vector<int32_t> &code,
+                         std::vector<int32_t> &thr, std::vector<int32_t> &sweep_offs,
+                         int32_t &max_gs) {
   const int kt = p.kt, nthr_bits = kt - kRegBits;
   const int off = (int)code.size();
   sweep_offs.push_back(off);
@@ -624,7 +625,8 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
       flush_cz();
       if (o.kind == FK_BLOCK) {
         int r = regbit_of[loc[o.q0]];
-        enc.push_back({OP_U1, r, mslot_of[o.block], o.gslot >= 0 ? local_gs[o.gslot] : -1});
+        const int32_t code_u1 = backward && first_on_wire[oi] ? OP_U1_LAST : OP_U1;
+        enc.push_back({code_u1, r, mslot_of[o.block], o.gslot >= 0 ? local_gs[o.gslot] : -1});
       } else {
         int r = regbit_of[loc[o.q1]];
         int lc = loc[o.q0];
@@ -654,10 +656,25 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
 
 Program encode_program(const CircuitDesc &c, const Plan &p) {
   Program pr;
+  // blocks that are the first op on their qubit in execution order
+  std::vector<char> first_on_wire(p.ops.size(), 0), touched(c.n, 0);
   for (const Sweep &sw : p.sweeps)
-    encode_sweep(c, p, sw, false, pr.code, pr.thr, pr.sweep_off_fwd, pr.max_gslots_per_sweep);
+    for (const Stage &st : sw.stages)
+      for (int oi : st.ops) {
+        const FOp &o = p.ops[oi];
+        if (o.kind == FK_BLOCK) {
+          if (!touched[o.q0]) first_on_wire[oi] = 1;
+          touched[o.q0] = 1;
+        } else {
+          touched[o.q0] = touched[o.q1] = 1;
+        }
+      }
+  for (const Sweep &sw : p.sweeps)
+    encode_sweep(c, p, sw, false, first_on_wire, pr.code, pr.thr, pr.sweep_off_fwd,
+                 pr.max_gslots_per_sweep);
   for (int s = (int)p.sweeps.size() - 1; s >= 0; --s)
-    encode_sweep(c, p, p.sweeps[s], true, pr.code, pr.thr, pr.sweep_off_bwd, pr.max_gslots_per_sweep);
+    encode_sweep(c, p, p.sweeps[s], true, first_on_wire, pr.code, pr.thr, pr.sweep_off_bwd,
+                 pr.max_gslots_per_sweep);
   return pr;
 }
 

@@ -33,7 +33,7 @@ constexpr int kMinTileQubits = kRegBits;
 // accumulators are staged in LDS.
 constexpr int kMaxSweepBlocks = 96;
 
-enum OpCode : int32_t { OP_U1 = 1, OP_CNOT = 2, OP_DIAG = 3 };
+enum OpCode : int32_t { OP_U1 = 1, OP_CNOT = 2, OP_DIAG = 3, OP_U1_LAST = 4 };
 
 // --- device program -------------------------------------------------------
 //
@@ -58,6 +58,13 @@ enum OpCode : int32_t { OP_U1 = 1, OP_CNOT = 2, OP_DIAG = 3 };
 //   [36 .. 40)  tile-local positions of the 4 register bits, ascending
 //   [40 ..)     ops, 4 int32 each: {code, a, b, c}
 //     OP_U1:   a = register bit, b = sweep-local matrix slot, c = sweep-local gslot or -1
+//     OP_U1_LAST (backward only): as OP_U1 for a block that is the first op
+//              on its qubit in forward order, i.e. the last one the
+//              backward meets on that qubit: its transition-matrix sums are
+//              taken, its un-apply is skipped.  Every later op of the
+//              backward acts on other qubits and commutes with it, so
+//              keeping the block applied on both psi and lambda changes no
+//              later <lambda|P|psi>, and nothing reads the final states.
 //     OP_CNOT: a = target register bit, b = 0 (control is register bit c) or
 //              1 (control is global qubit c)
 //     OP_DIAG: a = offset of a diag record (below), b, c unused

@@ -86,8 +86,8 @@ def check_program(plan, n, circ=None):
                 diag_recs = []
                 for o in range(nops):
                     op = S[ST_OPS + 4 * o: ST_OPS + 4 * o + 4]
-                    assert op[0] in (1, 2, 3)
-                    if op[0] == 1:
+                    assert op[0] in (1, 2, 3) or (op[0] == 4 and direction == "bwd")
+                    if op[0] in (1, 4):
                         assert 0 <= op[1] < 4 and 0 <= op[2] < plan["n_blocks"]
                     elif op[0] == 2:
                         assert 0 <= op[1] < 4 and op[2] in (0, 1)
@@ -182,3 +182,39 @@ def test_program_layout_empty_circuit():
     plan = q.Circuit.from_workload(circ).plan("c64")
     assert len(plan["sweeps"]) == 1 and len(plan["sweeps"][0]["stages"]) == 1
     check_program(plan, 6, circ)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_last_op_per_qubit_is_marked_in_the_backward(seed):
+    """The backward marks a fused block as T-only (op code 4) exactly when it
+    is the first op on its qubit in the plan's execution order (the last the
+    backward meets there); forward programs never carry the mark."""
+    import paper_2404_06314_amd as qtm
+    rng = np.random.default_rng(seed)
+    for n in (5, 7, 9):
+        circ = W.random_circuit(rng, n, 50, extended=0.2)
+        circ = W.Circuit(n=n, gates=circ.gates[[int(t) not in W.CONTROLLED_TYPES for t in circ.gates[:, 0]]],
+                         n_inputs=circ.n_inputs, n_weights=circ.n_weights, masks=circ.masks)
+        c = qtm.Circuit.from_workload(circ)
+        c.set_option(qtm.QTM_OPT_TILE_QUBITS, 4)
+        c.set_option(qtm.QTM_OPT_LOW_QUBITS, 2)
+        plan = c.plan("c64")
+        code = np.array(plan["code"], dtype=np.int64)
+        counts = {}
+        for direction, offs in (("fwd", plan["sweep_off_fwd"]), ("bwd", plan["sweep_off_bwd"])):
+            k = 0
+            for off in offs:
+                H = code[off:]
+                for s in range(int(H[0])):
+                    S = code[int(H[SW_STAGES + s]):]
+                    for o in range(int(S[0])):
+                        k += int(S[ST_OPS + 4 * o] == 4)
+            counts[direction] = k
+        order = [g for sw in plan["sweeps"] for st in sw["stages"] for g in st["gates"]]
+        first = {}
+        for g in order:
+            t, q0, q1 = (int(v) for v in circ.gates[g][:3])
+            for q in ((q0,) if t in W.PARAM_TYPES or t in W.FIXED_TYPES else (q0, q1)):
+                first.setdefault(q, t)
+        want = sum(1 for t in first.values() if t in W.PARAM_TYPES or t in W.FIXED_TYPES)
+        assert counts["fwd"] == 0 and counts["bwd"] == want, (n, counts, want)
