@@ -468,6 +468,16 @@ __device__ __forceinline__ void tcomp(const Cx<R> (&v)[kRegs], const Cx<R> (&l)[
   }
 }
 
+// Streaming (non-temporal) access to one complex64 amplitude of the state
+// arrays, which are read and written once per sweep.
+__device__ __forceinline__ Cx<float> ld_nt(const Cx<float> *p) {
+  const unsigned long long u = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
+  return __builtin_bit_cast(Cx<float>, u);
+}
+__device__ __forceinline__ void st_nt(Cx<float> *p, Cx<float> v) {
+  __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), reinterpret_cast<unsigned long long *>(p));
+}
+
 // Arguments of one forward sweep (one circuit, samples along blockIdx.y).
 struct FwdArgs {
   const int32_t *prog;
