@@ -80,3 +80,51 @@ def test_c3_full_batch(precision):
             vg, sc = c.jit_info(precision, direction, s)
             print(f"c3 {precision} dir {direction} sweep {s}: {vg} VGPRs, {sc} B scratch")
             assert sc <= 64
+
+
+@pytest.mark.parametrize("tile,klo", [(10, 4), (11, 3), (11, 4), (12, 5)])
+def test_matrix_core_ladder_tiles(tile, klo):
+    """CZ-ladder circuits through the matrix-core specialised sweeps (tiles of
+    10-12 qubits) at several low-qubit counts."""
+    rng = np.random.default_rng(tile * 10 + klo)
+    circ = W.layered_circuit(14, 4, "ladder", extra_masks=(0b11 << 6, (1 << 14) - 1))
+    wl = W.random_workload(rng, circ, 4)
+    got = run_gpu(circ, wl.inputs, wl.weights, wl.grad_out, "c64", qcirc=jit_circuit(circ, tile, klo))
+    assert_parity(got, oracle_ref(wl), "c64", f"jit ladder t{tile}l{klo}")
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_matrix_core_random_cz_heavy(seed):
+    """Random circuits where half the gates are CZ (between any qubits), the
+    rest rotations and CNOTs, through the matrix-core specialised sweeps."""
+    rng = np.random.default_rng(900 + seed)
+    n = 12
+    g = []
+    for _ in range(160):
+        r = rng.random()
+        if r < 0.5:
+            a, b = rng.choice(n, size=2, replace=False)
+            g.append((W.CZ, int(a), int(b), 0, 0))
+        elif r < 0.6:
+            a, b = rng.choice(n, size=2, replace=False)
+            g.append((W.CNOT, int(a), int(b), 0, 0))
+        else:
+            t = int(rng.integers(0, 3))
+            src = W.SRC_INPUT if rng.random() < 0.3 else W.SRC_WEIGHT
+            g.append((t, int(rng.integers(0, n)), 0, src, int(rng.integers(0, 4))))
+    circ = W.Circuit(n=n, gates=np.array(g, np.int32), n_inputs=4, n_weights=4,
+                     masks=rng.integers(1, 1 << n, size=5, dtype=np.uint64))
+    wl = W.random_workload(rng, circ, 3)
+    t, k = [(10, 2), (11, 4), (12, 3), (10, 5)][seed - 1]
+    got = run_gpu(circ, wl.inputs, wl.weights, wl.grad_out, "c64", qcirc=jit_circuit(circ, t, k))
+    assert_parity(got, oracle_ref(wl), "c64", f"jit cz-heavy seed={seed} t{t}l{k}")
+
+
+def test_c3_benchmarked_configuration():
+    """The n=20 workload in the configuration the benchmark times (tile 11, 4
+    low qubits, specialised sweeps) against the oracle fixture."""
+    d = np.load(os.path.join(GOLDEN, "oracle_c3_b64.npz"), allow_pickle=False)
+    wl = W.config_workload("c3")
+    got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, "c64",
+                  qcirc=jit_circuit(wl.circuit, 11, 4))
+    assert_parity(got, (d["expvals"], d["grad_w"], d["grad_x"]), "c64", "jit c3 t11l4")
