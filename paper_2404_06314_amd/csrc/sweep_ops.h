@@ -228,8 +228,19 @@ __device__ __forceinline__ constexpr int pair_lo(int p) {
   return ((p >> P) << (P + 1)) | (p & ((1 << P) - 1));
 }
 
-template <int P, int NS>
-__device__ __forceinline__ void u1_mfma_bit(Cx<float> (*const *vs)[kRegs], const MCols &A) {
+// Sign flips of A operand values (bit 31 of m), e.g. rows 2-3 of the
+// expanded gate, which negates the |1> half of every output pair.
+__device__ __forceinline__ MCols mcols_xor(const MCols &a, uint32_t m) {
+  auto f = [m](float x) { return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x) ^ m); };
+  return MCols{f(a.k0), f(a.k1), f(a.k2), f(a.k3)};
+}
+
+// Gate on register bit P of NS register tiles with the matrix cores; pair p
+// (registers pair_lo<P>(p) and that | 2^P) uses A1 if bit p of SEL is set,
+// else A0 (A1 carries the sign of a diagonal op folded into the output).
+template <int P, int NS, int SEL>
+__device__ __forceinline__ void u1_mfma_bit_sel(Cx<float> (*const *vs)[kRegs], const MCols &A0,
+                                                const MCols &A1) {
   constexpr int NP = kRegs / 2, CH = 4;  // 4 independent accumulation chains at a time
   const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -240,24 +251,31 @@ __device__ __forceinline__ void u1_mfma_bit(Cx<float> (*const *vs)[kRegs], const
       floatx4 acc[CH];
 #pragma unroll
       for (int p = 0; p < CH; ++p)
-        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(A.k0, v[pair_lo<P>(c0 + p)].x, zero, 0, 0, 0);
+        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(((SEL >> (c0 + p)) & 1) ? A1.k0 : A0.k0,
+                                                    v[pair_lo<P>(c0 + p)].x, zero, 0, 0, 0);
 #pragma unroll
       for (int p = 0; p < CH; ++p)
-        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(A.k1, v[pair_lo<P>(c0 + p)].y, acc[p], 0, 0, 0);
+        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(((SEL >> (c0 + p)) & 1) ? A1.k1 : A0.k1,
+                                                    v[pair_lo<P>(c0 + p)].y, acc[p], 0, 0, 0);
 #pragma unroll
       for (int p = 0; p < CH; ++p)
-        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(A.k2, v[pair_lo<P>(c0 + p) | (1 << P)].x,
-                                                    acc[p], 0, 0, 0);
+        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(((SEL >> (c0 + p)) & 1) ? A1.k2 : A0.k2,
+                                                    v[pair_lo<P>(c0 + p) | (1 << P)].x, acc[p], 0, 0, 0);
 #pragma unroll
       for (int p = 0; p < CH; ++p)
-        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(A.k3, v[pair_lo<P>(c0 + p) | (1 << P)].y,
-                                                    acc[p], 0, 0, 0);
+        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(((SEL >> (c0 + p)) & 1) ? A1.k3 : A0.k3,
+                                                    v[pair_lo<P>(c0 + p) | (1 << P)].y, acc[p], 0, 0, 0);
 #pragma unroll
       for (int p = 0; p < CH; ++p) {
         v[pair_lo<P>(c0 + p)] = Cx<float>{acc[p][0], acc[p][1]};
         v[pair_lo<P>(c0 + p) | (1 << P)] = Cx<float>{acc[p][2], acc[p][3]};
       }
     }
+}
+
+template <int P, int NS>
+__device__ __forceinline__ void u1_mfma_bit(Cx<float> (*const *vs)[kRegs], const MCols &A) {
+  u1_mfma_bit_sel<P, NS, 0>(vs, A, A);
 }
 
 // Apply m (adjoint = false) or m^dag (adjoint = true) to register bit p of
@@ -283,9 +301,10 @@ __device__ __forceinline__ void u1_mfma(Cx<float> (*const *vs)[kRegs], int p, co
 // interleaved costs ~30% more than issuing them one group after the other
 // (measured: 8 MFMA + 12 FMA per step take 150 cycles interleaved, 114
 // grouped, 78 + 37 alone).
-template <int P>
-__device__ __forceinline__ void bwd_u1_mfma_bit(Cx<float> (&v)[kRegs], Cx<float> (&l)[kRegs],
-                                                const MCols &A, float &tx, float &ty, float &tz) {
+template <int P, int SEL>
+__device__ __forceinline__ void bwd_u1_mfma_bit_sel(Cx<float> (&v)[kRegs], Cx<float> (&l)[kRegs],
+                                                    const MCols &A0, const MCols &A1, float &tx,
+                                                    float &ty, float &tz) {
   tx = ty = tz = 0.f;
 #pragma unroll
   for (int j = 0; j < kRegs; ++j)
@@ -295,8 +314,13 @@ __device__ __forceinline__ void bwd_u1_mfma_bit(Cx<float> (&v)[kRegs], Cx<float>
     }
   __builtin_amdgcn_sched_barrier(0);
   Cx<float>(*const vs[2])[kRegs] = {&v, &l};
-  u1_mfma_bit<P, 2>(vs, A);
+  u1_mfma_bit_sel<P, 2, SEL>(vs, A0, A1);
   __builtin_amdgcn_sched_barrier(0);
+}
+template <int P>
+__device__ __forceinline__ void bwd_u1_mfma_bit(Cx<float> (&v)[kRegs], Cx<float> (&l)[kRegs],
+                                                const MCols &A, float &tx, float &ty, float &tz) {
+  bwd_u1_mfma_bit_sel<P, 0>(v, l, A, A, tx, ty, tz);
 }
 
 __device__ __forceinline__ void bwd_u1_mfma(Cx<float> (&v)[kRegs], Cx<float> (&l)[kRegs], int p,
