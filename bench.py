@@ -79,19 +79,23 @@ def sweep_bytes(n_sweeps: int, kind: int) -> int:
     return 3 + 4 * (n_sweeps - 2) + 2
 
 
-def block_ops(plan, kind: int = 0) -> int:
-    """Number of fused single-qubit blocks the program applies as matrices:
-    every block in the forward (kind 0); in the backward (kind 1) the blocks
-    it un-applies, i.e. without the last block on each qubit, whose un-apply
-    the method does not need (op code 4: transition-matrix sums only)."""
+def block_ops(plan, kind: int = 0) -> float:
+    """Fused single-qubit blocks the program applies as matrices, in units of
+    a full 2x2 gate: in the forward (kind 0) every block, the first block on
+    each qubit counting half (op code 5: its |1> inputs are 0, so half the
+    products); in the backward (kind 1) the blocks it un-applies, i.e.
+    without the last block on each qubit, whose un-apply the method does not
+    need (op code 4: transition-matrix sums only)."""
     code = plan["code"]
-    n = 0
+    n = 0.0
     for off in plan["sweep_off_fwd" if kind == 0 else "sweep_off_bwd"]:
         nst = code[off]
         for s in range(nst):
             so = code[off + 90 + s]
             nops = code[so]
-            n += sum(1 for o in range(nops) if code[so + 40 + 4 * o] == 1)
+            for o in range(nops):
+                c = code[so + 40 + 4 * o]
+                n += 1.0 if c == 1 else 0.5 if c == 5 else 0.0
     return n
 
 
@@ -240,7 +244,7 @@ def main():
         # pair, applied to psi in the forward and un-applied on psi and
         # lambda in the backward (except each qubit's last block there)
         nblk = block_ops(plan, kind)
-        flop_step = B * (1 << (circ.n - 1)) * nblk * 32 * (2 if kind == 1 else 1)
+        flop_step = int(B * (1 << (circ.n - 1)) * nblk * 32 * (2 if kind == 1 else 1))
         per_launch_flop = flop_step / S
         tfs = per_launch_flop / avg_s / 1e12
         use_jit = args.jit and args.path == "fused"
@@ -417,7 +421,7 @@ def bench_uneven(args):
     flop = 0
     for c, wl in zip(circs, items):
         plan = c.plan("c64")
-        flop += (1 << (wl.circuit.n - 1)) * block_ops(plan, kind) * 32 * (2 if kind == 1 else 1)
+        flop += int((1 << (wl.circuit.n - 1)) * block_ops(plan, kind) * 32 * (2 if kind == 1 else 1))
     tfs = flop / avg_s / 1e12
     name = "k_multi_bwd" if kind == 1 else "k_multi_fwd"
     log(f"{name}: {launches} launches, avg {avg_s * 1e6:.1f} us, {flop / 1e9:.2f} GFLOP per launch "

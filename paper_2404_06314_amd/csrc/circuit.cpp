@@ -625,7 +625,7 @@ static void encode_sweep(const CircuitDesc &c, const Plan &p, const Sweep &sw, b
       flush_cz();
       if (o.kind == FK_BLOCK) {
         int r = regbit_of[loc[o.q0]];
-        const int32_t code_u1 = backward && first_on_wire[oi] ? OP_U1_LAST : OP_U1;
+        const int32_t code_u1 = !first_on_wire[oi] ? OP_U1 : backward ? OP_U1_LAST : OP_U1_FIRST;
         enc.push_back({code_u1, r, mslot_of[o.block], o.gslot >= 0 ? local_gs[o.gslot] : -1});
       } else {
         int r = regbit_of[loc[o.q1]];

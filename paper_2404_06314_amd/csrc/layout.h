@@ -33,7 +33,7 @@ constexpr int kMinTileQubits = kRegBits;
 // accumulators are staged in LDS.
 constexpr int kMaxSweepBlocks = 96;
 
-enum OpCode : int32_t { OP_U1 = 1, OP_CNOT = 2, OP_DIAG = 3, OP_U1_LAST = 4 };
+enum OpCode : int32_t { OP_U1 = 1, OP_CNOT = 2, OP_DIAG = 3, OP_U1_LAST = 4, OP_U1_FIRST = 5 };
 
 // --- device program -------------------------------------------------------
 //
@@ -65,6 +65,10 @@ enum OpCode : int32_t { OP_U1 = 1, OP_CNOT = 2, OP_DIAG = 3, OP_U1_LAST = 4 };
 //              backward acts on other qubits and commutes with it, so
 //              keeping the block applied on both psi and lambda changes no
 //              later <lambda|P|psi>, and nothing reads the final states.
+//     OP_U1_FIRST (forward only): as OP_U1 for a block that is the first op
+//              on its qubit: every amplitude with that qubit's bit set is
+//              still 0, so only the matrix columns of the |0> inputs are
+//              needed.
 //     OP_CNOT: a = target register bit, b = 0 (control is register bit c) or
 //              1 (control is global qubit c)
 //     OP_DIAG: a = offset of a diag record (below), b, c unused

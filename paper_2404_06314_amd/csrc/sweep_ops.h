@@ -238,7 +238,9 @@ __device__ __forceinline__ MCols mcols_xor(const MCols &a, uint32_t m) {
 // Gate on register bit P of NS register tiles with the matrix cores; pair p
 // (registers pair_lo<P>(p) and that | 2^P) uses A1 if bit p of SEL is set,
 // else A0 (A1 carries the sign of a diagonal op folded into the output).
-template <int P, int NS, int SEL>
+// LOW0: the inputs of the |1> half are known to be 0 (the gate is the first
+// on its qubit), so only the two accumulation steps of the |0> half run.
+template <int P, int NS, int SEL, bool LOW0 = false>
 __device__ __forceinline__ void u1_mfma_bit_sel(Cx<float> (*const *vs)[kRegs], const MCols &A0,
                                                 const MCols &A1) {
   constexpr int NP = kRegs / 2, CH = 4;  // 4 independent accumulation chains at a time
@@ -257,14 +259,16 @@ __device__ __forceinline__ void u1_mfma_bit_sel(Cx<float> (*const *vs)[kRegs], c
       for (int p = 0; p < CH; ++p)
         acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(((SEL >> (c0 + p)) & 1) ? A1.k1 : A0.k1,
                                                     v[pair_lo<P>(c0 + p)].y, acc[p], 0, 0, 0);
+      if constexpr (!LOW0) {
 #pragma unroll
-      for (int p = 0; p < CH; ++p)
-        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(((SEL >> (c0 + p)) & 1) ? A1.k2 : A0.k2,
-                                                    v[pair_lo<P>(c0 + p) | (1 << P)].x, acc[p], 0, 0, 0);
+        for (int p = 0; p < CH; ++p)
+          acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(((SEL >> (c0 + p)) & 1) ? A1.k2 : A0.k2,
+                                                      v[pair_lo<P>(c0 + p) | (1 << P)].x, acc[p], 0, 0, 0);
 #pragma unroll
-      for (int p = 0; p < CH; ++p)
-        acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(((SEL >> (c0 + p)) & 1) ? A1.k3 : A0.k3,
-                                                    v[pair_lo<P>(c0 + p) | (1 << P)].y, acc[p], 0, 0, 0);
+        for (int p = 0; p < CH; ++p)
+          acc[p] = __builtin_amdgcn_mfma_f32_4x4x1f32(((SEL >> (c0 + p)) & 1) ? A1.k3 : A0.k3,
+                                                      v[pair_lo<P>(c0 + p) | (1 << P)].y, acc[p], 0, 0, 0);
+      }
 #pragma unroll
       for (int p = 0; p < CH; ++p) {
         v[pair_lo<P>(c0 + p)] = Cx<float>{acc[p][0], acc[p][1]};

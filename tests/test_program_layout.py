@@ -86,8 +86,8 @@ def check_program(plan, n, circ=None):
                 diag_recs = []
                 for o in range(nops):
                     op = S[ST_OPS + 4 * o: ST_OPS + 4 * o + 4]
-                    assert op[0] in (1, 2, 3) or (op[0] == 4 and direction == "bwd")
-                    if op[0] in (1, 4):
+                    assert op[0] in (1, 2, 3) or op[0] == (4 if direction == "bwd" else 5)
+                    if op[0] in (1, 4, 5):
                         assert 0 <= op[1] < 4 and 0 <= op[2] < plan["n_blocks"]
                     elif op[0] == 2:
                         assert 0 <= op[1] < 4 and op[2] in (0, 1)
@@ -188,7 +188,8 @@ def test_program_layout_empty_circuit():
 def test_last_op_per_qubit_is_marked_in_the_backward(seed):
     """The backward marks a fused block as T-only (op code 4) exactly when it
     is the first op on its qubit in the plan's execution order (the last the
-    backward meets there); forward programs never carry the mark."""
+    backward meets there); the forward marks the same blocks with op code 5
+    (the |1> inputs of the gate are still 0)."""
     import paper_2404_06314_amd as qtm
     rng = np.random.default_rng(seed)
     for n in (5, 7, 9):
@@ -201,14 +202,14 @@ def test_last_op_per_qubit_is_marked_in_the_backward(seed):
         plan = c.plan("c64")
         code = np.array(plan["code"], dtype=np.int64)
         counts = {}
-        for direction, offs in (("fwd", plan["sweep_off_fwd"]), ("bwd", plan["sweep_off_bwd"])):
+        for direction, offs, mark in (("fwd", plan["sweep_off_fwd"], 5), ("bwd", plan["sweep_off_bwd"], 4)):
             k = 0
             for off in offs:
                 H = code[off:]
                 for s in range(int(H[0])):
                     S = code[int(H[SW_STAGES + s]):]
                     for o in range(int(S[0])):
-                        k += int(S[ST_OPS + 4 * o] == 4)
+                        k += int(S[ST_OPS + 4 * o] == mark)
             counts[direction] = k
         order = [g for sw in plan["sweeps"] for st in sw["stages"] for g in st["gates"]]
         first = {}
@@ -217,4 +218,4 @@ def test_last_op_per_qubit_is_marked_in_the_backward(seed):
             for q in ((q0,) if t in W.PARAM_TYPES or t in W.FIXED_TYPES else (q0, q1)):
                 first.setdefault(q, t)
         want = sum(1 for t in first.values() if t in W.PARAM_TYPES or t in W.FIXED_TYPES)
-        assert counts["fwd"] == 0 and counts["bwd"] == want, (n, counts, want)
+        assert counts["fwd"] == want and counts["bwd"] == want, (n, counts, want)
