@@ -65,20 +65,6 @@ def recorded_traffic(kernel: str, workload: str):
     return None
 
 
-def sweep_bytes(n_sweeps: int, kind: int) -> int:
-    """State-array reads + writes per amplitude, summed over a pass's sweeps.
-
-    forward: the first sweep generates |0> (1 write), the others read and
-    write psi (2); backward: the first sweep reads psi and writes psi and
-    lambda (3), middle sweeps read and write both (4), the last only reads
-    both (2)."""
-    if kind == 0:
-        return 1 + 2 * (n_sweeps - 1)
-    if n_sweeps == 1:
-        return 1
-    return 3 + 4 * (n_sweeps - 2) + 2
-
-
 def block_ops(plan, kind: int = 0) -> float:
     """Fused single-qubit blocks the program applies as matrices, in units of
     a full 2x2 gate: in the forward (kind 0) every block, the first block on
@@ -97,6 +83,64 @@ def block_ops(plan, kind: int = 0) -> float:
                 c = code[so + 40 + 4 * o]
                 n += 1.0 if c == 1 else 0.5 if c == 5 else 0.0
     return n
+
+
+def _sweep_block_ops(plan, kind: int, unapply_first: bool):
+    """block_ops per sweep of the pass (in its own order); with
+    unapply_first, the backward also counts each qubit's last block where
+    the specialised kernels un-apply it (every sweep but the one the
+    backward ends with, see live_work)."""
+    code = plan["code"]
+    offs = plan["sweep_off_fwd" if kind == 0 else "sweep_off_bwd"]
+    out = []
+    for i, off in enumerate(offs):
+        n = 0.0
+        nst = code[off]
+        for s in range(nst):
+            so = code[off + 90 + s]
+            for o in range(code[so]):
+                c = code[so + 40 + 4 * o]
+                n += 1.0 if c == 1 else 0.5 if c == 5 else \
+                    (1.0 if c == 4 and unapply_first and i < len(offs) - 1 else 0.0)
+        out.append(n)
+    return out
+
+
+def live_work(plan, n: int, kind: int, jit: bool):
+    """(state passes, block units) of one pass: the state-array reads and
+    writes per amplitude of the register, and the fused blocks applied as
+    full 2x2 gates over the whole register (block_ops), both summed over
+    the sweeps and counting only the work the kernels do.
+
+    The state starts at |0...0>; with D_in / D_out the qubits not excited
+    before / after forward sweep s (plan["excited"]), the amplitudes with a
+    bit of D_out set are 0 throughout sweep s.  The specialised kernels
+    (jit) run only tiles with no D_out bit among their outer qubits (all
+    tiles in the last forward sweep), read psi (and lambda) only where no
+    bit of D_in (forward) / D_out (backward) is set, and store only where
+    the next sweep reads: no D_out bit (forward, but all of the final
+    state) / no D_in bit (backward).  The compiled kernels do all of it."""
+    S = len(plan["sweeps"])
+    full = (1 << n) - 1
+    ex = plan["excited"]
+    frac = lambda m: 2.0 ** -bin(m).count("1")
+    blocks = _sweep_block_ops(plan, kind, jit)
+    passes = units = 0.0
+    for i in range(S):
+        s = i if kind == 0 else S - 1 - i  # forward index
+        din = full if s == 0 else full & ~ex[s - 1]
+        dout = full & ~ex[s]
+        if not jit:
+            din = dout = 0
+        tile = sum(1 << q for q in plan["sweeps"][s]["tile"])
+        skip = 0 if s == S - 1 else dout & ~tile
+        units += blocks[i] * frac(skip)
+        if kind == 0:
+            passes += (0.0 if s == 0 else frac(din)) + (1.0 if s == S - 1 else frac(dout))
+        else:
+            passes += frac(dout) * (1 if s == S - 1 else 2)   # psi (and lambda) read
+            passes += 0.0 if s == 0 else 2 * frac(din)         # psi and lambda stored
+    return passes, units
 
 
 def cpu_baseline(wl, threads: int, samples: int):
@@ -235,19 +279,20 @@ def main():
         c.set_option(q.QTM_OPT_TIMING, 0)
         kind = 1 if res[1][0] >= res[0][0] else 0
         ms_tot, launches = res[kind]
-        bytes_per_step = B * (1 << circ.n) * elem * sweep_bytes(S, kind)
+        use_jit = args.jit and args.path == "fused"
+        passes, units = live_work(plan, circ.n, kind, use_jit)
+        bytes_per_step = B * (1 << circ.n) * elem * passes
         per_launch_bytes = bytes_per_step / S
         avg_s = ms_tot / launches / 1e3
         gbs = per_launch_bytes / avg_s / 1e9
         # algorithmic matrix-core work: every fused block is a 2x2 complex
         # gate on each of the B * 2^(n-1) pairs = 16 real MACs (32 flop) per
         # pair, applied to psi in the forward and un-applied on psi and
-        # lambda in the backward (except each qubit's last block there)
-        nblk = block_ops(plan, kind)
-        flop_step = int(B * (1 << (circ.n - 1)) * nblk * 32 * (2 if kind == 1 else 1))
+        # lambda in the backward (except each qubit's last block there),
+        # over the tiles the kernels run (live_work)
+        flop_step = int(B * (1 << (circ.n - 1)) * units * 32 * (2 if kind == 1 else 1))
         per_launch_flop = flop_step / S
         tfs = per_launch_flop / avg_s / 1e12
-        use_jit = args.jit and args.path == "fused"
         sfx = f"_t{plan_kt}l{plan_klo}" + ("_c128" if prec == "c128" else "")
         name = (("qtm_jit_bwd" if kind == 1 else "qtm_jit_fwd") + sfx) if use_jit else \
             ("k_fused_bwd" if kind == 1 else "k_fused_fwd")

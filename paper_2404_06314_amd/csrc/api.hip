@@ -285,6 +285,7 @@ JitSpec jit_spec(qtm_circuit_t c, int precision, const HostPlan &hp) {
   sp.n_blocks = hp.n_blocks;
   sp.masks = c->desc.masks;
   sp.seed_add = c->desc.has_offdiag();
+  sp.nwg_full = fused_wg_per_sample(sp.n, sp.kt);
   sp.hp = &hp;
   return sp;
 }
@@ -669,6 +670,8 @@ int qtm_plan_json(qtm_circuit_t c, int32_t precision, char *buf, size_t len, siz
     extra += "],\"sweep_off_bwd\":[";
     for (size_t i = 0; i < prog.sweep_off_bwd.size(); ++i)
       extra += (i ? "," : "") + std::to_string(prog.sweep_off_bwd[i]);
+    extra += "],\"excited\":[";
+    for (size_t i = 0; i < prog.excited.size(); ++i) extra += (i ? "," : "") + std::to_string(prog.excited[i]);
     extra += "]}";
     js.pop_back();
     js += extra;

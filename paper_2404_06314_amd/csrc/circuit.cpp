@@ -669,6 +669,15 @@ Program encode_program(const CircuitDesc &c, const Plan &p) {
           touched[o.q0] = touched[o.q1] = 1;
         }
       }
+  uint64_t ex = 0;
+  for (const Sweep &sw : p.sweeps) {
+    for (const Stage &st : sw.stages)
+      for (int oi : st.ops) {
+        const FOp &o = p.ops[oi];
+        if ((o.kind == FK_BLOCK && !o.diagonal) || o.kind == FK_CNOT) ex |= (uint64_t)1 << o.target();
+      }
+    pr.excited.push_back(ex);
+  }
   for (const Sweep &sw : p.sweeps)
     encode_sweep(c, p, sw, false, first_on_wire, pr.code, pr.thr, pr.sweep_off_fwd,
                  pr.max_gslots_per_sweep);

@@ -141,6 +141,12 @@ struct Program {
   std::vector<int32_t> sweep_off_fwd;  // forward order
   std::vector<int32_t> sweep_off_bwd;  // backward order (stages and ops reversed)
   int32_t max_gslots_per_sweep = 0;
+  // Per forward sweep: the qubits excited by its end, i.e. the target of a
+  // non-diagonal block or of a CNOT in it or an earlier sweep.  The state
+  // starts at |0...0>, and diagonal gates and CNOT controls never move
+  // weight onto a set bit of a qubit not yet excited, so at every point of
+  // sweep s the amplitudes with such a bit set are exactly 0.
+  std::vector<uint64_t> excited;
 };
 
 Program encode_program(const CircuitDesc &c, const Plan &p);

@@ -91,17 +91,22 @@ __global__ void __launch_bounds__(256) k_fused_grad_slot(const double *__restric
                                                          const double *__restrict__ coef,
                                                          const int32_t *__restrict__ gs_ptr,
                                                          const int32_t *__restrict__ gs_occ, int n_occ,
-                                                         int n_gslots, int nwg, double *__restrict__ gocc) {
+                                                         int n_gslots, int nwg,
+                                                         const int32_t *__restrict__ gs_rows,
+                                                         double *__restrict__ gocc) {
   __shared__ double sh[4];
   const int gs = blockIdx.x, b = blockIdx.y;
+  // rows of the slot's partials: one per workgroup of its sweep (fewer than
+  // nwg where the specialised sweep runs only the tiles that can be nonzero)
+  const int rows = gs_rows ? gs_rows[gs] : nwg;
   double tx = 0.0, ty = 0.0, tz = 0.0, nr = 0.0;
-  for (int wg = threadIdx.x; wg < nwg; wg += blockDim.x) {
+  for (int wg = threadIdx.x; wg < rows; wg += blockDim.x) {
     const double *p = part + (((int64_t)b * n_gslots + gs) * nwg + wg) * 3;
     tx += p[0];
     ty += p[1];
     tz += p[2];
-    nr += pnorm[(int64_t)b * nwg + wg];
   }
+  for (int wg = threadIdx.x; wg < nwg; wg += blockDim.x) nr += pnorm[(int64_t)b * nwg + wg];
   tx = block_sum(tx, sh);
   ty = block_sum(ty, sh);
   tz = block_sum(tz, sh);
@@ -143,7 +148,7 @@ static hipError_t launch_sweep(K kernel, const JitSweeps *js, int dir, int sw, i
                                size_t lds, hipStream_t s, A &a) {
   if (js) {
     void *args[] = {&a};
-    return hipModuleLaunchKernel(js->k[dir][sw].fn, nwg, B, 1, nt, 1, 1, 0, s, args, nullptr);
+    return hipModuleLaunchKernel(js->k[dir][sw].fn, js->nwg[dir][sw], B, 1, nt, 1, 1, 0, s, args, nullptr);
   }
   hipLaunchKernelGGL(kernel, dim3(nwg, B), dim3(nt), lds, s, a);
   return hipSuccess;
@@ -274,7 +279,8 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
   if (d.n_occ > 0 && p.n_gslots > 0) {
     const int nwg = fused_wg_per_sample(d.n, p.kt);
     k_fused_grad_slot<<<dim3(p.n_gslots, B), nwg >= 256 ? 256 : 64, 0, s>>>(
-        part_grad, part_norm, coef, p.gs_ptr, p.gs_occ, d.n_occ, p.n_gslots, nwg, gocc);
+        part_grad, part_norm, coef, p.gs_ptr, p.gs_occ, d.n_occ, p.n_gslots, nwg,
+        js ? js->gs_rows_dev : nullptr, gocc);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -28,6 +28,7 @@ struct JitSpec {
   int M = 0;          // observables
   int n_blocks = 0;   // fused blocks (matrix table stride per sample)
   bool seed_add = false;  // backward: lam holds a bra term to add in the first sweep
+  int nwg_full = 0;   // row stride of the per-workgroup partial buffers
   std::vector<uint64_t> masks;
   const HostPlan *hp = nullptr;
 };
@@ -39,6 +40,22 @@ struct JitSpec {
 // configurations apart.
 std::string jit_source(const JitSpec &sp, int dir, int sweep);
 std::string jit_kernel_name(const JitSpec &sp, int dir);
+
+// Work of a specialised sweep restricted to the amplitudes that can be
+// nonzero (Program::excited): with D_in / D_out the qubits not excited before
+// / after forward sweep s, the state is 0 wherever a bit of D_out is set
+// throughout the sweep, and the backward needs psi and lambda only where no
+// bit of D_out is set (each gate keeps the bits of D_out, so that part of
+// lambda evolves on its own, and every gradient term pairs it with psi).
+struct SweepLive {
+  uint64_t skip = 0;     // tile-outer qubits: tiles with one of them set are not run
+  uint64_t zin = 0;      // amplitudes with one of these bits set load as 0 (not read)
+  uint64_t nostore = 0;  // amplitudes with one of these bits set are not stored
+  uint64_t din = 0;      // D_in of the forward sweep
+  int64_t tiles = 0;     // tiles run per sample
+  int nwg = 0;           // workgroups launched per sample
+};
+SweepLive sweep_live(const JitSpec &sp, int dir, int sweep);
 
 // Static LDS bytes of that kernel.
 size_t jit_lds_bytes(const JitSpec &sp, int dir, int sweep);
@@ -52,6 +69,9 @@ struct JitKernel {
 
 struct JitSweeps {
   std::vector<JitKernel> k[2];  // [dir][sweep]
+  std::vector<int> nwg[2];      // workgroups per sample of each launch
+  std::vector<int32_t> gs_rows;  // per gradient slot: partial rows its sweep writes
+  int32_t *gs_rows_dev = nullptr;
   std::string name[2];          // kernel name per direction
   int device = -1;
   bool loaded = false;

@@ -1,0 +1,107 @@
+"""GPU parity for circuits whose qubits are excited late.  The state starts
+at |0...0>, so until a qubit meets its first non-diagonal gate (a rotation
+block that is not diagonal, or a CNOT target) every amplitude with its bit
+set is 0; the specialised sweeps skip tiles and loads of such amplitudes and
+keep only what later sweeps read.  These circuits excite qubits one group at
+a time, by rotations and by CNOT targets, put diagonal blocks and CZs on
+qubits before their first rotation, leave a qubit unexcited to the end
+(with X and Y observables on it), and run through the matrix-core kernels
+with one tile per workgroup and with a tile loop, and through the
+complex128 kernels; each against the oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import assert_parity, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def staircase(n: int, layers: int, step: int, idle=(), strings=None) -> W.Circuit:
+    """Layer l rotates qubits below (l + 1) * step (RX input, RY and RZ
+    weights) and applies a CZ ladder over them; the next qubit up gets RZ and
+    a CZ to the active group (diagonal, it stays unexcited) and, every other
+    layer, a CNOT from the top active qubit (which excites it).  Qubits in
+    `idle` only ever get RZ and CZ."""
+    g, nw = [], 0
+    for l in range(layers):
+        top = min(n, (l + 1) * step)
+        act = [q for q in range(top) if q not in idle]
+        for q in act:
+            g.append([W.RX, q, 0, W.SRC_INPUT, q % 4])
+            g.append([W.RY, q, 0, W.SRC_WEIGHT, nw]); nw += 1
+            g.append([W.RZ, q, 0, W.SRC_WEIGHT, nw]); nw += 1
+        for a, b in zip(act, act[1:]):
+            g.append([W.CZ, a, b, 0, 0])
+        if top < n:
+            g.append([W.RZ, top, 0, W.SRC_WEIGHT, nw]); nw += 1
+            g.append([W.CZ, act[-1], top, 0, 0])
+            if l % 2 == 1:
+                g.append([W.CNOT, act[-1], top, 0, 0])
+        for q in idle:
+            g.append([W.RZ, q, 0, W.SRC_WEIGHT, nw]); nw += 1
+            g.append([W.CZ, q, (q + 1) % n, 0, 0])
+    circ = W.Circuit(n=n, gates=np.array(g, np.int32), n_inputs=4, n_weights=nw,
+                     masks=W.z_masks(n, extra=((1 << n) - 1,)))
+    return W.with_observables(circ, strings) if strings else circ
+
+
+def _run(circ, B, seed, precision, tile, klo):
+    import paper_2404_06314_amd as q
+    rng = np.random.default_rng(seed)
+    wl = W.random_workload(rng, circ, B)
+    c = q.Circuit.from_workload(circ)
+    c.set_option(q.QTM_OPT_JIT, 1)
+    c.set_option(q.QTM_OPT_TILE_QUBITS, tile)
+    c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
+    got = run_gpu(circ, wl.inputs, wl.weights, wl.grad_out, precision, qcirc=c)
+    ref = oracle.vjp(wl.circuit, wl.inputs, wl.weights, wl.grad_out)
+    return c, got, ref
+
+
+def _plan_has_dead_sweeps(c, precision):
+    """At least one sweep before the last leaves some qubit unexcited."""
+    p = c.plan(precision)
+    full = (1 << p["n"]) - 1
+    return any(e != full for e in p["excited"][:-1])
+
+
+@pytest.mark.parametrize("n,tile,klo,step,layers", [(16, 10, 4, 3, 6), (16, 11, 3, 4, 5),
+                                                    (18, 12, 5, 5, 4), (14, 10, 4, 2, 8)])
+def test_staircase_matrix_core(n, tile, klo, step, layers):
+    circ = staircase(n, layers, step)
+    c, got, ref = _run(circ, 3, 900 + n, "c64", tile, klo)
+    assert _plan_has_dead_sweeps(c, "c64")
+    assert_parity(got, ref, "c64", f"staircase n{n} kt{tile} klo{klo}")
+
+
+def test_staircase_tile_loop():
+    """2^(n - tile) = 1024 tiles per sample: the kernels loop over tiles."""
+    circ = staircase(20, 4, 6)
+    c, got, ref = _run(circ, 2, 920, "c64", 10, 4)
+    assert _plan_has_dead_sweeps(c, "c64")
+    assert_parity(got, ref, "c64", "staircase n20 kt10 tile loop")
+
+
+@pytest.mark.parametrize("tile,klo", [(6, 3), (8, 4)])
+def test_staircase_complex128(tile, klo):
+    circ = staircase(12, 5, 3)
+    c, got, ref = _run(circ, 3, 930 + tile, "c128", tile, klo)
+    assert _plan_has_dead_sweeps(c, "c128")
+    assert_parity(got, ref, "c128", f"staircase n12 c128 kt{tile}")
+
+
+@pytest.mark.parametrize("precision,tile,klo", [("c64", 10, 4), ("c128", 7, 3)])
+def test_qubit_never_excited(precision, tile, klo):
+    """Qubit 13 gets only RZ and CZ: <X_13> and <Y_13 Z_0> are 0, but the bra
+    terms of those strings are not, and live on amplitudes the sweeps take
+    as 0."""
+    n = 14
+    strings = ([{q: "Z"} for q in range(n)] + [{13: "X"}, {13: "Y", 0: "Z"}, {12: "X", 13: "Y"},
+                                              {11: "Y", 12: "X"}])
+    circ = staircase(n, 5, 3, idle=(13,), strings=strings)
+    c, got, ref = _run(circ, 3, 940, precision, tile, klo)
+    full = (1 << n) - 1
+    assert c.plan(precision)["excited"][-1] == full & ~(1 << 13)
+    assert_parity(got, ref, precision, f"never excited {precision}")

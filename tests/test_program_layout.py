@@ -219,3 +219,45 @@ def test_last_op_per_qubit_is_marked_in_the_backward(seed):
                 first.setdefault(q, t)
         want = sum(1 for t in first.values() if t in W.PARAM_TYPES or t in W.FIXED_TYPES)
         assert counts["fwd"] == want and counts["bwd"] == want, (n, counts, want)
+
+
+DIAGONAL_1Q = (W.RZ, W.Z, W.S, W.SDG, W.T, W.TDG)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_excited_qubits_per_sweep(seed):
+    """Per sweep, the qubits excited by its end: those that were the target
+    of a non-diagonal one-qubit gate or of a CNOT in it or an earlier sweep
+    (a CZ, or a block of diagonal gates, keeps the |1> half of a qubit at 0).
+    The masks are monotone, every qubit the circuit rotates off the diagonal
+    is in the last one, and a qubit given only RZ and CZ never is."""
+    import paper_2404_06314_amd as q
+    rng = np.random.default_rng(700 + seed)
+    n = 9
+    circ = W.random_circuit(rng, n, 60, extended=0.3)
+    keep = [int(t) not in W.CONTROLLED_TYPES and not (int(t) not in DIAGONAL_1Q + (W.CZ,) and
+                                                       (int(a) == 8 or (int(t) == W.CNOT and int(b) == 8)))
+            for t, a, b in circ.gates[:, :3]]
+    circ = W.Circuit(n=n, gates=circ.gates[keep], n_inputs=circ.n_inputs, n_weights=circ.n_weights,
+                     masks=circ.masks)
+    c = q.Circuit.from_workload(circ)
+    c.set_option(q.QTM_OPT_TILE_QUBITS, 5)
+    c.set_option(q.QTM_OPT_LOW_QUBITS, 2)
+    p = c.plan()
+    ex = p["excited"]
+    assert len(ex) == len(p["sweeps"])
+    want, seen = 0, []
+    for sw, got in zip(p["sweeps"], ex):
+        for st in sw["stages"]:
+            for gi in st["gates"]:
+                t, a, b = (int(v) for v in circ.gates[gi, :3])
+                if t == W.CNOT:
+                    want |= 1 << b
+                elif t != W.CZ and t not in DIAGONAL_1Q:
+                    want |= 1 << a
+        seen.append(want)
+    # a block's gates are fused, so its qubit is excited if any of them is
+    # off the diagonal: the per-gate reading above gives the same mask
+    assert ex == seen
+    assert all((x & y) == x for x, y in zip(ex, ex[1:]))
+    assert not (ex[-1] >> 8) & 1
