@@ -105,3 +105,53 @@ def test_qubit_never_excited(precision, tile, klo):
     full = (1 << n) - 1
     assert c.plan(precision)["excited"][-1] == full & ~(1 << 13)
     assert_parity(got, ref, precision, f"never excited {precision}")
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_jacobian_staircase(precision):
+    """The Jacobian (one backward per observable) through the specialised
+    sweeps on a circuit whose qubits are excited late."""
+    import torch
+    import paper_2404_06314_amd as q
+    from gpu_helpers import (FLOOR_G_C64, FLOOR_G_C128, TOL_G_C64, TOL_G_C128, TOL_Z_C64, TOL_Z_C128,
+                             assert_grad_close)
+    circ = staircase(14, 5, 3, strings=[{0: "Z"}, {13: "X"}, {5: "Y", 6: "Z"}, {12: "Z", 13: "Z"}])
+    rng = np.random.default_rng(950)
+    wl = W.random_workload(rng, circ, 2)
+    c = q.Circuit.from_workload(circ)
+    c.set_option(q.QTM_OPT_JIT, 1)
+    c.set_option(q.QTM_OPT_TILE_QUBITS, 10 if precision == "c64" else 7)
+    c.set_option(q.QTM_OPT_LOW_QUBITS, 4 if precision == "c64" else 3)
+    assert _plan_has_dead_sweeps(c, precision)
+    ev, jw, jx = c.jacobian(torch.as_tensor(wl.inputs, device="cuda:0"),
+                            torch.as_tensor(wl.weights, device="cuda:0"), precision)
+    torch.cuda.synchronize()
+    rev, rjw, rjx = oracle.jacobian(circ, wl.inputs, wl.weights)
+    tz, tg, fl = ((TOL_Z_C64, TOL_G_C64, FLOOR_G_C64) if precision == "c64"
+                  else (TOL_Z_C128, TOL_G_C128, FLOOR_G_C128))
+    assert np.max(np.abs(ev.cpu().numpy() - rev)) <= tz
+    jw, jx = jw.cpu().numpy(), jx.cpu().numpy()
+    for b in range(2):
+        for m in range(circ.n_obs):
+            assert_grad_close(jw[b, m], rjw[b, m], tg, f"J_w[{b},{m}]", fl)
+            assert_grad_close(jx[b, m], rjx[b, m], tg, f"J_x[{b},{m}]", fl)
+
+
+def test_no_kept_state_and_recomputed_forward():
+    """Forward without a kept state, then a backward that recomputes the
+    forward itself, through the specialised sweeps."""
+    import torch
+    import paper_2404_06314_amd as q
+    circ = staircase(16, 6, 3)
+    rng = np.random.default_rng(960)
+    wl = W.random_workload(rng, circ, 3)
+    c = q.Circuit.from_workload(circ)
+    c.set_option(q.QTM_OPT_JIT, 1)
+    c.set_option(q.QTM_OPT_TILE_QUBITS, 10)
+    c.set_option(q.QTM_OPT_LOW_QUBITS, 4)
+    x, w, G = (torch.as_tensor(a, device="cuda:0") for a in (wl.inputs, wl.weights, wl.grad_out))
+    ev = c.forward(x, w, "c64", state=None)
+    gw, gx = c.backward(x, w, G, "c64", state=None)
+    torch.cuda.synchronize()
+    ref = oracle.vjp(wl.circuit, wl.inputs, wl.weights, wl.grad_out)
+    assert_parity((ev.cpu().numpy(), gw.cpu().numpy(), gx.cpu().numpy()), ref, "c64", "no kept state")
