@@ -142,3 +142,26 @@ def test_max_qubits_n30_closed_form(precision):
         gwb, gx[b] = C.bloch_grad(prod, x[b], w, G[b])
         gw += gwb
     assert_parity(got, (ev, gw, gx), precision, f"n30 {precision}")
+
+
+@pytest.mark.parametrize("precision,tile,klo", [("c64", 12, 4), ("c128", 11, 4)])
+def test_c5_specialised_tile_loop(precision, tile, klo):
+    """n=26, 10 layers, CNOT ring, 2 samples, through the specialised kernels
+    in the configurations the benchmark uses: 2^14 or 2^15 tiles per sample,
+    so each workgroup loops over tiles and loads the next one during the
+    current one's stages."""
+    import paper_2404_06314_amd as q
+    wl = W.config_workload("c5", batch=2)
+    ref = fixture("oracle_c5_b2.npz")
+    c = q.Circuit.from_workload(wl.circuit)
+    c.set_option(q.QTM_OPT_JIT, 1)
+    c.set_option(q.QTM_OPT_TILE_QUBITS, tile)
+    c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
+    got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, precision, qcirc=c)
+    assert_parity(got, ref, precision, f"c5 specialised {precision} kt{tile}")
+    if precision == "c64":
+        # the complex128 kernels of two sweeps spill a few hundred bytes at
+        # this size (double-precision amplitudes take twice the registers)
+        for direction in (0, 1):
+            for s in range(len(c.plan(precision)["sweeps"])):
+                assert c.jit_info(precision, direction, s)[1] <= 64
