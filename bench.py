@@ -45,7 +45,10 @@ def kernel_digest(kernel: str) -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[fam]:
         with open(os.path.join(ROOT, "paper_2404_06314_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+            # whole-line comments do not change a kernel
+            for line in fh:
+                if not line.lstrip().startswith(b"//"):
+                    h.update(line)
     return h.hexdigest()[:16]
 
 
