@@ -7,7 +7,7 @@ import math
 
 import torch
 
-from . import Circuit, precision_code
+from . import QTM_OPT_JIT, Circuit, precision_code
 
 
 class QtmFunction(torch.autograd.Function):
@@ -50,13 +50,24 @@ class QuantumLayer(torch.nn.Module):
     hyperparameters).  Each entry is (name, size, init) with init one of
     "uniform" (U[0, 2 pi)), "ones", "zeros", a number (constant) or a tensor
     of that size; the sizes must add up to the circuit's weight count.
+
+    ``specialised`` runs the sweep kernels generated and compiled for this
+    circuit (QTM_OPT_JIT): a one-off compile of a few seconds on the first
+    call, then 2-4x faster steps from about 14 qubits on.  The default
+    (None) turns them on from SPECIALISED_FROM_QUBITS qubits.
     """
 
+    SPECIALISED_FROM_QUBITS = 14
+
     def __init__(self, circuit: Circuit, precision="c64", weights=None, device="cuda",
-                 param_sets=None):
+                 param_sets=None, specialised=None):
         super().__init__()
         self.circuit = circuit
         self.precision = precision
+        if specialised is None:
+            specialised = circuit.n >= self.SPECIALISED_FROM_QUBITS
+        if specialised:
+            circuit.set_option(QTM_OPT_JIT, 1)
         if param_sets is None:
             if weights is None:
                 weights = torch.rand(circuit.n_weights, dtype=torch.float64) * (2 * math.pi)
@@ -73,7 +84,7 @@ class QuantumLayer(torch.nn.Module):
 
     @classmethod
     def eq7(cls, n: int, depth: int, entangler="chain", observables=None, precision="c64",
-            device="cuda", theta_init="uniform", lambda_init="ones"):
+            device="cuda", theta_init="uniform", lambda_init="ones", specialised=None):
         """The paper's benchmark ansatz (Eq. (7)) with parameter sets
         ``theta`` and ``lambda``; observables: Z masks (default Z on every
         qubit)."""
@@ -82,7 +93,8 @@ class QuantumLayer(torch.nn.Module):
         masks = z_observables(n) if observables is None else observables
         circ = Circuit(n, gates, n, n_th + n_lam, masks)
         return cls(circ, precision, device=device,
-                   param_sets=[("theta", n_th, theta_init), ("lambda", n_lam, lambda_init)])
+                   param_sets=[("theta", n_th, theta_init), ("lambda", n_lam, lambda_init)],
+                   specialised=specialised)
 
     @property
     def weights_vector(self):
@@ -137,12 +149,12 @@ class HybridModule(torch.nn.Module):
 
     def __init__(self, input_size: int, output_size: int, n_qubits: int, depth: int,
                  entangler="chain", precision="c64", device="cuda", theta_init="uniform",
-                 lambda_init="ones"):
+                 lambda_init="ones", specialised=None):
         super().__init__()
         self.pre = torch.nn.Linear(input_size, n_qubits, dtype=torch.float64, device=device)
         self.quantum = QuantumLayer.eq7(n_qubits, depth, entangler=entangler, precision=precision,
                                         device=device, theta_init=theta_init,
-                                        lambda_init=lambda_init)
+                                        lambda_init=lambda_init, specialised=specialised)
         self.post = torch.nn.Linear(n_qubits, output_size, dtype=torch.float64, device=device)
 
     def forward(self, x):

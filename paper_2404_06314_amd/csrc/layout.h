@@ -65,6 +65,10 @@ enum OpCode : int32_t { OP_U1 = 1, OP_CNOT = 2, OP_DIAG = 3, OP_U1_LAST = 4, OP_
 //              backward acts on other qubits and commutes with it, so
 //              keeping the block applied on both psi and lambda changes no
 //              later <lambda|P|psi>, and nothing reads the final states.
+//              The specialised backward sweeps un-apply it anyway in every
+//              sweep but the last one they run: the next sweep takes the
+//              qubit's |1> half as 0 (not excited yet), which holds only
+//              once the block is undone.
 //     OP_U1_FIRST (forward only): as OP_U1 for a block that is the first op
 //              on its qubit: every amplitude with that qubit's bit set is
 //              still 0, so only the matrix columns of the |0> inputs are
