@@ -86,32 +86,29 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
 // matrix components summed over the workgroup partials and the norm summed
 // over the first backward sweep's partials (fixed order), then
 // g[b][k] = (px TX + py TY + pz TZ) / norm for every rotation k of the slot.
-__global__ void __launch_bounds__(256) k_fused_grad_slot(const double *__restrict__ part,
-                                                         const double *__restrict__ pnorm,
-                                                         const double *__restrict__ coef,
-                                                         const int32_t *__restrict__ gs_ptr,
-                                                         const int32_t *__restrict__ gs_occ, int n_occ,
-                                                         int n_gslots, int nwg,
-                                                         const int32_t *__restrict__ gs_rows,
-                                                         double *__restrict__ gocc) {
-  __shared__ double sh[4];
-  const int gs = blockIdx.x, b = blockIdx.y;
+__global__ void __launch_bounds__(64) k_fused_grad_slot(const double *__restrict__ part,
+                                                        const double *__restrict__ pnorm,
+                                                        const double *__restrict__ coef,
+                                                        const int32_t *__restrict__ gs_ptr,
+                                                        const int32_t *__restrict__ gs_occ, int n_occ,
+                                                        int n_gslots, int nwg,
+                                                        const int32_t *__restrict__ gs_rows,
+                                                        double *__restrict__ gocc) {
+  // one wave per (slot, sample)
+  const int gs = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
   // rows of the slot's partials: one per workgroup of its sweep (fewer than
   // nwg where the specialised sweep runs only the tiles that can be nonzero)
   const int rows = gs_rows ? gs_rows[gs] : nwg;
-  double tx = 0.0, ty = 0.0, tz = 0.0, nr = 0.0;
-  for (int wg = threadIdx.x; wg < rows; wg += blockDim.x) {
-    const double *p = part + (((int64_t)b * n_gslots + gs) * nwg + wg) * 3;
-    tx += p[0];
-    ty += p[1];
-    tz += p[2];
-  }
-  for (int wg = threadIdx.x; wg < nwg; wg += blockDim.x) nr += pnorm[(int64_t)b * nwg + wg];
-  tx = block_sum(tx, sh);
-  ty = block_sum(ty, sh);
-  tz = block_sum(tz, sh);
-  nr = block_sum(nr, sh);
-  for (int e = gs_ptr[gs] + threadIdx.x; e < gs_ptr[gs + 1]; e += blockDim.x) {
+  // the slot's rows are contiguous (3 components each): consecutive lanes
+  // read consecutive doubles; element e = t + 64 k is component e % 3
+  const double *p = part + ((int64_t)b * n_gslots + gs) * nwg * 3;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int e = t, c = t % 3; e < rows * 3; e += 64, c = c == 2 ? 0 : c + 1) acc[c] += p[e];
+  double nr = 0.0;
+  for (int wg = t; wg < nwg; wg += 64) nr += pnorm[(int64_t)b * nwg + wg];
+  const double tx = wave_sum_w<64>(acc[0]), ty = wave_sum_w<64>(acc[1]), tz = wave_sum_w<64>(acc[2]);
+  nr = wave_sum_w<64>(nr);
+  for (int e = gs_ptr[gs] + t; e < gs_ptr[gs + 1]; e += 64) {
     const int k = gs_occ[e];
     const double *cf = coef + ((int64_t)b * n_occ + k) * 3;
     gocc[(int64_t)b * n_occ + k] = (cf[0] * tx + cf[1] * ty + cf[2] * tz) / nr;
@@ -278,7 +275,7 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
   if (e != hipSuccess) return e;
   if (d.n_occ > 0 && p.n_gslots > 0) {
     const int nwg = fused_wg_per_sample(d.n, p.kt);
-    k_fused_grad_slot<<<dim3(p.n_gslots, B), nwg >= 256 ? 256 : 64, 0, s>>>(
+    k_fused_grad_slot<<<dim3(p.n_gslots, B), 64, 0, s>>>(
         part_grad, part_norm, coef, p.gs_ptr, p.gs_occ, d.n_occ, p.n_gslots, nwg,
         js ? js->gs_rows_dev : nullptr, gocc);
     e = hipGetLastError();
