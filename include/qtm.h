@@ -154,8 +154,9 @@ int qtm_forward(qtm_circuit_t c, int32_t batch, int32_t precision, const double 
 /* Adjoint VJP (Sec. II-A, reverse gradient).
  *   grad_expvals  dev [batch][n_obs] float64: G = dL/d<O>
  *   state         dev buffer written by qtm_forward with the same circuit, batch,
- *                 precision and angles; it is un-computed in place (on return it
- *                 holds about |0...0>), so one forward serves one backward.
+ *                 precision and angles; the backward consumes it (it works in
+ *                 place and its contents on return are unspecified), so one
+ *                 forward serves one backward.
  *                 NULL: the forward is recomputed into the workspace.
  *   grad_weights  dev [n_weights] float64, overwritten (summed over the batch)
  *   grad_inputs   dev [batch][n_inputs] float64, overwritten; may be NULL. */
