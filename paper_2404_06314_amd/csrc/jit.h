@@ -9,7 +9,9 @@
 // same device helpers, instantiated for the op's register bit), compiles it
 // with hiprtc and loads it as a module: straight-line code per stage, no op
 // dispatch, and the compiler is free to keep amplitudes in whatever
-// registers the matrix-core instructions leave them in.
+// registers the matrix-core instructions leave them in.  Knowing the plan
+// also lets each sweep skip the tiles and amplitudes that are still 0
+// (SweepLive below).
 #pragma once
 
 #include <hip/hip_runtime.h>
