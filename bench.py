@@ -192,7 +192,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batch would be "
-              "split across GPUs with one all-reduce of dL/dweights, which this build does not do",
+              "split across GPUs with one all-reduce of dL/dweights, which is not implemented",
               file=sys.stderr)
         sys.exit(2)
 
