@@ -261,3 +261,52 @@ def test_excited_qubits_per_sweep(seed):
     assert ex == seen
     assert all((x & y) == x for x, y in zip(ex, ex[1:]))
     assert not (ex[-1] >> 8) & 1
+
+
+@pytest.mark.parametrize("name,tile,klo", [("c3", 11, 4), ("c3", 12, 5), ("c5", 12, 4)])
+def test_bench_work_model(name, tile, klo):
+    """bench.py's count of the work the sweeps do: the compiled kernels read
+    and write every state once per sweep (the first forward sweep only
+    writes, the last backward one only reads); the specialised kernels never
+    move more and apply no more blocks, except the last block of each qubit
+    they un-apply in sweeps after the first."""
+    import bench
+    import paper_2404_06314_amd as q
+    wl = W.config_workload(name, batch=1)
+    c = q.Circuit.from_workload(wl.circuit)
+    c.set_option(q.QTM_OPT_TILE_QUBITS, tile)
+    c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
+    p = c.plan()
+    S, n = len(p["sweeps"]), wl.circuit.n
+    for kind in (0, 1):
+        passes, units = bench.live_work(p, n, kind, False)
+        assert passes == (1 + 2 * (S - 1) if kind == 0 else 3 + 4 * (S - 2) + 2)
+        assert units == bench.block_ops(p, kind)
+        lp, lu = bench.live_work(p, n, kind, True)
+        assert 0 < lp <= passes
+        extra = sum(bench._sweep_block_ops(p, kind, True)) - bench.block_ops(p, kind)
+        assert 0 < lu <= units + extra
+
+
+def test_bench_work_model_n20_tile11():
+    """The n = 20 plan at tile 11 / 4 low qubits: qubits 11-19 are unexcited
+    after sweep 0, 16-19 after sweeps 1 and 2, none after sweep 3.  So the
+    forward writes 1/512, reads 1/512 and writes 1/16, reads and writes 1/16,
+    reads 1/16 and writes all, reads and writes all: 3 + 4/16 + 2/512 state
+    passes.  The backward reads psi in full and writes psi and lambda
+    (sweep 4: 3), reads both in full and writes 2/16 (sweep 3), reads and
+    writes 2/16 (sweep 2), reads 2/16 and writes 2/512 (sweep 1), reads
+    2/512 (sweep 0): 5 + 8/16 + 4/512."""
+    import bench
+    import paper_2404_06314_amd as q
+    wl = W.config_workload("c3", batch=1)
+    c = q.Circuit.from_workload(wl.circuit)
+    c.set_option(q.QTM_OPT_TILE_QUBITS, 11)
+    c.set_option(q.QTM_OPT_LOW_QUBITS, 4)
+    p = c.plan()
+    full = (1 << 20) - 1
+    assert p["excited"] == [(1 << 11) - 1, (1 << 16) - 1, (1 << 16) - 1, full, full]
+    fwd = (1 / 512) + (1 / 512 + 1 / 16) + (1 / 16 + 1 / 16) + (1 / 16 + 1) + (1 + 1)
+    bwd = (1 + 2) + (2 + 2 / 16) + (2 / 16 + 2 / 16) + (2 / 16 + 2 / 512) + 2 / 512
+    assert bench.live_work(p, 20, 0, True)[0] == pytest.approx(fwd)
+    assert bench.live_work(p, 20, 1, True)[0] == pytest.approx(bwd)
