@@ -264,9 +264,12 @@ int qtm_jit_info(qtm_circuit_t c, int32_t precision, int32_t dir, int32_t sweep,
                  int32_t *scratch);
 
 /* Diagnostics: JSON description of the fused-path plan (sweeps, tile qubits,
- * stages and the gate indices each stage runs) for the given precision.
- * Writes at most len bytes (NUL-terminated) into buf and the full size into
- * *needed; buf may be NULL to query the size. */
+ * stages and the gate indices each stage runs) for the given precision, the
+ * encoded device program, and per sweep the qubits excited by its end
+ * ("excited": a bit mask; the specialised kernels take amplitudes with a
+ * bit of an unexcited qubit as 0).  Writes at most len bytes (NUL-
+ * terminated) into buf and the full size into *needed; buf may be NULL to
+ * query the size. */
 int qtm_plan_json(qtm_circuit_t c, int32_t precision, char *buf, size_t len, size_t *needed);
 
 /* Message for the calling thread's last non-OK return ("" if none). */

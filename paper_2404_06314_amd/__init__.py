@@ -115,6 +115,9 @@ class Circuit:
         return int(out.value)
 
     def plan(self, precision=QTM_C64) -> dict:
+        """The fused-path plan (qtm_plan_json): sweeps with their tile qubits
+        and stages, the encoded program (code, thr, sweep offsets) and, per
+        sweep, the mask of qubits excited by its end (excited)."""
         lib = _lib.load()
         need = ctypes.c_size_t()
         _lib.check(lib.qtm_plan_json(self._h, precision_code(precision), None, 0, ctypes.byref(need)))
