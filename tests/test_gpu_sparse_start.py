@@ -155,3 +155,33 @@ def test_no_kept_state_and_recomputed_forward():
     torch.cuda.synchronize()
     ref = oracle.vjp(wl.circuit, wl.inputs, wl.weights, wl.grad_out)
     assert_parity((ev.cpu().numpy(), gw.cpu().numpy(), gx.cpu().numpy()), ref, "c64", "no kept state")
+
+
+def test_degenerate_circuits_specialised():
+    """Extremes of the zero-amplitude logic through the specialised kernels
+    (14 qubits, tile 10): an empty circuit (only |0...0> is ever nonzero), a
+    circuit of diagonal gates only (no qubit is ever excited; X and Y
+    observables on top), and qubits excited only by fixed gates (H, X, SX)."""
+    n = 14
+    empty = W.Circuit(n=n, gates=np.zeros((0, 5), np.int32), n_inputs=0, n_weights=0,
+                      masks=W.z_masks(n, ((1 << n) - 1,)))
+    diag = []
+    for q_ in range(n):
+        diag.append([W.RZ, q_, 0, W.SRC_WEIGHT, q_])
+        diag.append([W.S if q_ % 2 else W.T, q_, 0, 0, 0])
+    diag += [[W.CZ, q_, q_ + 1, 0, 0] for q_ in range(n - 1)]
+    diag_c = W.with_observables(
+        W.Circuit(n=n, gates=np.array(diag, np.int32), n_inputs=0, n_weights=n, masks=W.z_masks(n)),
+        [{q_: "Z"} for q_ in range(n)] + [{3: "X"}, {5: "Y", 6: "X"}, {0: "Z", 13: "Z"}])
+    fixed = []
+    for q_ in range(n):
+        fixed.append([(W.H, W.X, W.SX)[q_ % 3], q_, 0, 0, 0])
+        fixed.append([W.RZ, q_, 0, W.SRC_WEIGHT, q_])
+        fixed.append([W.RY, q_, 0, W.SRC_INPUT, q_ % 2])
+    fixed += [[W.CNOT, q_, (q_ + 3) % n, 0, 0] for q_ in range(n)]
+    fixed_c = W.Circuit(n=n, gates=np.array(fixed, np.int32), n_inputs=2, n_weights=n, masks=W.z_masks(n))
+    for name, circ in (("empty", empty), ("diagonal", diag_c), ("fixed", fixed_c)):
+        c, got, ref = _run(circ, 2, 980, "c64", 10, 4)
+        assert_parity(got, ref, "c64", f"degenerate {name}")
+        if name == "empty":
+            np.testing.assert_allclose(got[0], 1.0, atol=1e-6)
