@@ -76,6 +76,7 @@ int upload(T **dst, const std::vector<T> &src, std::vector<void *> &owned) {
 struct StateTag {
   uint64_t circuit_id;
   int32_t batch, precision;
+  uint64_t prep_gen;  // the circuit's prep_gen right after that forward
 };
 std::mutex g_reg_mu;
 std::unordered_map<void *, StateTag> g_registry;
@@ -140,6 +141,12 @@ struct qtm_circuit_s {
   std::map<std::tuple<int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision)
   DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm, part_pauli;
   DevBuf jac_state, jac_G, jac_gw, jac_out;
+  // What `mats` and `coef` hold: counted up by every forward (and by a
+  // backward that prepares its own), with the fused plan, batch and
+  // precision they were computed for (plan NULL: not by the fused path).
+  uint64_t prep_gen = 0;
+  const DevPlan *prep_plan = nullptr;
+  int32_t prep_B = 0, prep_prec = -1;
 
   ~qtm_circuit_s() {
     for (void *p : owned) (void)hipFree(p);
@@ -366,15 +373,24 @@ int forward_sweeps(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, co
     if ((rc = get_plan(c, prec, &p))) return rc;
     if ((rc = c->mats.ensure((size_t)B * std::max(p->n_blocks, 1) * sizeof(M2<double>)))) return rc;
     if ((rc = c->part_obs.ensure(fused_part_obs_doubles(d, *p, B) * sizeof(double)))) return rc;
+    // the derivative coefficients too, so that the backward can reuse both
+    if ((rc = c->coef.ensure((size_t)B * std::max(d.n_occ, 1) * 3 * sizeof(double)))) return rc;
     const JitSweeps *js = nullptr;
     if (c->jit && (rc = get_jit(c, prec, true, &js))) return rc;
+    c->prep_gen++;
+    c->prep_plan = nullptr;
     hipError_t e =
         prec == QTM_C64
-            ? fused_forward<float>(d, *p, B, x, w, c->mats.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get(), js)
-            : fused_forward<double>(d, *p, B, x, w, c->mats.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get(), js);
+            ? fused_forward<float>(d, *p, B, x, w, c->mats.p, (double *)c->coef.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get(), js)
+            : fused_forward<double>(d, *p, B, x, w, c->mats.p, (double *)c->coef.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get(), js);
     if (e != hipSuccess) return hip_fail(e, "fused forward launch");
+    c->prep_plan = p;
+    c->prep_B = B;
+    c->prep_prec = prec;
     return QTM_OK;
   }
+  c->prep_gen++;
+  c->prep_plan = nullptr;
   if ((rc = c->cs.ensure((size_t)B * std::max(d.n_occ, 1) * sizeof(double2)))) return rc;
   if ((rc = c->part.ensure(plain_part_doubles(d, B) * sizeof(double)))) return rc;
   hipError_t e = launch_half_angles(d, B, x, w, (double2 *)c->cs.p, s);
@@ -389,9 +405,12 @@ int forward_sweeps(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, co
 
 // Adjoint backward from the final states in psi (consumed).  Leaves the
 // per-sample, per-rotation derivatives in c->gocc.
+// prepped: no forward has run on c since the one that filled psi, so mats
+// and coef may still hold its matrices (checked against the plan, batch and
+// precision here).
 int run_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
                  const double *weights, const double *grad_expvals, void *psi, double *grad_weights,
-                 double *grad_inputs, hipStream_t s) {
+                 double *grad_inputs, bool prepped, hipStream_t s) {
   const DevCircuit &d = c->dev;
   const size_t sbytes = ((size_t)batch << c->desc.n) * elem_bytes(precision);
   int rc;
@@ -409,13 +428,21 @@ int run_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
     if (c->jit && (rc = get_jit(c, precision, true, &js))) return rc;
     if ((rc = c->part_norm.ensure((size_t)batch * fused_wg_per_sample(d.n, p->kt) * sizeof(double))))
       return rc;
+    const bool reuse = prepped && c->prep_plan == p && c->prep_B == batch && c->prep_prec == precision;
+    if (!reuse) {
+      // this backward prepares mats and coef itself
+      c->prep_gen++;
+      c->prep_plan = p;
+      c->prep_B = batch;
+      c->prep_prec = precision;
+    }
     e = precision == QTM_C64
             ? fused_backward<float>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
-                                    (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
+                                    (double *)c->coef.p, reuse, psi, c->lam.p, (double *)c->part_grad.p,
                                     (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
                                     grad_inputs, s, c->timer.get(), js)
             : fused_backward<double>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
-                                     (double *)c->coef.p, psi, c->lam.p, (double *)c->part_grad.p,
+                                     (double *)c->coef.p, reuse, psi, c->lam.p, (double *)c->part_grad.p,
                                      (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
                                      grad_inputs, s, c->timer.get(), js);
   } else {
@@ -540,7 +567,7 @@ int qtm_forward(qtm_circuit_t c, int32_t batch, int32_t precision, const double 
   if (rc) return rc;
   if (state) {
     std::lock_guard<std::mutex> g(g_reg_mu);
-    g_registry[state] = StateTag{c->id, batch, precision};
+    g_registry[state] = StateTag{c->id, batch, precision, c->prep_gen};
   }
   return QTM_OK;
 }
@@ -559,12 +586,14 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
   const DevCircuit &d = c->dev;
   const size_t sbytes = ((size_t)batch << c->desc.n) * elem_bytes(precision);
   void *psi = state;
+  bool prepped = true;
   if (state) {
     std::lock_guard<std::mutex> g(g_reg_mu);
     auto it = g_registry.find(state);
     if (it == g_registry.end() || it->second.circuit_id != c->id || it->second.batch != batch ||
         it->second.precision != precision)
       return fail(QTM_ERR_STATE, "state buffer was not filled by qtm_forward for this circuit, batch and precision");
+    prepped = it->second.prep_gen == c->prep_gen;
     g_registry.erase(it);
   } else {
     // recompute the forward into the workspace (expectation values go to a scratch area)
@@ -575,7 +604,8 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
     if ((rc = do_forward(c, batch, precision, inputs, weights, (double *)c->gocc.p, psi, true, s)))
       return rc;
   }
-  return run_backward(c, batch, precision, inputs, weights, grad_expvals, psi, grad_weights, grad_inputs, s);
+  return run_backward(c, batch, precision, inputs, weights, grad_expvals, psi, grad_weights, grad_inputs,
+                      prepped, s);
 }
 
 int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
@@ -606,7 +636,7 @@ int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double
       return hip_fail(e, "jacobian state copy");
     if ((e = launch_onehot((double *)c->jac_G.p, batch, M, m, s))) return hip_fail(e, "jacobian seed");
     if ((rc = run_backward(c, batch, precision, inputs, weights, (double *)c->jac_G.p, c->state_ws.p,
-                           (double *)c->jac_gw.p, nullptr, s)))
+                           (double *)c->jac_gw.p, nullptr, true, s)))
       return rc;
     if ((e = launch_scatter_jac(d, batch, (double *)c->gocc.p, inputs, weights, m, jac_weights,
                                   jac_inputs, s)))

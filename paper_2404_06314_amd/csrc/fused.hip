@@ -249,9 +249,10 @@ static hipError_t prep(const DevCircuit &d, const DevPlan &p, int B, const doubl
 
 template <typename R>
 hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
-                         const double *w, void *mats, void *state, double *part_obs, double *out,
-                         bool store_final, hipStream_t s, SweepTimer *tm, const JitSweeps *js) {
-  hipError_t e = prep<R>(d, p, B, x, w, mats, nullptr, s);
+                         const double *w, void *mats, double *coef, void *state, double *part_obs,
+                         double *out, bool store_final, hipStream_t s, SweepTimer *tm,
+                         const JitSweeps *js) {
+  hipError_t e = prep<R>(d, p, B, x, w, mats, coef, s);
   if (e != hipSuccess) return e;
 #define FWD_CALL(K) e = run_fwd<R, K>(d, p, B, mats, state, part_obs, store_final, s, tm, js)
   QTM_KT_DISPATCH(p.kt, FWD_CALL)
@@ -262,10 +263,13 @@ hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const dou
 
 template <typename R>
 hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
-                          const double *w, const double *G, void *mats, double *coef, void *state,
-                          void *lam, double *part_grad, double *part_norm, double *gocc, double *gw,
-                          double *gx, hipStream_t s, SweepTimer *tm, const JitSweeps *js) {
-  hipError_t e = prep<R>(d, p, B, x, w, mats, coef, s);
+                          const double *w, const double *G, void *mats, double *coef, bool prepped,
+                          void *state, void *lam, double *part_grad, double *part_norm,
+                          double *gocc, double *gw, double *gx, hipStream_t s, SweepTimer *tm,
+                          const JitSweeps *js) {
+  // prepped: mats and coef still hold what the forward computed from the
+  // same angles for this plan and batch
+  hipError_t e = prepped ? hipSuccess : prep<R>(d, p, B, x, w, mats, coef, s);
   if (e != hipSuccess) return e;
   // bra term of observables with X or Y factors, added in the first sweep
   if ((e = launch_pauli_seed<R>(d, B, state, lam, G, false, s)) != hipSuccess) return e;
@@ -285,18 +289,18 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
 }
 
 template hipError_t fused_forward<float>(const DevCircuit &, const DevPlan &, int, const double *,
-                                         const double *, void *, void *, double *, double *, bool,
-                                         hipStream_t, SweepTimer *, const JitSweeps *);
+                                         const double *, void *, double *, void *, double *, double *,
+                                         bool, hipStream_t, SweepTimer *, const JitSweeps *);
 template hipError_t fused_forward<double>(const DevCircuit &, const DevPlan &, int, const double *,
-                                          const double *, void *, void *, double *, double *, bool,
-                                          hipStream_t, SweepTimer *, const JitSweeps *);
+                                          const double *, void *, double *, void *, double *, double *,
+                                          bool, hipStream_t, SweepTimer *, const JitSweeps *);
 template hipError_t fused_backward<float>(const DevCircuit &, const DevPlan &, int, const double *,
-                                          const double *, const double *, void *, double *, void *,
-                                          void *, double *, double *, double *, double *, double *,
-                                          hipStream_t, SweepTimer *, const JitSweeps *);
+                                          const double *, const double *, void *, double *, bool,
+                                          void *, void *, double *, double *, double *, double *,
+                                          double *, hipStream_t, SweepTimer *, const JitSweeps *);
 template hipError_t fused_backward<double>(const DevCircuit &, const DevPlan &, int, const double *,
-                                           const double *, const double *, void *, double *, void *,
-                                           void *, double *, double *, double *, double *, double *,
-                                           hipStream_t, SweepTimer *, const JitSweeps *);
+                                           const double *, const double *, void *, double *, bool,
+                                           void *, void *, double *, double *, double *, double *,
+                                           double *, hipStream_t, SweepTimer *, const JitSweeps *);
 
 }  // namespace qtm

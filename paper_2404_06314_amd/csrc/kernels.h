@@ -91,14 +91,19 @@ size_t fused_part_obs_doubles(const DevCircuit &d, const DevPlan &p, int B);
 size_t fused_part_grad_doubles(const DevCircuit &d, const DevPlan &p, int B);
 
 // js: kernels specialised for this plan (nullptr: the compiled sweep kernels).
+// The forward's prep also writes the derivative coefficients when coef is
+// not NULL; the backward skips its prep when `prepped` (mats and coef hold
+// what a forward computed from the same angles, plan and batch).
 template <typename R>
 hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
-                         const double *w, void *mats, void *state, double *part_obs, double *out,
-                         bool store_final, hipStream_t s, SweepTimer *tm, const JitSweeps *js);
+                         const double *w, void *mats, double *coef, void *state, double *part_obs,
+                         double *out, bool store_final, hipStream_t s, SweepTimer *tm,
+                         const JitSweeps *js);
 template <typename R>
 hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
-                          const double *w, const double *G, void *mats, double *coef, void *state,
-                          void *lam, double *part_grad, double *part_norm, double *gocc, double *gw,
-                          double *gx, hipStream_t s, SweepTimer *tm, const JitSweeps *js);
+                          const double *w, const double *G, void *mats, double *coef, bool prepped,
+                          void *state, void *lam, double *part_grad, double *part_norm,
+                          double *gocc, double *gw, double *gx, hipStream_t s, SweepTimer *tm,
+                          const JitSweeps *js);
 
 }  // namespace qtm
