@@ -201,3 +201,15 @@ def test_fixed_gates_fuse_into_blocks_and_controlled_rotations_stay_per_gate(qtm
     with pytest.raises(qtm.QtmError) as ei:
         c.plan("c64")
     assert ei.value.code == -2 and "per-gate" in str(ei.value)
+
+
+def test_missing_library_raises_instead_of_falling_back(qtm, monkeypatch, tmp_path):
+    # No CPU path exists behind the binding: without the shared library the
+    # loader raises, and so does every compute entry point that needs it.
+    monkeypatch.setattr(qtm._lib, "_lib", None)
+    monkeypatch.setattr(qtm._lib, "LIB_PATH", tmp_path / "libqtm.so")
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        qtm._lib.load()
+    wl = W.config_workload("c1")
+    with pytest.raises(ImportError):
+        qtm.Circuit.from_workload(wl.circuit)
