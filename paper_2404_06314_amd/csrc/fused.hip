@@ -153,8 +153,8 @@ static hipError_t launch_sweep(K kernel, const JitSweeps *js, int dir, int sw, i
 
 template <typename R, int KT>
 static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *mats, void *state,
-                          double *part_obs, bool store_final, hipStream_t s, SweepTimer *tm,
-                          const JitSweeps *js) {
+                          double *part_obs, double *out, bool store_final, hipStream_t s,
+                          SweepTimer *tm, const JitSweeps *js) {
   const int nwg = fused_wg_per_sample(d.n, KT);
   const size_t lds = fwd_lds<R, KT>(d.n_obs);
   hipError_t e = allow_lds(k_fused_fwd<R, KT>, lds);
@@ -176,6 +176,7 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *ma
     a.M = d.n_obs;
     a.obs_sgn = p.obs_sgn_f;
     a.part_obs = part_obs;
+    a.out = out;
     if (tm) tm->before(0, s);
     e = launch_sweep(k_fused_fwd<R, KT>, js, 0, sw, nwg, B, 1 << (KT - kRegBits), lds, s, a);
     if (tm) tm->after(0, s);
@@ -254,10 +255,12 @@ hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const dou
                          const JitSweeps *js) {
   hipError_t e = prep<R>(d, p, B, x, w, mats, coef, s);
   if (e != hipSuccess) return e;
-#define FWD_CALL(K) e = run_fwd<R, K>(d, p, B, mats, state, part_obs, store_final, s, tm, js)
+#define FWD_CALL(K) e = run_fwd<R, K>(d, p, B, mats, state, part_obs, out, store_final, s, tm, js)
   QTM_KT_DISPATCH(p.kt, FWD_CALL)
 #undef FWD_CALL
   if (e != hipSuccess) return e;
+  // a specialised last sweep over single-tile samples has written out
+  if (js && js->loaded && js->direct_obs) return hipSuccess;
   return launch_obs_final(part_obs, B, fused_wg_per_sample(d.n, p.kt), d.n_obs, out, true, s);
 }
 

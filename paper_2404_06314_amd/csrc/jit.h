@@ -74,6 +74,7 @@ struct JitSweeps {
   std::vector<int> nwg[2];      // workgroups per sample of each launch
   std::vector<int32_t> gs_rows;  // per gradient slot: partial rows its sweep writes
   int32_t *gs_rows_dev = nullptr;
+  bool direct_obs = false;      // the last forward sweep writes <Z_m> itself
   std::string name[2];          // kernel name per direction
   int device = -1;
   bool loaded = false;

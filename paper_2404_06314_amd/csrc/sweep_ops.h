@@ -521,6 +521,8 @@ struct FwdArgs {
   int M;
   const float *obs_sgn;  // [(M+1)][16]
   double *part_obs;      // [B][gridDim.x][M+1]
+  double *out;           // [B][M] <Z_m>, written directly by a specialised last
+                         // sweep when one tile holds a whole sample
 };
 
 

@@ -49,6 +49,22 @@ def test_multi_sweep_layered(precision, n, L, ent, tile, klo):
 
 
 @pytest.mark.parametrize("precision", ["c64", "c128"])
+@pytest.mark.parametrize("n,L,ent,B", [(5, 3, "ring", 7), (6, 2, "ladder", 3), (12, 2, "ring", 5)])
+def test_single_tile_samples_write_expectations_directly(precision, n, L, ent, B):
+    # tile = n: one workgroup holds a whole sample, and the last forward sweep
+    # divides by the norm itself instead of leaving partial rows (at n = 5 a
+    # workgroup has 2 threads for 9 observables, so each thread takes several)
+    if precision == "c128" and n > 10:
+        pytest.skip("complex128 tiles default to 11 qubits; a 12-qubit complex128 tile is not a tested configuration")
+    rng = np.random.default_rng(40 + n)
+    masks = ((1 << n) - 1, 0b101, 0b11 << (n - 2), 1 << (n - 1))
+    circ = W.layered_circuit(n, L, ent, extra_masks=masks)
+    wl = W.random_workload(rng, circ, B)
+    got = run_gpu(circ, wl.inputs, wl.weights, wl.grad_out, precision, qcirc=jit_circuit(circ, n))
+    assert_parity(got, oracle_ref(wl), precision, f"jit single tile n={n} B={B} {precision}")
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_random_circuits(precision, seed):
     rng = np.random.default_rng(500 + seed)
