@@ -174,6 +174,22 @@ def test_specialised_kernels_compile_without_a_device(qtm):
             assert "qtm_jit_bwd" in src and "u1_" in src
 
 
+def test_last_forward_sweep_writes_expectations_only_for_single_tile_samples(qtm):
+    """With one tile per sample the last specialised forward sweep divides by
+    the norm and writes <Z_m>; with several it leaves per-workgroup partial
+    rows for the reduction kernel (the n = 20 benchmark circuit)."""
+    for n, tile, direct in ((8, 8, True), (12, 12, True), (12, 10, False), (20, 12, False)):
+        c = qtm.Circuit.from_workload(W.layered_circuit(n, 2, "ladder"))
+        c.set_option(qtm.QTM_OPT_TILE_QUBITS, tile)
+        last = len(c.plan("c64")["sweeps"]) - 1
+        src = c.jit_source("c64", 0, last)
+        assert ("a.out[" in src) == direct, (n, tile)
+        assert ("a.part_obs[" in src) == (not direct), (n, tile)
+        # earlier sweeps never write observables
+        if last > 0:
+            assert "a.out[" not in c.jit_source("c64", 0, 0)
+
+
 def test_paper_ansatz_plans_and_compiles(qtm):
     """The paper's ansatz (weight-scaled inputs) plans like any circuit: the
     plan's gate order gives the oracle's results, and its specialised
