@@ -54,8 +54,6 @@ def test_single_tile_samples_write_expectations_directly(precision, n, L, ent, B
     # tile = n: one workgroup holds a whole sample, and the last forward sweep
     # divides by the norm itself instead of leaving partial rows (at n = 5 a
     # workgroup has 2 threads for 9 observables, so each thread takes several)
-    if precision == "c128" and n > 10:
-        pytest.skip("complex128 tiles default to 11 qubits; a 12-qubit complex128 tile is not a tested configuration")
     rng = np.random.default_rng(40 + n)
     masks = ((1 << n) - 1, 0b101, 0b11 << (n - 2), 1 << (n - 1))
     circ = W.layered_circuit(n, L, ent, extra_masks=masks)
@@ -136,11 +134,32 @@ def test_matrix_core_random_cz_heavy(seed):
     assert_parity(got, oracle_ref(wl), "c64", f"jit cz-heavy seed={seed} t{t}l{k}")
 
 
-def test_c3_benchmarked_configuration():
-    """The n=20 workload in the configuration the benchmark times (tile 11, 4
-    low qubits, specialised sweeps) against the oracle fixture."""
+def test_c3_runner_up_configuration():
+    """The n=20 workload at tile 11 / 4 low qubits (specialised sweeps), the
+    autotuner's second choice, against the oracle fixture.  The configuration
+    the benchmark times (tile 12 / 5 low qubits) is the default one, which
+    test_c3_full_batch runs."""
     d = np.load(os.path.join(GOLDEN, "oracle_c3_b64.npz"), allow_pickle=False)
     wl = W.config_workload("c3")
     got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, "c64",
                   qcirc=jit_circuit(wl.circuit, 11, 4))
     assert_parity(got, (d["expvals"], d["grad_w"], d["grad_x"]), "c64", "jit c3 t11l4")
+
+
+@pytest.mark.parametrize("jit", [0, 1])
+@pytest.mark.parametrize("n,L,ent,klo", [(12, 3, "ring", 5), (14, 2, "ladder", 4)])
+def test_c128_tile12(jit, n, L, ent, klo):
+    """complex128 with 12-qubit tiles (the option and the autotuner accept
+    them; the default complex128 tile is 11): generic and specialised sweeps,
+    one tile per sample (n = 12) and several (n = 14)."""
+    import paper_2404_06314_amd as q
+    rng = np.random.default_rng(1200 + n)
+    circ = W.layered_circuit(n, L, ent, extra_masks=((1 << n) - 1,))
+    wl = W.random_workload(rng, circ, 3)
+    c = q.Circuit.from_workload(circ)
+    c.set_option(q.QTM_OPT_JIT, jit)
+    c.set_option(q.QTM_OPT_TILE_QUBITS, 12)
+    c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
+    got = run_gpu(circ, wl.inputs, wl.weights, wl.grad_out, "c128", qcirc=c)
+    assert c.plan("c128")["kt"] == 12
+    assert_parity(got, oracle_ref(wl), "c128", f"c128 tile 12 n={n} jit={jit}")
