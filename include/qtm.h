@@ -53,7 +53,10 @@ extern "C" {
 #define QTM_ERR_INVALID_ARG (-1) /* bad qubit, control == target, index out of range,
                                     batch <= 0, NULL where required, bad mask */
 #define QTM_ERR_UNSUPPORTED (-2) /* n_qubits > 30, unknown gate type or option */
-#define QTM_ERR_WORKSPACE (-3)   /* device allocation of the workspace failed */
+#define QTM_ERR_WORKSPACE (-3)   /* device allocation of the workspace failed, or it would
+                                    take a circuit handle's workspace beyond the byte count in
+                                    the environment variable QTM_MAX_WORKSPACE_BYTES (read when
+                                    a workspace buffer grows; unset or 0 = no cap) */
 #define QTM_ERR_HIP (-4)         /* a HIP call failed; message in qtm_last_error */
 #define QTM_ERR_STATE (-5)       /* state buffer not produced by qtm_forward for
                                     this (circuit, batch, precision) */
@@ -82,13 +85,31 @@ enum {
   QTM_OPT_PATH = 0,        /* QTM_PATH_*; AUTO = fused */
   QTM_OPT_TILE_QUBITS = 1, /* fused path: qubits per LDS tile (0 = default) */
   QTM_OPT_LOW_QUBITS = 2,  /* fused path: contiguous low qubits always in a tile */
-  QTM_OPT_RENORM = 3,      /* reserved: expectation values are always divided by the norm */
+  QTM_OPT_RENORM = 3,      /* fused path: R >= 1 rescales the states every R sweeps with FP64
+                              norms (see the note at qtm_forward); 0 (default): no rescale.  The
+                              expectation values and gradients are divided by the FP64 norm in
+                              either case.  0 <= R <= 1024, else QTM_ERR_INVALID_ARG. */
   QTM_OPT_TIMING = 4,      /* 1: record HIP events around every sweep kernel (qtm_timing_read) */
   QTM_OPT_JIT = 5          /* fused path: 1 = run sweep kernels specialised for this circuit
                               (generated from its plan and compiled with hiprtc on the first
                               call per precision, which takes seconds; errors surface as
                               QTM_ERR_UNSUPPORTED with the compiler's message), 0 = the
-                              compiled generic sweep kernels (default) */
+                              compiled generic sweep kernels (default) */,
+  QTM_OPT_CHECK_ANGLES = 6 /* 1: qtm_forward, qtm_backward and qtm_jacobian first check that every
+                              input and weight is finite (a check kernel on the stream, then a
+                              copy to the host and a wait for the stream); a NaN or infinity
+                              returns QTM_ERR_INVALID_ARG naming the first such entry, and
+                              nothing else is launched.  0 (default): no check, no wait. */,
+  QTM_OPT_DENSE_BLOCKS = 7 /* 1: complex64 forwards apply the weight part of each layer, RZ RY on
+                              4 consecutive qubits with the CZ gates inside the block, as one dense
+                              16 x 16 unitary shared by the batch (Sec. II-B, Eq. (6)) on the
+                              matrix cores, one pass over the state per (layer, block), with the
+                              per-sample RX encoding on the vector units and the CZ gates between
+                              blocks as signs.  Only for layered circuits (per layer RX(input),
+                              RY(weight), RZ(weight) on every qubit in qubit order, then the open
+                              CZ chain) of 12, 16, ... qubits with Z-string observables, else
+                              QTM_ERR_UNSUPPORTED; the backward is unchanged (it prepares its own
+                              gate matrices).  0 (default): the fused sweeps. */
 };
 
 /* One gate.  Rotations (RX, RY, RZ): q0 = qubit, src = QTM_SRC_INPUT or
@@ -143,6 +164,14 @@ int qtm_set_option(qtm_circuit_t c, int32_t option, int64_t value);
 int qtm_state_bytes(qtm_circuit_t c, int32_t batch, int32_t precision, size_t *bytes);
 
 /* Forward pass (Sec. II-A, II-B).
+ * Periodic renormalisation (QTM_OPT_RENORM = R >= 1, fused path): forward
+ * sweep s, for s a positive multiple of R, scales the state it loads by
+ * 1 / sqrt(N), N the FP64 norm the sweep before it stored; backward sweep i
+ * (a positive multiple of R) scales psi and lambda by the square roots of
+ * the products of their FP64 load / end norm ratios over the R sweeps
+ * before it, undoing the rounding drift of those sweeps.  Every gate is
+ * linear, so the results change by rounding only.  Ignored by the per-gate
+ * path and the uneven batch.
  *   inputs   dev [batch][n_inputs]  float64 (may be NULL if n_inputs == 0)
  *   weights  dev [n_weights]        float64 (may be NULL if n_weights == 0)
  *   expvals  dev [batch][n_obs]     float64, written
@@ -154,9 +183,13 @@ int qtm_forward(qtm_circuit_t c, int32_t batch, int32_t precision, const double 
 /* Adjoint VJP (Sec. II-A, reverse gradient).
  *   grad_expvals  dev [batch][n_obs] float64: G = dL/d<O>
  *   state         dev buffer written by qtm_forward with the same circuit, batch,
- *                 precision and angles; the backward consumes it (it works in
- *                 place and its contents on return are unspecified), so one
- *                 forward serves one backward.
+ *                 precision and angles; the backward consumes it: it works in
+ *                 place and does not un-compute the states back to |0...0>
+ *                 (the last un-apply of each qubit is skipped and the final
+ *                 sweep stores nothing), so its contents on return are
+ *                 unspecified and one forward serves one backward.  The
+ *                 rounding drift of the evolution is reported instead by
+ *                 qtm_forward_norms.
  *                 NULL: the forward is recomputed into the workspace.
  *   grad_weights  dev [n_weights] float64, overwritten (summed over the batch)
  *   grad_inputs   dev [batch][n_inputs] float64, overwritten; may be NULL. */
@@ -224,6 +257,18 @@ int qtm_multi_timing_read(qtm_multi_t m, int32_t kind, double *total_ms, int64_t
 /* Number of tile work units in the persistent queue of a pass (kind 0
  * forward, 1 backward); -1 before the first call has built the queue. */
 int qtm_multi_units(qtm_multi_t m, int32_t kind, int64_t *units);
+
+/* Diagnostics (norm-drift watchdog): every sample's squared norm <psi|psi>
+ * of the final state of the last forward pass on c (qtm_forward, or the
+ * forward that qtm_backward with state = NULL or qtm_jacobian runs), taken
+ * from that pass's own FP64 reduction (no further pass over the states).
+ * The evolution is unitary (Eq. (1)-(2): a normalised state), so the exact
+ * value is 1 and its distance from 1 is the rounding drift of the amplitude
+ * arithmetic; the expectation values are divided by it.
+ *   norms  dev [batch] float64, written (asynchronously on `stream`).
+ * QTM_ERR_STATE if the last forward pass on c had another batch, or if a
+ * per-gate-path backward has reused its partial sums since. */
+int qtm_forward_norms(qtm_circuit_t c, int32_t batch, double *norms, void *stream);
 
 /* Diagnostics: with QTM_OPT_TIMING set, the library records a pair of HIP
  * events on the call's stream around every sweep kernel it launches.

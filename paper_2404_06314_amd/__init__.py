@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import (QTM_C64, QTM_C128, QTM_CNOT, QTM_CZ, QTM_PATH_AUTO, QTM_PATH_FUSED,
                    QTM_PATH_PLAIN, QTM_RX, QTM_RY, QTM_RZ, QTM_SRC_INPUT, QTM_SRC_NONE,
                    QTM_SRC_SCALED, QTM_SRC_WEIGHT, QTM_OPT_LOW_QUBITS, QTM_OPT_PATH, QTM_OPT_RENORM,
-                   QTM_OPT_TILE_QUBITS, QTM_OPT_TIMING, QTM_OPT_JIT, QtmError)
+                   QTM_OPT_TILE_QUBITS, QTM_OPT_TIMING, QTM_OPT_JIT, QTM_OPT_CHECK_ANGLES, QTM_OPT_DENSE_BLOCKS, QtmError)
 
 __all__ = ["Circuit", "Multi", "QtmError", "precision_code", "lib_path",
            "QTM_C64", "QTM_C128", "QTM_PATH_AUTO", "QTM_PATH_PLAIN", "QTM_PATH_FUSED"]
@@ -202,6 +202,15 @@ class Circuit:
                           _ptr(grad_expvals), _ptr(state), _ptr(gw), _ptr(gx),
                           _stream_ptr(stream))
         return gw, gx
+
+    def forward_norms(self, batch: int, stream=None):
+        """Squared norms (B,) float64 of the final states of the last forward
+        pass (qtm_forward_norms): 1 in exact arithmetic; the distance from 1
+        is the rounding drift of the evolution."""
+        import torch
+        out = torch.empty((int(batch),), dtype=torch.float64, device="cuda")
+        _lib.check(_lib.load().qtm_forward_norms(self._h, int(batch), _ptr(out), _stream_ptr(stream)))
+        return out
 
 
 def _jacobian(self, inputs, weights, precision=QTM_C64, need_inputs=True, stream=None):

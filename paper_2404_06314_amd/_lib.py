@@ -26,6 +26,8 @@ QTM_C64, QTM_C128 = 0, 1
 QTM_PATH_AUTO, QTM_PATH_PLAIN, QTM_PATH_FUSED = 0, 1, 2
 QTM_OPT_PATH, QTM_OPT_TILE_QUBITS, QTM_OPT_LOW_QUBITS, QTM_OPT_RENORM, QTM_OPT_TIMING = 0, 1, 2, 3, 4
 QTM_OPT_JIT = 5
+QTM_OPT_CHECK_ANGLES = 6
+QTM_OPT_DENSE_BLOCKS = 7
 
 # every exported function of include/qtm.h: name -> (restype, argtypes)
 _P = ctypes.c_void_p
@@ -49,6 +51,7 @@ SIGNATURES = {
     "qtm_multi_timing_read": (ctypes.c_int, [_P, _I32, _P, _P]),
     "qtm_multi_units": (ctypes.c_int, [_P, _I32, _P]),
     "qtm_timing_read": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "qtm_forward_norms": (ctypes.c_int, [_P, _I32, _P, _P]),
     "qtm_jit_source": (ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_char_p, _SZ, _P]),
     "qtm_jit_compile": (ctypes.c_int, [_P, _I32]),
     "qtm_jacobian": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P, _P]),

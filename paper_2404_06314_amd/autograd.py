@@ -4,6 +4,7 @@ module holding the trainable weights."""
 from __future__ import annotations
 
 import math
+import warnings
 
 import torch
 
@@ -55,15 +56,24 @@ class QuantumLayer(torch.nn.Module):
     circuit (QTM_OPT_JIT): a one-off compile of a few seconds on the first
     call, then 2-4x faster steps from about 14 qubits on.  The default
     (None) turns them on from SPECIALISED_FROM_QUBITS qubits.
+
+    ``drift_tol`` (a float, default None) turns on the norm-drift watchdog:
+    after each forward the squared norms of the final states
+    (qtm_forward_norms, 1 in exact arithmetic) are read back, which waits
+    for the stream, and a RuntimeWarning is issued when one is further than
+    ``drift_tol`` from 1; ``last_drift`` keeps the largest distance seen in
+    the last forward.
     """
 
     SPECIALISED_FROM_QUBITS = 14
 
     def __init__(self, circuit: Circuit, precision="c64", weights=None, device="cuda",
-                 param_sets=None, specialised=None):
+                 param_sets=None, specialised=None, drift_tol=None):
         super().__init__()
         self.circuit = circuit
         self.precision = precision
+        self.drift_tol = drift_tol
+        self.last_drift = None
         if specialised is None:
             specialised = circuit.n >= self.SPECIALISED_FROM_QUBITS
         if specialised:
@@ -113,8 +123,15 @@ class QuantumLayer(torch.nn.Module):
         return groups
 
     def forward(self, inputs):
-        return QtmFunction.apply(inputs.to(torch.float64), self.weights_vector, self.circuit,
-                                 self.precision)
+        out = QtmFunction.apply(inputs.to(torch.float64), self.weights_vector, self.circuit,
+                                self.precision)
+        if self.drift_tol is not None:
+            nr = self.circuit.forward_norms(int(inputs.shape[0]))
+            self.last_drift = float(torch.max(torch.abs(nr - 1.0)).item())
+            if self.last_drift > self.drift_tol:
+                warnings.warn(f"state norm drifted by {self.last_drift:.3e} (> {self.drift_tol:g}) "
+                              "in the last forward", RuntimeWarning)
+        return out
 
 
 def _initial(size: int, init):

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -14,6 +15,7 @@
 #include "qtm.h"
 #include "circuit.h"
 #include "jit.h"
+#include "k9.h"
 #include "kernels.h"
 #include "multi.h"
 #include "tune.h"
@@ -33,26 +35,49 @@ int hip_fail(hipError_t e, const std::string &where) {
   return QTM_ERR_HIP;
 }
 
-// Grow-only device buffer.
+// Cap on one circuit handle's device workspace in bytes, from the
+// environment variable QTM_MAX_WORKSPACE_BYTES (read whenever a workspace
+// buffer has to grow); 0 = no cap.  Returns false for a value that is not a
+// byte count.
+bool workspace_cap(size_t *cap) {
+  *cap = 0;
+  const char *v = getenv("QTM_MAX_WORKSPACE_BYTES");
+  if (!v || !*v) return true;
+  char *end = nullptr;
+  const unsigned long long x = strtoull(v, &end, 10);
+  if (!end || *end != 0) return false;
+  *cap = (size_t)x;
+  return true;
+}
+
+// Grow-only device buffer; `total` (if set) counts the bytes of all buffers
+// of the owning handle, which the cap above bounds.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  size_t *total = nullptr;
   int ensure(size_t need) {
     if (need <= bytes) return QTM_OK;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-    size_t want = need < 256 ? 256 : need;
+    const size_t want = need < 256 ? 256 : need;
+    size_t cap = 0;
+    if (!workspace_cap(&cap)) return fail(QTM_ERR_WORKSPACE, "QTM_MAX_WORKSPACE_BYTES is not a byte count");
+    const size_t others = total ? *total - bytes : 0;
+    if (cap && others + want > cap)
+      return fail(QTM_ERR_WORKSPACE, "workspace of " + std::to_string(others + want) +
+                                         " bytes exceeds QTM_MAX_WORKSPACE_BYTES=" + std::to_string(cap));
+    release();
     if (hipMalloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
       return fail(QTM_ERR_WORKSPACE, "workspace allocation of " + std::to_string(want) + " bytes failed");
     }
     bytes = want;
+    if (total) *total += want;
     return QTM_OK;
   }
   void release() {
     if (p) (void)hipFree(p);
+    if (total) *total -= bytes;
     p = nullptr;
     bytes = 0;
   }
@@ -129,7 +154,7 @@ struct qtm_circuit_s {
   int path = QTM_PATH_AUTO;
   int tile_qubits = 0;
   int low_qubits = 0;
-  int renorm = 1;
+  int renorm = 0;  // QTM_OPT_RENORM: rescale every `renorm` sweeps (0 = off)
   int device = -1;
   std::unique_ptr<EventTimer> timer;
   bool uploaded = false;
@@ -138,9 +163,20 @@ struct qtm_circuit_s {
   std::map<std::pair<int, int>, DevPlan> plans;
   std::map<std::pair<int, int>, HostPlan> hplans;
   int jit = 0;  // QTM_OPT_JIT
-  std::map<std::tuple<int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision)
+  std::map<std::tuple<int, int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision, renorm)
   DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm, part_pauli;
-  DevBuf jac_state, jac_G, jac_gw, jac_out;
+  DevBuf jac_state, jac_G, jac_gw, jac_out, chk, rn;
+  // shared-weight dense-block forward (QTM_OPT_DENSE_BLOCKS)
+  int k9 = 0;
+  K9Layout k9l;
+  K9Dev k9d;
+  DevBuf k9_tab, k9_rx, k9_part;
+  size_t ws_total = 0;  // device workspace bytes of this handle
+  int check_angles = 0;  // QTM_OPT_CHECK_ANGLES
+  // The partial sums the last forward pass left for qtm_forward_norms:
+  // [batch][rows][n_obs + 1] doubles with the squared norm in column n_obs.
+  const double *norm_part = nullptr;
+  int32_t norm_rows = 0, norm_B = 0;
   // What `mats` and `coef` hold: counted up by every forward (and by a
   // backward that prepares its own), with the fused plan, batch and
   // precision they were computed for (plan NULL: not by the fused path).
@@ -148,11 +184,16 @@ struct qtm_circuit_s {
   const DevPlan *prep_plan = nullptr;
   int32_t prep_B = 0, prep_prec = -1;
 
+  std::vector<DevBuf *> bufs() {
+    return {&cs, &part, &gocc, &lam, &state_ws, &mats, &coef, &part_obs, &part_grad, &part_norm,
+            &part_pauli, &jac_state, &jac_G, &jac_gw, &jac_out, &chk, &rn, &k9_tab, &k9_rx, &k9_part};
+  }
+  qtm_circuit_s() {
+    for (DevBuf *b : bufs()) b->total = &ws_total;
+  }
   ~qtm_circuit_s() {
     for (void *p : owned) (void)hipFree(p);
-    for (DevBuf *b : {&cs, &part, &gocc, &lam, &state_ws, &mats, &coef, &part_obs, &part_grad,
-                      &part_norm, &part_pauli, &jac_state, &jac_G, &jac_gw, &jac_out})
-      b->release();
+    for (DevBuf *b : bufs()) b->release();
   }
 };
 
@@ -293,6 +334,7 @@ JitSpec jit_spec(qtm_circuit_t c, int precision, const HostPlan &hp) {
   sp.masks = c->desc.masks;
   sp.seed_add = c->desc.has_offdiag();
   sp.nwg_full = fused_wg_per_sample(sp.n, sp.kt);
+  sp.renorm = c->renorm;
   sp.hp = &hp;
   return sp;
 }
@@ -304,7 +346,7 @@ int get_jit(qtm_circuit_t c, int precision, bool load, const JitSweeps **out) {
   const HostPlan *hp = nullptr;
   int rc = get_host_plan(c, precision, &hp);
   if (rc) return rc;
-  const auto key = std::make_tuple(hp->kt, hp->klo, precision);
+  const auto key = std::make_tuple(hp->kt, hp->klo, precision, c->renorm);
   auto it = c->jits.find(key);
   if (it == c->jits.end()) {
     std::unique_ptr<JitSweeps> js(new JitSweeps());
@@ -342,65 +384,168 @@ int check_common(qtm_circuit_t c, int32_t batch, int32_t precision) {
 
 size_t elem_bytes(int precision) { return precision == QTM_C128 ? 16 : 8; }
 
-int forward_sweeps(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, const double *w,
-                   double *out, void *state, bool keep, hipStream_t s);
+// Device buffers of one forward pass (the library's workspace).
+struct FwdBufs {
+  void *mats = nullptr;         // fused: [B][n_blocks] gate matrices
+  double *coef = nullptr;       // fused: [B][n_occ][3] derivative coefficients
+  double *part_obs = nullptr;   // fused: observable partial sums
+  double2 *cs = nullptr;        // per-gate: half-angle cosines and sines
+  double *part = nullptr;       // per-gate: observable partial sums
+  double *part_pauli = nullptr; // observables with X or Y factors
+  double *rn = nullptr;         // fused, QTM_OPT_RENORM: the forward's norm records
+};
 
-// Forward pass: the sweeps (or per-gate kernels) with the diagonal
-// observables, then the observables with X or Y factors.
+// Byte sizes of those buffers for (B, plan); p = NULL on the per-gate path.
+struct FwdSizes {
+  size_t mats = 0, coef = 0, part_obs = 0, cs = 0, part = 0, part_pauli = 0, rn = 0;
+};
+FwdSizes fwd_sizes(const DevCircuit &d, const DevPlan *p, int32_t B, int renorm) {
+  FwdSizes z;
+  if (p) {
+    z.mats = (size_t)B * std::max(p->n_blocks, 1) * sizeof(M2<double>);
+    z.part_obs = fused_part_obs_doubles(d, *p, B) * sizeof(double);
+    z.coef = (size_t)B * std::max(d.n_occ, 1) * 3 * sizeof(double);
+    if (renorm) z.rn = fused_rn_doubles(d, *p, B) * sizeof(double);
+  } else {
+    z.cs = (size_t)B * std::max(d.n_occ, 1) * sizeof(double2);
+    z.part = plain_part_doubles(d, B) * sizeof(double);
+  }
+  if (d.n_nd > 0) z.part_pauli = pauli_part_doubles(d, B) * sizeof(double);
+  return z;
+}
+
+// The forward's launches: the sweeps (p != NULL; js = specialised kernels or
+// NULL) or the per-gate kernels, with the diagonal observables, then the
+// observables with X or Y factors (read from the stored final states).
+hipError_t launch_forward(qtm_circuit_t c, const DevPlan *p, const JitSweeps *js, int32_t B, int32_t prec,
+                          const double *x, const double *w, double *out, void *state, bool keep,
+                          const FwdBufs &b, SweepTimer *tm, hipStream_t s) {
+  const DevCircuit &d = c->dev;
+  if (d.n_nd > 0) keep = true;
+  hipError_t e;
+  if (p) {
+    Renorm rn;
+    if (c->renorm) {
+      rn.period = c->renorm;
+      rn.fwd = b.rn;
+    }
+    e = prec == QTM_C64
+            ? fused_forward<float>(d, *p, B, x, w, b.mats, b.coef, state, b.part_obs, out, keep, s, tm, js, rn)
+            : fused_forward<double>(d, *p, B, x, w, b.mats, b.coef, state, b.part_obs, out, keep, s, tm, js, rn);
+  } else {
+    e = launch_half_angles(d, B, x, w, b.cs, s);
+    if (e == hipSuccess)
+      e = prec == QTM_C64 ? plain_forward<float>(d, c->hinfo, B, b.cs, state, b.part, out, false, s)
+                          : plain_forward<double>(d, c->hinfo, B, b.cs, state, b.part, out, false, s);
+  }
+  if (e != hipSuccess) return e;
+  return prec == QTM_C64 ? launch_pauli_expval<float>(d, B, state, b.part_pauli, out, s)
+                         : launch_pauli_expval<double>(d, B, state, b.part_pauli, out, s);
+}
+
+// The shared-weight dense-block forward (complex64): uploads the slot
+// tables once, sizes its workspace, runs k9_forward.
+int k9_run(qtm_circuit_t c, int32_t B, const double *x, const double *w, double *out, void *state,
+           hipStream_t s) {
+  const DevCircuit &d = c->dev;
+  int rc;
+  if (c->k9d.n == 0) {
+    int32_t *rx = nullptr, *ry = nullptr, *rz = nullptr;
+    if ((rc = upload(&rx, c->k9l.rx, c->owned)) || (rc = upload(&ry, c->k9l.ry, c->owned)) ||
+        (rc = upload(&rz, c->k9l.rz, c->owned)))
+      return rc;
+    c->k9d.rx = rx;
+    c->k9d.ry = ry;
+    c->k9d.rz = rz;
+    c->k9d.L = c->k9l.L;
+    c->k9d.n = c->k9l.n;
+  }
+  const int rows = k9_part_rows(c->k9l);
+  if ((rc = c->k9_tab.ensure(k9_tab_floats(c->k9l) * sizeof(float))) ||
+      (rc = c->k9_rx.ensure((size_t)B * c->k9l.L * c->k9l.n * sizeof(float2))) ||
+      (rc = c->k9_part.ensure((size_t)B * rows * (d.n_obs + 1) * sizeof(double))))
+    return rc;
+  c->prep_gen++;
+  c->prep_plan = nullptr;
+  c->norm_part = nullptr;
+  hipError_t e = k9_forward(c->k9d, d, B, x, w, state, (float *)c->k9_tab.p, (float2 *)c->k9_rx.p,
+                            (double *)c->k9_part.p, out, s, c->timer.get());
+  if (e != hipSuccess) return hip_fail(e, "dense-block forward launch");
+  c->norm_part = (const double *)c->k9_part.p;
+  c->norm_rows = rows;
+  c->norm_B = B;
+  return QTM_OK;
+}
+
+// Forward pass on the library's workspace.
 int do_forward(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, const double *w,
                double *out, void *state, bool keep, hipStream_t s) {
   const DevCircuit &d = c->dev;
   int rc;
-  if (d.n_nd > 0) {
-    // observables with X or Y factors are read from the stored final states
-    keep = true;
-    if ((rc = c->part_pauli.ensure(pauli_part_doubles(d, B) * sizeof(double)))) return rc;
-  }
-  if ((rc = forward_sweeps(c, B, prec, x, w, out, state, keep, s))) return rc;
-  hipError_t e = prec == QTM_C64
-                     ? launch_pauli_expval<float>(d, B, state, (double *)c->part_pauli.p, out, s)
-                     : launch_pauli_expval<double>(d, B, state, (double *)c->part_pauli.p, out, s);
-  if (e != hipSuccess) return hip_fail(e, "pauli observables launch");
-  return QTM_OK;
-}
-
-int forward_sweeps(qtm_circuit_t c, int32_t B, int32_t prec, const double *x, const double *w,
-                   double *out, void *state, bool keep, hipStream_t s) {
-  const DevCircuit &d = c->dev;
-  int rc;
+  if (c->k9 && prec == QTM_C64 && use_fused(c)) return k9_run(c, B, x, w, out, state, s);
+  DevPlan *p = nullptr;
+  const JitSweeps *js = nullptr;
   if (use_fused(c)) {
-    DevPlan *p = nullptr;
     if ((rc = get_plan(c, prec, &p))) return rc;
-    if ((rc = c->mats.ensure((size_t)B * std::max(p->n_blocks, 1) * sizeof(M2<double>)))) return rc;
-    if ((rc = c->part_obs.ensure(fused_part_obs_doubles(d, *p, B) * sizeof(double)))) return rc;
-    // the derivative coefficients too, so that the backward can reuse both
-    if ((rc = c->coef.ensure((size_t)B * std::max(d.n_occ, 1) * 3 * sizeof(double)))) return rc;
-    const JitSweeps *js = nullptr;
     if (c->jit && (rc = get_jit(c, prec, true, &js))) return rc;
-    c->prep_gen++;
-    c->prep_plan = nullptr;
-    hipError_t e =
-        prec == QTM_C64
-            ? fused_forward<float>(d, *p, B, x, w, c->mats.p, (double *)c->coef.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get(), js)
-            : fused_forward<double>(d, *p, B, x, w, c->mats.p, (double *)c->coef.p, state, (double *)c->part_obs.p, out, keep, s, c->timer.get(), js);
-    if (e != hipSuccess) return hip_fail(e, "fused forward launch");
-    c->prep_plan = p;
-    c->prep_B = B;
-    c->prep_prec = prec;
-    return QTM_OK;
+  }
+  const FwdSizes z = fwd_sizes(d, p, B, c->renorm);
+  FwdBufs b;
+  if (p) {
+    // the derivative coefficients too, so that the backward can reuse both
+    if ((rc = c->mats.ensure(z.mats)) || (rc = c->part_obs.ensure(z.part_obs)) || (rc = c->coef.ensure(z.coef)))
+      return rc;
+    b.mats = c->mats.p;
+    b.coef = (double *)c->coef.p;
+    b.part_obs = (double *)c->part_obs.p;
+    if (z.rn) {
+      // the forward's records, then the backward's (fused_rn_doubles)
+      if ((rc = c->rn.ensure(z.rn))) return rc;
+      b.rn = (double *)c->rn.p;
+    }
+  } else {
+    if ((rc = c->cs.ensure(z.cs)) || (rc = c->part.ensure(z.part))) return rc;
+    b.cs = (double2 *)c->cs.p;
+    b.part = (double *)c->part.p;
+  }
+  if (z.part_pauli) {
+    if ((rc = c->part_pauli.ensure(z.part_pauli))) return rc;
+    b.part_pauli = (double *)c->part_pauli.p;
   }
   c->prep_gen++;
   c->prep_plan = nullptr;
-  if ((rc = c->cs.ensure((size_t)B * std::max(d.n_occ, 1) * sizeof(double2)))) return rc;
-  if ((rc = c->part.ensure(plain_part_doubles(d, B) * sizeof(double)))) return rc;
-  hipError_t e = launch_half_angles(d, B, x, w, (double2 *)c->cs.p, s);
-  if (e == hipSuccess)
-    e = prec == QTM_C64 ? plain_forward<float>(d, c->hinfo, B, (double2 *)c->cs.p, state,
-                                               (double *)c->part.p, out, false, s)
-                        : plain_forward<double>(d, c->hinfo, B, (double2 *)c->cs.p, state,
-                                                (double *)c->part.p, out, false, s);
-  if (e != hipSuccess) return hip_fail(e, "plain forward launch");
+  c->norm_part = nullptr;
+  hipError_t e = launch_forward(c, p, js, B, prec, x, w, out, state, keep, b, c->timer.get(), s);
+  if (e != hipSuccess) return hip_fail(e, "forward launch");
+  if (p) {
+    c->prep_plan = p;
+    c->prep_B = B;
+    c->prep_prec = prec;
+  }
+  c->norm_part = p ? b.part_obs : b.part;
+  c->norm_rows = p ? fused_wg_per_sample(d.n, p->kt) : plain_norm_rows(d.n, B);
+  c->norm_B = B;
   return QTM_OK;
+}
+
+// With QTM_OPT_CHECK_ANGLES: every input and weight must be finite.  Runs a
+// check kernel on the stream, copies its result to the host and waits.
+int check_angles(qtm_circuit_t c, int32_t B, const double *x, const double *w, hipStream_t s) {
+  if (!c->check_angles) return QTM_OK;
+  const int64_t nx = x ? (int64_t)B * c->desc.n_inputs : 0, nw = w ? c->desc.n_weights : 0;
+  int rc = c->chk.ensure(sizeof(unsigned long long));
+  if (rc) return rc;
+  unsigned long long first = 0;
+  hipError_t e = launch_first_nonfinite(x, nx, w, nw, (unsigned long long *)c->chk.p, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&first, c->chk.p, sizeof first, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "angle check");
+  if (first == ~0ull) return QTM_OK;
+  if ((int64_t)first < nx)
+    return fail(QTM_ERR_INVALID_ARG, "non-finite angle source: inputs[" +
+                                         std::to_string(first / c->desc.n_inputs) + "][" +
+                                         std::to_string(first % c->desc.n_inputs) + "]");
+  return fail(QTM_ERR_INVALID_ARG, "non-finite angle source: weights[" + std::to_string(first - nx) + "]");
 }
 
 // Adjoint backward from the final states in psi (consumed).  Leaves the
@@ -436,18 +581,27 @@ int run_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
       c->prep_B = batch;
       c->prep_prec = precision;
     }
+    Renorm rn;
+    if (c->renorm) {
+      const size_t nrn = fused_rn_doubles(d, *p, batch);
+      if ((rc = c->rn.ensure(nrn * sizeof(double)))) return rc;
+      rn.period = c->renorm;
+      rn.bwd = (double *)c->rn.p + nrn / 5;  // after the forward's records
+    }
     e = precision == QTM_C64
             ? fused_backward<float>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
                                     (double *)c->coef.p, reuse, psi, c->lam.p, (double *)c->part_grad.p,
                                     (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
-                                    grad_inputs, s, c->timer.get(), js)
+                                    grad_inputs, s, c->timer.get(), js, rn)
             : fused_backward<double>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
                                      (double *)c->coef.p, reuse, psi, c->lam.p, (double *)c->part_grad.p,
                                      (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
-                                     grad_inputs, s, c->timer.get(), js);
+                                     grad_inputs, s, c->timer.get(), js, rn);
   } else {
     if ((rc = c->cs.ensure((size_t)batch * std::max(d.n_occ, 1) * sizeof(double2)))) return rc;
     if ((rc = c->part.ensure(plain_part_doubles(d, batch) * sizeof(double)))) return rc;
+    // the per-gate backward reuses the forward's partial-sum buffer
+    c->norm_part = nullptr;
     e = launch_half_angles(d, batch, inputs, weights, (double2 *)c->cs.p, s);
     if (e == hipSuccess)
       e = precision == QTM_C64
@@ -526,7 +680,8 @@ int qtm_set_option(qtm_circuit_t c, int32_t option, int64_t value) {
       c->low_qubits = (int)value;
       return QTM_OK;
     case QTM_OPT_RENORM:
-      c->renorm = value ? 1 : 0;
+      if (value < 0 || value > 1024) return fail(QTM_ERR_INVALID_ARG, "renormalisation period must be 0..1024");
+      c->renorm = (int)value;
       return QTM_OK;
     case QTM_OPT_TIMING:
       if (value && !c->timer) c->timer.reset(new EventTimer());
@@ -534,6 +689,19 @@ int qtm_set_option(qtm_circuit_t c, int32_t option, int64_t value) {
       return QTM_OK;
     case QTM_OPT_JIT:
       c->jit = value ? 1 : 0;
+      return QTM_OK;
+    case QTM_OPT_CHECK_ANGLES:
+      c->check_angles = value ? 1 : 0;
+      return QTM_OK;
+    case QTM_OPT_DENSE_BLOCKS:
+      if (value) {
+        std::string why;
+        K9Layout k;
+        if (!k9_detect(c->desc, k, why)) return fail(QTM_ERR_UNSUPPORTED, "dense blocks: " + why);
+        if (c->desc.has_offdiag()) return fail(QTM_ERR_UNSUPPORTED, "dense blocks: Z-string observables only");
+        if (c->k9d.n == 0) c->k9l = std::move(k);
+      }
+      c->k9 = value ? 1 : 0;
       return QTM_OK;
     default:
       return fail(QTM_ERR_UNSUPPORTED, "unknown option");
@@ -557,6 +725,7 @@ int qtm_forward(qtm_circuit_t c, int32_t batch, int32_t precision, const double 
   if (c->desc.n_weights > 0 && !weights) return fail(QTM_ERR_INVALID_ARG, "weights is NULL");
   if ((rc = ensure_device(c))) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if ((rc = check_angles(c, batch, inputs, weights, s))) return rc;
   const size_t sbytes = ((size_t)batch << c->desc.n) * elem_bytes(precision);
   void *st = state;
   if (!st) {
@@ -583,6 +752,7 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
   if (c->desc.n_weights > 0 && !weights) return fail(QTM_ERR_INVALID_ARG, "weights is NULL");
   if ((rc = ensure_device(c))) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if ((rc = check_angles(c, batch, inputs, weights, s))) return rc;
   const DevCircuit &d = c->dev;
   const size_t sbytes = ((size_t)batch << c->desc.n) * elem_bytes(precision);
   void *psi = state;
@@ -619,6 +789,7 @@ int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double
   if (cd.n_weights > 0 && !weights) return fail(QTM_ERR_INVALID_ARG, "weights is NULL");
   if ((rc = ensure_device(c))) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if ((rc = check_angles(c, batch, inputs, weights, s))) return rc;
   const DevCircuit &d = c->dev;
   const int M = d.n_obs;
   const size_t sbytes = ((size_t)batch << cd.n) * elem_bytes(precision);
@@ -672,6 +843,15 @@ int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *la
   if (!c || kind < 0 || kind > 1 || !total_ms || !launches)
     return fail(QTM_ERR_INVALID_ARG, "bad arguments");
   return read_timer(c->timer.get(), kind, total_ms, launches);
+}
+
+int qtm_forward_norms(qtm_circuit_t c, int32_t batch, double *norms, void *stream) {
+  if (!c || !norms) return fail(QTM_ERR_INVALID_ARG, "bad arguments");
+  if (!c->norm_part || c->norm_B != batch)
+    return fail(QTM_ERR_STATE, "no forward pass with this batch has run on the circuit");
+  hipError_t e = launch_norms(c->norm_part, batch, c->norm_rows, c->dev.n_obs, norms, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "norms launch");
+  return QTM_OK;
 }
 
 // Diagnostics: JSON description of the fused plan for (precision) into buf.
@@ -751,7 +931,7 @@ int qtm_jit_info(qtm_circuit_t c, int32_t precision, int32_t dir, int32_t sweep,
   const HostPlan *hp = nullptr;
   int rc = get_host_plan(c, precision, &hp);
   if (rc) return rc;
-  auto it = c->jits.find(std::make_tuple(hp->kt, hp->klo, (int)precision));
+  auto it = c->jits.find(std::make_tuple(hp->kt, hp->klo, (int)precision, c->renorm));
   if (it == c->jits.end() || !it->second->loaded) return fail(QTM_ERR_INVALID_ARG, "specialised kernels not loaded");
   if (sweep < 0 || sweep >= (int)it->second->k[dir].size()) return fail(QTM_ERR_INVALID_ARG, "sweep out of range");
   *vgprs = it->second->k[dir][sweep].vgprs;

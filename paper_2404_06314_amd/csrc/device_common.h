@@ -150,6 +150,52 @@ __device__ __forceinline__ float dpp_sum_to_lane63(float v) {
   return v;
 }
 
+// A double from another lane of the same row of 16, by a DPP pattern that
+// is valid for every lane (quad_perm, row_ror, row_mirror): both 32-bit
+// halves move with the same pattern.
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm_d(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// FP64 sum of a per-thread value over the 64 lanes of a wave (every lane
+// gets it): DPP steps within rows of 16, lane shuffles across rows.
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v += dpp_perm_d<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_perm_d<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_perm_d<0x124>(v);  // row_ror:4
+  v += dpp_perm_d<0x128>(v);  // row_ror:8
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// FP64 sums of three per-thread values a, b, c over each row of 16 lanes.
+// The first two steps transpose while they reduce (a lane passes on two
+// values, then one, instead of three), so on return each lane holds one of
+// its row's sums, chosen by lane & 3: 0 -> a, 1 -> c, 2 -> b, 3 -> 0.
+__device__ __forceinline__ double row_sum3_d(double a, double b, double c) {
+  const unsigned l = __lane_id();
+  const bool odd = (l & 1u) != 0, hi = (l & 2u) != 0;
+  const double s0 = odd ? a : c, k0 = odd ? c : a;
+  const double s1 = odd ? b : 0.0, k1 = odd ? 0.0 : b;
+  const double u0 = k0 + dpp_perm_d<0xb1>(s0);  // quad_perm [1,0,3,2]: a (even) / c (odd) pair sums
+  const double u1 = k1 + dpp_perm_d<0xb1>(s1);  //                      b (even) / 0 (odd)
+  const double s2 = hi ? u0 : u1, k2 = hi ? u1 : u0;
+  double r = k2 + dpp_perm_d<0x4e>(s2);         // quad_perm [2,3,0,1]: quad sums
+  r += dpp_perm_d<0x124>(r);                    // row_ror:4
+  r += dpp_perm_d<0x128>(r);                    // row_ror:8
+  return r;
+}
+// Component (0 = a, 1 = b, 2 = c) that row_sum3_d leaves in lane l (l & 3 < 3).
+__device__ __forceinline__ int row_sum3_comp(unsigned l) {
+  const unsigned q = l & 3u;
+  return q == 0u ? 0 : q == 1u ? 2 : 1;
+}
+
 __device__ __forceinline__ int parity_u64(uint64_t v) { return __popcll(v) & 1; }
 
 // Matrix of a fixed one-qubit gate (type 5 H, 6 X, 7 Y, 8 Z, 9 S, 10 S^dag,

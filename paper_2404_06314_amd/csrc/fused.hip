@@ -36,6 +36,9 @@ int fused_wg_per_sample(int n, int kt) {
 size_t fused_part_obs_doubles(const DevCircuit &d, const DevPlan &p, int B) {
   return (size_t)B * fused_wg_per_sample(d.n, p.kt) * (d.n_obs + 1);
 }
+size_t fused_rn_doubles(const DevCircuit &d, const DevPlan &p, int B) {
+  return (size_t)std::max(p.n_sweeps, 1) * B * fused_wg_per_sample(d.n, p.kt) * 5;
+}
 size_t fused_part_grad_doubles(const DevCircuit &d, const DevPlan &p, int B) {
   return (size_t)B * (size_t)(p.n_gslots > 0 ? p.n_gslots : 1) * fused_wg_per_sample(d.n, p.kt) * 3;
 }
@@ -128,7 +131,7 @@ static size_t bwd_lds(int ngs) {
   constexpr int NT = 1 << (KT - kRegBits);
   constexpr int NW = (NT + 63) / 64;
   const size_t acc = (size_t)ngs * 3 * NW;
-  return (2 * sizeof(Cx<R>) << KT) + sizeof(M2<R>) * kMaxSweepBlocks + sizeof(double) * (NW + acc);
+  return (2 * sizeof(Cx<R>) << KT) + sizeof(M2<R>) * kMaxSweepBlocks + sizeof(double) * (2 * NW + acc);
 }
 
 template <typename K>
@@ -154,7 +157,7 @@ static hipError_t launch_sweep(K kernel, const JitSweeps *js, int dir, int sw, i
 template <typename R, int KT>
 static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *mats, void *state,
                           double *part_obs, double *out, bool store_final, hipStream_t s,
-                          SweepTimer *tm, const JitSweeps *js) {
+                          SweepTimer *tm, const JitSweeps *js, const Renorm &rn) {
   const int nwg = fused_wg_per_sample(d.n, KT);
   const size_t lds = fwd_lds<R, KT>(d.n_obs);
   hipError_t e = allow_lds(k_fused_fwd<R, KT>, lds);
@@ -177,6 +180,15 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *ma
     a.obs_sgn = p.obs_sgn_f;
     a.part_obs = part_obs;
     a.out = out;
+    if (rn.period > 0) {
+      // sweep sw rescales when it is a positive multiple of the period; the
+      // sweep before it records its end norm
+      if (sw > 0 && sw % rn.period == 0) {
+        a.rn_prev = rn.fwd + (size_t)(sw - 1) * B * nwg;
+        a.rn_prev_n = js ? js->nwg[0][sw - 1] : nwg;
+      }
+      if (sw + 1 < p.n_sweeps && (sw + 1) % rn.period == 0) a.rn_out = rn.fwd + (size_t)sw * B * nwg;
+    }
     if (tm) tm->before(0, s);
     e = launch_sweep(k_fused_fwd<R, KT>, js, 0, sw, nwg, B, 1 << (KT - kRegBits), lds, s, a);
     if (tm) tm->after(0, s);
@@ -188,7 +200,7 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *ma
 template <typename R, int KT>
 static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const double *G, void *mats,
                           void *psi, void *lam, double *part_grad, double *part_norm, hipStream_t s,
-                          SweepTimer *tm, const JitSweeps *js) {
+                          SweepTimer *tm, const JitSweeps *js, const Renorm &rn) {
   const int nwg = fused_wg_per_sample(d.n, KT);
   const size_t lds = bwd_lds<R, KT>(p.max_gslots);
   hipError_t e = allow_lds(k_fused_bwd<R, KT>, lds);
@@ -214,6 +226,12 @@ static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const do
     a.part_grad = part_grad;
     a.n_gslots = p.n_gslots > 0 ? p.n_gslots : 1;
     a.part_norm = part_norm;
+    if (rn.period > 0) {
+      a.rn_rec = rn.bwd;
+      a.rn_i = sw;
+      a.rn_period = rn.period;
+      a.rn_rows = nwg;
+    }
     if (tm) tm->before(1, s);
     e = launch_sweep(k_fused_bwd<R, KT>, js, 1, sw, nwg, B, 1 << (KT - kRegBits), lds, s, a);
     if (tm) tm->after(1, s);
@@ -252,10 +270,10 @@ template <typename R>
 hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                          const double *w, void *mats, double *coef, void *state, double *part_obs,
                          double *out, bool store_final, hipStream_t s, SweepTimer *tm,
-                         const JitSweeps *js) {
+                         const JitSweeps *js, const Renorm &rn) {
   hipError_t e = prep<R>(d, p, B, x, w, mats, coef, s);
   if (e != hipSuccess) return e;
-#define FWD_CALL(K) e = run_fwd<R, K>(d, p, B, mats, state, part_obs, out, store_final, s, tm, js)
+#define FWD_CALL(K) e = run_fwd<R, K>(d, p, B, mats, state, part_obs, out, store_final, s, tm, js, rn)
   QTM_KT_DISPATCH(p.kt, FWD_CALL)
 #undef FWD_CALL
   if (e != hipSuccess) return e;
@@ -269,14 +287,14 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
                           const double *w, const double *G, void *mats, double *coef, bool prepped,
                           void *state, void *lam, double *part_grad, double *part_norm,
                           double *gocc, double *gw, double *gx, hipStream_t s, SweepTimer *tm,
-                          const JitSweeps *js) {
+                          const JitSweeps *js, const Renorm &rn) {
   // prepped: mats and coef still hold what the forward computed from the
   // same angles for this plan and batch
   hipError_t e = prepped ? hipSuccess : prep<R>(d, p, B, x, w, mats, coef, s);
   if (e != hipSuccess) return e;
   // bra term of observables with X or Y factors, added in the first sweep
   if ((e = launch_pauli_seed<R>(d, B, state, lam, G, false, s)) != hipSuccess) return e;
-#define BWD_CALL(K) e = run_bwd<R, K>(d, p, B, G, mats, state, lam, part_grad, part_norm, s, tm, js)
+#define BWD_CALL(K) e = run_bwd<R, K>(d, p, B, G, mats, state, lam, part_grad, part_norm, s, tm, js, rn)
   QTM_KT_DISPATCH(p.kt, BWD_CALL)
 #undef BWD_CALL
   if (e != hipSuccess) return e;
@@ -293,17 +311,19 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
 
 template hipError_t fused_forward<float>(const DevCircuit &, const DevPlan &, int, const double *,
                                          const double *, void *, double *, void *, double *, double *,
-                                         bool, hipStream_t, SweepTimer *, const JitSweeps *);
+                                         bool, hipStream_t, SweepTimer *, const JitSweeps *, const Renorm &);
 template hipError_t fused_forward<double>(const DevCircuit &, const DevPlan &, int, const double *,
                                           const double *, void *, double *, void *, double *, double *,
-                                          bool, hipStream_t, SweepTimer *, const JitSweeps *);
+                                          bool, hipStream_t, SweepTimer *, const JitSweeps *, const Renorm &);
 template hipError_t fused_backward<float>(const DevCircuit &, const DevPlan &, int, const double *,
                                           const double *, const double *, void *, double *, bool,
                                           void *, void *, double *, double *, double *, double *,
-                                          double *, hipStream_t, SweepTimer *, const JitSweeps *);
+                                          double *, hipStream_t, SweepTimer *, const JitSweeps *,
+                                          const Renorm &);
 template hipError_t fused_backward<double>(const DevCircuit &, const DevPlan &, int, const double *,
                                            const double *, const double *, void *, double *, bool,
                                            void *, void *, double *, double *, double *, double *,
-                                           double *, hipStream_t, SweepTimer *, const JitSweeps *);
+                                           double *, hipStream_t, SweepTimer *, const JitSweeps *,
+                                           const Renorm &);
 
 }  // namespace qtm

@@ -31,6 +31,7 @@ struct JitSpec {
   int n_blocks = 0;   // fused blocks (matrix table stride per sample)
   bool seed_add = false;  // backward: lam holds a bra term to add in the first sweep
   int nwg_full = 0;   // row stride of the per-workgroup partial buffers
+  int renorm = 0;     // periodic renormalisation every `renorm` sweeps (0 = off; see FwdArgs / BwdArgs)
   std::vector<uint64_t> masks;
   const HostPlan *hp = nullptr;
 };

@@ -72,6 +72,13 @@ hipError_t launch_pauli_expval(const DevCircuit &d, int B, const void *state, do
 template <typename R>
 hipError_t launch_pauli_seed(const DevCircuit &d, int B, const void *psi, void *lam, const double *G,
                              bool accumulate, hipStream_t s);
+// Diagnostics: rows of the forward's observable partials on the per-gate
+// path; every sample's squared state norm from such partials ([B][rows][M + 1],
+// the norm in column M); the first non-finite angle source (see k_first_nonfinite).
+int plain_norm_rows(int n, int B);
+hipError_t launch_norms(const double *part, int B, int rows, int M, double *out, hipStream_t s);
+hipError_t launch_first_nonfinite(const double *x, int64_t nx, const double *w, int64_t nw,
+                                  unsigned long long *first, hipStream_t s);
 hipError_t launch_onehot(double *G, int B, int M, int m, hipStream_t s);
 hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, const double *x,
                               const double *w, int m, double *jw, double *jx, hipStream_t s);
@@ -90,6 +97,16 @@ int fused_wg_per_sample(int n, int kt);
 size_t fused_part_obs_doubles(const DevCircuit &d, const DevPlan &p, int B);
 size_t fused_part_grad_doubles(const DevCircuit &d, const DevPlan &p, int B);
 
+// Periodic renormalisation of the fused sweeps: every `period` sweeps (0 =
+// off) the loads are rescaled by norms recorded by the sweeps before (see
+// FwdArgs / BwdArgs).  fwd: [n_sweeps][B][workgroups per sample] doubles,
+// bwd: [n_sweeps][B][workgroups per sample][4] doubles (fused_rn_doubles).
+struct Renorm {
+  int period = 0;
+  double *fwd = nullptr, *bwd = nullptr;
+};
+size_t fused_rn_doubles(const DevCircuit &d, const DevPlan &p, int B);
+
 // js: kernels specialised for this plan (nullptr: the compiled sweep kernels).
 // The forward's prep also writes the derivative coefficients when coef is
 // not NULL; the backward skips its prep when `prepped` (mats and coef hold
@@ -98,12 +115,12 @@ template <typename R>
 hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                          const double *w, void *mats, double *coef, void *state, double *part_obs,
                          double *out, bool store_final, hipStream_t s, SweepTimer *tm,
-                         const JitSweeps *js);
+                         const JitSweeps *js, const Renorm &rn);
 template <typename R>
 hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                           const double *w, const double *G, void *mats, double *coef, bool prepped,
                           void *state, void *lam, double *part_grad, double *part_norm,
                           double *gocc, double *gw, double *gx, hipStream_t s, SweepTimer *tm,
-                          const JitSweeps *js);
+                          const JitSweeps *js, const Renorm &rn);
 
 }  // namespace qtm

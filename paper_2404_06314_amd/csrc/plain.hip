@@ -478,6 +478,49 @@ static int plain_nblk(int B, int64_t work) {
   return (int)(v < 1 ? 1 : v);
 }
 
+int plain_norm_rows(int n, int B) { return plain_nblk(B, (int64_t)1 << n); }
+
+// Squared norm of every sample's final state from the forward's partial sums
+// (column M of part [B][rows][M + 1]); one workgroup per sample, fixed order.
+__global__ void __launch_bounds__(256) k_norm_final(const double *__restrict__ part, int rows, int M,
+                                                    double *__restrict__ out) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  const double *p = part + (int64_t)b * rows * (M + 1);
+  double nrm = 0.0;
+  for (int k = threadIdx.x; k < rows; k += blockDim.x) nrm += p[(int64_t)k * (M + 1) + M];
+  nrm = block_sum(nrm, sh);
+  if (threadIdx.x == 0) out[b] = nrm;
+}
+
+hipError_t launch_norms(const double *part, int B, int rows, int M, double *out, hipStream_t s) {
+  k_norm_final<<<B, rows >= 256 ? 256u : 64u, 0, s>>>(part, rows, M, out);
+  return hipGetLastError();
+}
+
+// First non-finite entry of the angle sources: index into inputs (0 ..
+// nx - 1) or nx + index into weights; ~0 when every value is finite.
+__global__ void k_nonfinite_init(unsigned long long *first) { *first = ~0ull; }
+__global__ void k_first_nonfinite(const double *__restrict__ x, int64_t nx, const double *__restrict__ w,
+                                  int64_t nw, unsigned long long *__restrict__ first) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nx + nw;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = i < nx ? x[i] : w[i - nx];
+    if (!isfinite(v)) atomicMin(first, (unsigned long long)i);
+  }
+}
+
+hipError_t launch_first_nonfinite(const double *x, int64_t nx, const double *w, int64_t nw,
+                                  unsigned long long *first, hipStream_t s) {
+  k_nonfinite_init<<<1, 1, 0, s>>>(first);
+  const int64_t work = nx + nw;
+  if (work > 0) {
+    const int64_t blocks = std::min<int64_t>((work + kThreads - 1) / kThreads, 1024);
+    k_first_nonfinite<<<(unsigned)blocks, kThreads, 0, s>>>(x, nx, w, nw, first);
+  }
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t plain_forward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,
                          void *state, double *part, double *out, bool normalise, hipStream_t s) {

@@ -523,6 +523,12 @@ struct FwdArgs {
   double *part_obs;      // [B][gridDim.x][M+1]
   double *out;           // [B][M] <Z_m>, written directly by a specialised last
                          // sweep when one tile holds a whole sample
+  // periodic renormalisation (NULL: off for this sweep): the previous
+  // sweep's end-norm partials [B][rn_prev_n], whose sum rescales this
+  // sweep's loads to norm 1; this sweep's own partials [B][gridDim.x]
+  const double *rn_prev = nullptr;
+  int rn_prev_n = 0;
+  double *rn_out = nullptr;
 };
 
 
@@ -546,6 +552,59 @@ struct BwdArgs {
   double *part_grad;       // [B][n_gslots][gridDim.x][3]
   int n_gslots;
   double *part_norm;       // [B][gridDim.x]
+  // periodic renormalisation (rn_rec NULL: off): per sweep i, sample b and
+  // workgroup the partial norms of psi at load, psi at the end, lambda at
+  // load and lambda at the end, [S][B][rn_rows][4]; sweep rn_i rescales psi
+  // and lambda at load when rn_i is a positive multiple of rn_period, by the
+  // square roots of the products of their load / end ratios over the
+  // rn_period sweeps before it (each sweep's drift undone)
+  double *rn_rec = nullptr;
+  int rn_i = 0, rn_period = 0, rn_rows = 0;
 };
+
+// Sum over a workgroup of NT threads (a power of two) in FP64, in a fixed
+// order (wave sums, then the waves in order); every thread gets it.  sh: NW
+// doubles of LDS.  Contains barriers: every thread of the workgroup calls it.
+template <int NT>
+__device__ __forceinline__ double wg_sum_d(double v, double *sh) {
+  constexpr int NW = (NT + 63) / 64, WS = NT < 64 ? NT : 64;
+  v = wave_sum_w<WS>(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < NW; ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+// Load / end norm ratios of psi and lambda in backward sweep j (see
+// BwdArgs), its norms summed over the `rows` workgroup partials of sample b,
+// multiplied into rp and rl.  sh: NW doubles of LDS; every thread calls it.
+template <int NT>
+__device__ __forceinline__ void rn_bwd_ratio(const double *__restrict__ rec, int j, int rows, int row_stride,
+                                             int B, int b, double *sh, double &rp, double &rl) {
+  const double *r = rec + ((int64_t)j * B + b) * row_stride * 4;
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < rows; k += NT)
+    for (int c = 0; c < 4; ++c) q[c] += r[4 * k + c];
+  for (int c = 0; c < 4; ++c) q[c] = wg_sum_d<NT>(q[c], sh);
+  // (a state that is exactly 0, e.g. lambda for G = 0, keeps its scale)
+  rp *= q[1] > 0.0 ? q[0] / q[1] : 1.0;
+  rl *= q[3] > 0.0 ? q[2] / q[3] : 1.0;
+}
+
+// Scales of a backward sweep that renormalises (see BwdArgs): psi and
+// lambda each by sqrt(prod over the previous `period` sweeps of load / end
+// norm), the norms summed over `rows` workgroup partials of sample b.
+// Every thread gets them; sh: NW doubles of LDS.
+template <int NT>
+__device__ __forceinline__ void rn_bwd_scales(const double *__restrict__ rec, int i, int period, int rows,
+                                              int B, int b, double *sh, double &sp, double &sl) {
+  double rp = 1.0, rl = 1.0;
+  for (int j = i - period; j < i; ++j) rn_bwd_ratio<NT>(rec, j, rows, rows, B, b, sh, rp, rl);
+  sp = sqrt(rp);
+  sl = sqrt(rl);
+}
 
 }  // namespace qtm

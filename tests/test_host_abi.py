@@ -84,6 +84,48 @@ def test_state_bytes_and_options(qtm):
         c.set_option(99, 1)
     c.set_option(qtm.QTM_OPT_TILE_QUBITS, 10)
     c.set_path(qtm.QTM_PATH_PLAIN)
+    # renormalisation period: 0 (off) .. 1024
+    for bad in (-1, 1025):
+        with pytest.raises(qtm.QtmError):
+            c.set_option(qtm.QTM_OPT_RENORM, bad)
+    c.set_option(qtm.QTM_OPT_RENORM, 3)
+    c.set_option(qtm.QTM_OPT_RENORM, 0)
+
+
+def test_dense_blocks_option_checks_the_circuit_form(qtm):
+    """QTM_OPT_DENSE_BLOCKS is accepted for layered RX / RY / RZ / CZ-chain
+    circuits of 12, 16, ... qubits only (host check, no device)."""
+    qtm.Circuit.from_workload(W.layered_circuit(12, 2, "ladder")).set_option(qtm.QTM_OPT_DENSE_BLOCKS, 1)
+    qtm.Circuit.from_workload(W.config_workload("c3").circuit).set_option(qtm.QTM_OPT_DENSE_BLOCKS, 1)
+    for circ in (W.layered_circuit(12, 2, "ring"), W.layered_circuit(10, 2, "ladder"),
+                 W.layered_circuit(8, 2, "ladder"), W.config_workload("c2").circuit):
+        c = qtm.Circuit.from_workload(circ)
+        with pytest.raises(qtm.QtmError) as e:
+            c.set_option(qtm.QTM_OPT_DENSE_BLOCKS, 1)
+        assert e.value.code == -2
+        c.set_option(qtm.QTM_OPT_DENSE_BLOCKS, 0)
+
+
+def test_renormalising_sweeps_compile_without_a_device(qtm):
+    """With QTM_OPT_RENORM the specialised kernels are generated per period
+    (a kernel-name suffix): the sweeps that rescale read the norm records of
+    the sweeps before them, the sweeps before a rescaling one write theirs."""
+    c = qtm.Circuit.from_workload(W.layered_circuit(14, 8, "ring"))
+    c.set_option(qtm.QTM_OPT_TILE_QUBITS, 10)
+    S = len(c.plan("c64")["sweeps"])
+    assert S >= 4
+    c.set_option(qtm.QTM_OPT_RENORM, 2)
+    for s in range(S):
+        f = c.jit_source("c64", 0, s)
+        assert "qtm_jit_fwd_t10l5_rn" in f
+        assert ("a.rn_prev" in f) == (s > 0 and s % 2 == 0), s
+        assert ("a.rn_out" in f) == (s + 1 < S and (s + 1) % 2 == 0), s
+        bw = c.jit_source("c64", 1, s)
+        assert ("rn_bwd_ratio" in bw) == (s > 0 and s % 2 == 0), s
+        assert ("a.rn_rec +" in bw) == (s < S - 1), s
+    c.jit_compile("c64")
+    c.set_option(qtm.QTM_OPT_RENORM, 0)
+    assert "rn_" not in c.jit_source("c64", 0, 2)
 
 
 def test_null_pointer_errors_do_not_touch_the_gpu(qtm):
@@ -96,6 +138,11 @@ def test_null_pointer_errors_do_not_touch_the_gpu(qtm):
     assert rc == qtm._lib.QTM_ERR_INVALID_ARG
     rc = lib.qtm_forward(c.handle, 0, 0, None, None, None, None, None)
     assert rc == qtm._lib.QTM_ERR_INVALID_ARG
+    # norms: NULL output, then no forward has run on the handle
+    assert lib.qtm_forward_norms(c.handle, 2, None, None) == qtm._lib.QTM_ERR_INVALID_ARG
+    assert lib.qtm_forward_norms(c.handle, 2, ctypes.c_void_p(8), None) == qtm._lib.QTM_ERR_STATE
+    c.set_option(qtm.QTM_OPT_CHECK_ANGLES, 1)
+    c.set_option(qtm.QTM_OPT_CHECK_ANGLES, 0)
 
 
 def _plan_gate_order(plan):
@@ -176,15 +223,17 @@ def test_specialised_kernels_compile_without_a_device(qtm):
 
 def test_last_forward_sweep_writes_expectations_only_for_single_tile_samples(qtm):
     """With one tile per sample the last specialised forward sweep divides by
-    the norm and writes <Z_m>; with several it leaves per-workgroup partial
-    rows for the reduction kernel (the n = 20 benchmark circuit)."""
+    the norm and writes <Z_m> (and the norm into its partial row, for the
+    norm diagnostics); with several it leaves per-workgroup partial rows of
+    every sum for the reduction kernel (the n = 20 benchmark circuit)."""
     for n, tile, direct in ((8, 8, True), (12, 12, True), (12, 10, False), (20, 12, False)):
         c = qtm.Circuit.from_workload(W.layered_circuit(n, 2, "ladder"))
         c.set_option(qtm.QTM_OPT_TILE_QUBITS, tile)
         last = len(c.plan("c64")["sweeps"]) - 1
         src = c.jit_source("c64", 0, last)
         assert ("a.out[" in src) == direct, (n, tile)
-        assert ("a.part_obs[" in src) == (not direct), (n, tile)
+        assert "a.part_obs[" in src, (n, tile)
+        assert ("else a.part_obs[" in src) == direct, (n, tile)
         # earlier sweeps never write observables
         if last > 0:
             assert "a.out[" not in c.jit_source("c64", 0, 0)
