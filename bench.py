@@ -22,6 +22,8 @@ sys.path.insert(0, ROOT)
 METRIC = "circuit evals/s (fwd+adjoint grad) n=20 depth 8 batch 64; % peak HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3
+# FP32 vector FMA peak without packed math: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+VALU_F32_PEAK_TFLOPS = 78.6
 
 
 def log(*a):
@@ -36,6 +38,7 @@ KERNEL_SOURCES = {
     "qtm_jit": ["jit.cpp"] + _COMMON,
     "k_fused": ["fused.hip", "sweep_fwd.inc", "sweep_bwd.inc"] + _COMMON,
     "k_multi": ["multi.hip", "schedule.cpp", "sweep_fwd.inc", "sweep_bwd.inc"] + _COMMON,
+    "k_k9": ["k9.hip", "sweep_ops.h", "device_common.h"],
 }
 
 
@@ -146,6 +149,44 @@ def live_work(plan, n: int, kind: int, jit: bool):
     return passes, units
 
 
+def grad_units(plan, n: int, jit: bool) -> float:
+    """Parameterised blocks whose transition-matrix sums the backward takes
+    (op codes 1 and 4 with a gradient slot), in units of a block over the
+    whole register, counting only the tiles the kernels run (as live_work)."""
+    code = plan["code"]
+    offs = plan["sweep_off_bwd"]
+    S = len(offs)
+    full = (1 << n) - 1
+    ex = plan["excited"]
+    units = 0.0
+    for i, off in enumerate(offs):
+        s = S - 1 - i  # forward index
+        g = 0
+        for st in range(code[off]):
+            so = code[off + 90 + st]
+            for o in range(code[so]):
+                c, gs = code[so + 40 + 4 * o], code[so + 40 + 4 * o + 3]
+                g += 1 if c in (1, 4) and gs >= 0 else 0
+        tile = sum(1 << q for q in plan["sweeps"][s]["tile"])
+        dout = full & ~ex[s]
+        skip = 0 if (s == S - 1 or not jit) else dout & ~tile
+        units += g * 2.0 ** -bin(skip).count("1")
+    return units
+
+
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
 def cpu_baseline(wl, threads: int, samples: int):
     import numpy as np
     import oracle
@@ -158,6 +199,18 @@ def cpu_baseline(wl, threads: int, samples: int):
     return {"value": s / dt, "unit": "circuit evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{s} of {wl.batch} samples of the same workload, forward + adjoint VJP "
                       f"in complex128, samples split over {threads} threads; {dt:.1f} s"}
+
+
+def cpu_baselines(wl, threads: int, samples: int, samples_1: int):
+    """The oracle on all `threads` cores (the reported value) and on one core,
+    with the host's CPU model and core count."""
+    allc = cpu_baseline(wl, threads, samples)
+    one = cpu_baseline(wl, 1, samples_1)
+    model, nproc = cpu_info()
+    allc["single_core"] = {"value": one["value"], "cores": 1, "sample": one["sample"]}
+    allc["cpu_model"] = model
+    allc["nproc"] = nproc
+    return allc
 
 
 def main():
@@ -176,6 +229,11 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="1: run the autotuner (tile size, low qubits, generic/specialised) first; "
                          "its time is not part of the timed steps")
+    ap.add_argument("--dense", type=int, default=0, choices=[0, 1],
+                    help="1: complex64 forwards with the shared-weight dense blocks on the matrix cores "
+                         "(QTM_OPT_DENSE_BLOCKS; layered CZ-chain circuits); implies --autotune 0")
+    ap.add_argument("--renorm", type=int, default=0,
+                    help="periodic renormalisation every R sweeps (QTM_OPT_RENORM); implies --autotune 0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--cpu-samples", type=int, default=0)
@@ -224,6 +282,10 @@ def main():
         c.set_option(q.QTM_OPT_LOW_QUBITS, args.klo)
     if args.jit and args.path == "fused":
         c.set_option(q.QTM_OPT_JIT, 1)
+    if args.dense or args.renorm:
+        args.autotune = 0
+        c.set_option(q.QTM_OPT_DENSE_BLOCKS, args.dense)
+        c.set_option(q.QTM_OPT_RENORM, args.renorm)
     tuned = None
     if args.autotune and args.path == "fused":
         t0 = time.perf_counter()
@@ -283,21 +345,31 @@ def main():
         kind = 1 if res[1][0] >= res[0][0] else 0
         ms_tot, launches = res[kind]
         use_jit = args.jit and args.path == "fused"
-        passes, units = live_work(plan, circ.n, kind, use_jit)
-        bytes_per_step = B * (1 << circ.n) * elem * passes
-        per_launch_bytes = bytes_per_step / S
+        dense_fwd = kind == 0 and args.dense and prec == "c64"
         avg_s = ms_tot / launches / 1e3
+        if dense_fwd:
+            # one pass per (layer, block of 4 qubits): the state read and
+            # written once; a dense 32 x 32 real operator on every column of
+            # 16 amplitudes (2048 flop)
+            per_launch_bytes = B * (1 << circ.n) * elem * 2
+            per_launch_flop = B * (1 << (circ.n - 4)) * 2048
+            units = 0.0
+        else:
+            passes, units = live_work(plan, circ.n, kind, use_jit)
+            bytes_per_step = B * (1 << circ.n) * elem * passes
+            per_launch_bytes = bytes_per_step / S
+            # algorithmic matrix-core work: every fused block is a 2x2 complex
+            # gate on each of the B * 2^(n-1) pairs = 16 real MACs (32 flop) per
+            # pair, applied to psi in the forward and un-applied on psi and
+            # lambda in the backward (except each qubit's last block there),
+            # over the tiles the kernels run (live_work)
+            flop_step = int(B * (1 << (circ.n - 1)) * units * 32 * (2 if kind == 1 else 1))
+            per_launch_flop = flop_step / S
         gbs = per_launch_bytes / avg_s / 1e9
-        # algorithmic matrix-core work: every fused block is a 2x2 complex
-        # gate on each of the B * 2^(n-1) pairs = 16 real MACs (32 flop) per
-        # pair, applied to psi in the forward and un-applied on psi and
-        # lambda in the backward (except each qubit's last block there),
-        # over the tiles the kernels run (live_work)
-        flop_step = int(B * (1 << (circ.n - 1)) * units * 32 * (2 if kind == 1 else 1))
-        per_launch_flop = flop_step / S
         tfs = per_launch_flop / avg_s / 1e12
-        sfx = f"_t{plan_kt}l{plan_klo}" + ("_c128" if prec == "c128" else "")
-        name = (("qtm_jit_bwd" if kind == 1 else "qtm_jit_fwd") + sfx) if use_jit else \
+        sfx = f"_t{plan_kt}l{plan_klo}" + ("_c128" if prec == "c128" else "") + ("_rn" if args.renorm else "")
+        name = "k_k9_pass" if dense_fwd else \
+            (("qtm_jit_bwd" if kind == 1 else "qtm_jit_fwd") + sfx) if use_jit else \
             ("k_fused_bwd" if kind == 1 else "k_fused_fwd")
         if use_jit:
             for d in (0, 1):
@@ -307,25 +379,35 @@ def main():
             f"and {per_launch_flop / 1e9:.1f} GFLOP per launch -> {gbs:.1f} GB/s, {tfs:.2f} TFLOP/s; "
             f"fwd sweeps {res[0][0] / args.steps:.3f} ms/step, "
             f"bwd sweeps {res[1][0] / args.steps:.3f} ms/step ({S} sweeps)")
-        hbm = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": round(gbs / HBM_PEAK_GBS, 4)}
-        mfma = {"achieved": round(tfs, 3), "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tfs / MFMA_F32_PEAK_TFLOPS, 4)}
-        use_mfma = prec == "c64" and mfma["frac"] > hbm["frac"]
-        main, other = (mfma, hbm) if use_mfma else (hbm, mfma)
-        roof = {"bound": "mfma" if use_mfma else "hbm", **main,
+        # serial issue floor of the sweeps: matrix-core products at the FP32
+        # matrix peak plus, in the backward, the transition-matrix FMAs (12
+        # per amplitude pair and parameterised block, 24 flop) at the FP32
+        # vector peak without packed math; gfx950 issues the two one after the
+        # other within a wave
+        gflop_step = B * (1 << (circ.n - 1)) * grad_units(plan, circ.n, use_jit) * 24 \
+            if kind == 1 else 0.0
+        floor_s = per_launch_flop / (MFMA_F32_PEAK_TFLOPS * 1e12) + \
+            gflop_step / S / (VALU_F32_PEAK_TFLOPS * 1e12)
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "traffic": recorded_traffic(name, W.WORKLOAD_NAMES[args.config]),
                 "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
-                "bytes_per_launch": int(per_launch_bytes), "flop_per_launch": int(per_launch_flop),
-                "sweeps": S, ("hbm" if use_mfma else "mfma"): other}
+                "bytes_per_launch": int(per_launch_bytes), "sweeps": S,
+                "mfma": {"achieved": round(tfs, 3), "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tfs / MFMA_F32_PEAK_TFLOPS, 4), "flop_per_launch": int(per_launch_flop)},
+                "issue": {"floor_us": round(floor_s * 1e6, 2), "frac": round(floor_s / avg_s, 4),
+                          "valu_flop_per_launch": int(gflop_step / S)}}
+        log(f"{name}: HBM {gbs / HBM_PEAK_GBS:.3f} of peak, matrix cores {tfs / MFMA_F32_PEAK_TFLOPS:.3f}, "
+            f"serial issue floor {floor_s * 1e6:.1f} us ({floor_s / avg_s:.3f} of the launch)")
 
     cpu = None
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         samples = args.cpu_samples or 3 * threads
-        log(f"cpu baseline: oracle on {samples} samples with {threads} threads ...")
-        cpu = cpu_baseline(wl, threads, samples)
-        log(f"cpu baseline: {cpu['value']:.3f} evals/s")
+        log(f"cpu baseline: oracle on {samples} samples with {threads} threads, then on one core ...")
+        cpu = cpu_baselines(wl, threads, samples, samples_1=max(1, min(3, samples)))
+        log(f"cpu baseline: {cpu['value']:.3f} evals/s on {threads} threads, "
+            f"{cpu['single_core']['value']:.3f} on one core ({cpu['cpu_model']}, nproc {cpu['nproc']})")
 
     out = {
         "metric": METRIC if args.config == "c3" else f"circuit evals/s (fwd+adjoint grad) {circ.name}",
@@ -346,7 +428,8 @@ def main():
                    "observables": circ.n_obs, "precision": prec, "path": args.path,
                    "specialised_kernels": bool(args.jit and args.path == "fused"),
                    "tile_qubits": plan_kt, "low_qubits": plan_klo,
-                   "autotuned": tuned is not None},
+                   "autotuned": tuned is not None, "dense_blocks": bool(args.dense),
+                   "renorm_period": args.renorm},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
