@@ -180,6 +180,28 @@ int qtm_state_bytes(qtm_circuit_t c, int32_t batch, int32_t precision, size_t *b
 int qtm_forward(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
                 const double *weights, double *expvals, void *state, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * forward pass as qtm_forward, with every workspace buffer (gate matrices,
+ * derivative coefficients, partial sums) carved from a scratch array of
+ * 16 MiB that the library's code object holds on each GPU until the process
+ * ends.  It calls no hipMalloc, hipFree or other allocating routine.
+ *   state    dev, qtm_state_bytes(); required (receives the final states).
+ *   others   as qtm_forward.
+ * Preconditions: one qtm_forward (or qtm_backward / qtm_autotune) with the
+ * same precision and tile options has run on this device, so that the
+ * circuit's constant tables and plan are resident (else QTM_ERR_STATE).  With
+ * QTM_OPT_JIT the specialised kernels are used if that call loaded them,
+ * otherwise the compiled ones.  A batch whose buffers exceed the scratch
+ * (error message gives both sizes) returns QTM_ERR_WORKSPACE.
+ * Every call on a GPU shares that GPU's scratch array, which keeps the last
+ * call's contents: calls that overlap on one GPU (other streams, other
+ * threads, other handles) race.  A state buffer filled here is not accepted
+ * by qtm_backward (QTM_ERR_STATE), and qtm_forward_norms does not report
+ * this pass. */
+int qtm_forward_noalloc(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
+                        const double *weights, double *expvals, void *state, void *stream);
+
 /* Adjoint VJP (Sec. II-A, reverse gradient).
  *   grad_expvals  dev [batch][n_obs] float64: G = dL/d<O>
  *   state         dev buffer written by qtm_forward with the same circuit, batch,

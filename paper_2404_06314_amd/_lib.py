@@ -41,6 +41,7 @@ SIGNATURES = {
     "qtm_set_option": (ctypes.c_int, [_P, _I32, _I64]),
     "qtm_state_bytes": (ctypes.c_int, [_P, _I32, _I32, _P]),
     "qtm_forward": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P]),
+    "qtm_forward_noalloc": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P]),
     "qtm_backward": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "qtm_multi_create": (ctypes.c_int, [_P, _I32, _P]),
     "qtm_multi_destroy": (ctypes.c_int, [_P]),

@@ -384,7 +384,8 @@ int check_common(qtm_circuit_t c, int32_t batch, int32_t precision) {
 
 size_t elem_bytes(int precision) { return precision == QTM_C128 ? 16 : 8; }
 
-// Device buffers of one forward pass (the library's workspace).
+// Device buffers of one forward pass: the library's workspace (qtm_forward)
+// or the no-allocation scratch array (qtm_forward_noalloc).
 struct FwdBufs {
   void *mats = nullptr;         // fused: [B][n_blocks] gate matrices
   double *coef = nullptr;       // fused: [B][n_occ][3] derivative coefficients
@@ -616,6 +617,31 @@ int run_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
   return QTM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the no-allocation forward: one array per GPU, in the library's
+// code object, held until the process ends.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device (with that device current).
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(QTM_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(QTM_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return QTM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -738,6 +764,79 @@ int qtm_forward(qtm_circuit_t c, int32_t batch, int32_t precision, const double 
     std::lock_guard<std::mutex> g(g_reg_mu);
     g_registry[state] = StateTag{c->id, batch, precision, c->prep_gen};
   }
+  return QTM_OK;
+}
+
+int qtm_forward_noalloc(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
+                        const double *weights, double *expvals, void *state, void *stream) {
+  int rc = check_common(c, batch, precision);
+  if (rc) return rc;
+  if (!expvals || !state) return fail(QTM_ERR_INVALID_ARG, "expvals and state are required");
+  if (c->desc.n_inputs > 0 && !inputs) return fail(QTM_ERR_INVALID_ARG, "inputs is NULL");
+  if (c->desc.n_weights > 0 && !weights) return fail(QTM_ERR_INVALID_ARG, "weights is NULL");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (c->k9 && precision == QTM_C64 && use_fused(c))
+    return fail(QTM_ERR_UNSUPPORTED, "qtm_forward_noalloc does not run the dense-block forward");
+  // the circuit's constant tables and plan must already be on this device
+  if (!c->uploaded || c->device != dev)
+    return fail(QTM_ERR_STATE, "the circuit's tables are not on this device: call qtm_forward once first");
+  const DevCircuit &d = c->dev;
+  const DevPlan *p = nullptr;
+  const JitSweeps *js = nullptr;
+  if (use_fused(c)) {
+    // the plan key as get_host_plan forms it; nothing is planned here
+    const int kt = default_kt(c, precision);
+    const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
+    auto it = c->plans.find(std::make_pair(kt, klo));
+    if (it == c->plans.end())
+      return fail(QTM_ERR_STATE, "the circuit's plan for this tile configuration is not on the device: "
+                                 "call qtm_forward once first");
+    p = &it->second;
+    // specialised kernels only if already compiled and loaded here; else the compiled ones
+    if (c->jit) {
+      auto jt = c->jits.find(std::make_tuple(kt, klo, (int)precision, c->renorm));
+      if (jt != c->jits.end() && jt->second->loaded && jt->second->device == dev) js = jt->second.get();
+    }
+  }
+  const FwdSizes z = fwd_sizes(d, p, batch, c->renorm);
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t need =
+      up(z.mats) + up(z.coef) + up(z.part_obs) + up(z.cs) + up(z.part) + up(z.part_pauli) + up(z.rn);
+  if (need > kScratchBytes)
+    return fail(QTM_ERR_WORKSPACE, "qtm_forward_noalloc needs " + std::to_string(need) +
+                                       " bytes of scratch for this batch; the maximum is " +
+                                       std::to_string(kScratchBytes));
+  void *base = nullptr;
+  if ((rc = scratch_address(dev, &base))) return rc;
+  unsigned char *q = (unsigned char *)base;
+  FwdBufs b;
+  b.mats = z.mats ? q : nullptr;
+  q += up(z.mats);
+  b.coef = z.coef ? (double *)q : nullptr;
+  q += up(z.coef);
+  b.part_obs = z.part_obs ? (double *)q : nullptr;
+  q += up(z.part_obs);
+  b.cs = z.cs ? (double2 *)q : nullptr;
+  q += up(z.cs);
+  b.part = z.part ? (double *)q : nullptr;
+  q += up(z.part);
+  b.part_pauli = z.part_pauli ? (double *)q : nullptr;
+  q += up(z.part_pauli);
+  b.rn = z.rn ? (double *)q : nullptr;
+  // the library's matrices (a backward may reuse them) and the norm partials
+  // are not this pass's; a state tag of this buffer no longer describes it
+  c->prep_gen++;
+  c->prep_plan = nullptr;
+  c->norm_part = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_reg_mu);
+    g_registry.erase(state);
+  }
+  e = launch_forward(c, p, js, batch, precision, inputs, weights, expvals, state, true, b, nullptr,
+                     (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "no-allocation forward launch");
   return QTM_OK;
 }
 

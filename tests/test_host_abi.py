@@ -138,6 +138,9 @@ def test_null_pointer_errors_do_not_touch_the_gpu(qtm):
     assert rc == qtm._lib.QTM_ERR_INVALID_ARG
     rc = lib.qtm_forward(c.handle, 0, 0, None, None, None, None, None)
     assert rc == qtm._lib.QTM_ERR_INVALID_ARG
+    # the no-allocation forward needs expvals and state
+    rc = lib.qtm_forward_noalloc(c.handle, 2, 0, None, None, None, None, None)
+    assert rc == qtm._lib.QTM_ERR_INVALID_ARG
     # norms: NULL output, then no forward has run on the handle
     assert lib.qtm_forward_norms(c.handle, 2, None, None) == qtm._lib.QTM_ERR_INVALID_ARG
     assert lib.qtm_forward_norms(c.handle, 2, ctypes.c_void_p(8), None) == qtm._lib.QTM_ERR_STATE
