@@ -232,6 +232,9 @@ def main():
     ap.add_argument("--dense", type=int, default=0, choices=[0, 1],
                     help="1: complex64 forwards with the shared-weight dense blocks on the matrix cores "
                          "(QTM_OPT_DENSE_BLOCKS; layered CZ-chain circuits); implies --autotune 0")
+    ap.add_argument("--greedy-plan", type=int, default=0, choices=[0, 1],
+                    help="1: the greedy sweep plan for the specialised kernels (QTM_OPT_GREEDY_PLAN) "
+                         "instead of the plan chosen for skipping zero tiles; implies --autotune 0")
     ap.add_argument("--renorm", type=int, default=0,
                     help="periodic renormalisation every R sweeps (QTM_OPT_RENORM); implies --autotune 0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -282,6 +285,9 @@ def main():
         c.set_option(q.QTM_OPT_LOW_QUBITS, args.klo)
     if args.jit and args.path == "fused":
         c.set_option(q.QTM_OPT_JIT, 1)
+    if args.greedy_plan:
+        args.autotune = 0
+        c.set_option(q.QTM_OPT_GREEDY_PLAN, 1)
     if args.dense or args.renorm:
         args.autotune = 0
         c.set_option(q.QTM_OPT_DENSE_BLOCKS, args.dense)
@@ -291,8 +297,9 @@ def main():
         t0 = time.perf_counter()
         tuned = c.autotune(wl.batch, prec, cache=False)
         args.jit = tuned["jit"]
+        args.greedy_plan = tuned.get("greedy", 0)
         log(f"autotune ({time.perf_counter() - t0:.1f} s): tile {tuned['tile']} klo {tuned['klo']} "
-            f"jit {tuned['jit']} ({len(tuned['candidates'])} candidates)")
+            f"jit {tuned['jit']} greedy plan {args.greedy_plan} ({len(tuned['candidates'])} candidates)")
     dev = torch.device("cuda:0")
     x = torch.as_tensor(wl.inputs, device=dev)
     w = torch.as_tensor(wl.weights, device=dev)
@@ -428,6 +435,7 @@ def main():
                    "observables": circ.n_obs, "precision": prec, "path": args.path,
                    "specialised_kernels": bool(args.jit and args.path == "fused"),
                    "tile_qubits": plan_kt, "low_qubits": plan_klo,
+                   "sweep_plan": "greedy" if (args.greedy_plan or not args.jit) else "zero-skip",
                    "autotuned": tuned is not None, "dense_blocks": bool(args.dense),
                    "renorm_period": args.renorm},
         "roofline": roof,

@@ -109,7 +109,14 @@ enum {
                               RY(weight), RZ(weight) on every qubit in qubit order, then the open
                               CZ chain) of 12, 16, ... qubits with Z-string observables, else
                               QTM_ERR_UNSUPPORTED; the backward is unchanged (it prepares its own
-                              gate matrices).  0 (default): the fused sweeps. */
+                              gate matrices).  0 (default): the fused sweeps. */,
+  QTM_OPT_GREEDY_PLAN = 8  /* fused path, sweep planning.  0 (default): with QTM_OPT_JIT the sweeps
+                              are planned for the specialised kernels, which skip the tiles whose
+                              amplitudes are all zero (a qubit not yet acted on by a non-diagonal
+                              gate holds |0>): a search over tile sequences by an estimated cost
+                              that counts only the tiles that run; the generic kernels take the
+                              greedy plan.  1: the greedy plan (each sweep runs the most ops a
+                              tile allows) for both.  Results agree within rounding either way. */
 };
 
 /* One gate.  Rotations (RX, RY, RZ): q0 = qubit, src = QTM_SRC_INPUT or
@@ -300,8 +307,11 @@ int qtm_forward_norms(qtm_circuit_t c, int32_t batch, double *norms, void *strea
 int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *launches);
 
 /* Tune the fused path of c for (batch, precision) on the current device:
- * tile qubits, contiguous low qubits, and the compiled generic versus the
- * specialised sweep kernels (QTM_OPT_JIT).  Every candidate must reproduce
+ * tile qubits, contiguous low qubits, the compiled generic versus the
+ * specialised sweep kernels (QTM_OPT_JIT), for the fastest specialised
+ * configuration also the greedy sweep plan (QTM_OPT_GREEDY_PLAN), and for
+ * complex64 layered CZ-chain circuits the dense-block forward
+ * (QTM_OPT_DENSE_BLOCKS).  Every candidate must reproduce
  * the per-gate complex128 result on seeded synthetic inputs within the
  * precision's tolerances (<Z> 1e-5 absolute and gradients 1e-4 relative for
  * complex64; 1e-12 / 1e-10 for complex128) before it is timed; the fastest

@@ -15,7 +15,8 @@ from . import _lib
 from ._lib import (QTM_C64, QTM_C128, QTM_CNOT, QTM_CZ, QTM_PATH_AUTO, QTM_PATH_FUSED,
                    QTM_PATH_PLAIN, QTM_RX, QTM_RY, QTM_RZ, QTM_SRC_INPUT, QTM_SRC_NONE,
                    QTM_SRC_SCALED, QTM_SRC_WEIGHT, QTM_OPT_LOW_QUBITS, QTM_OPT_PATH, QTM_OPT_RENORM,
-                   QTM_OPT_TILE_QUBITS, QTM_OPT_TIMING, QTM_OPT_JIT, QTM_OPT_CHECK_ANGLES, QTM_OPT_DENSE_BLOCKS, QtmError)
+                   QTM_OPT_TILE_QUBITS, QTM_OPT_TIMING, QTM_OPT_JIT, QTM_OPT_CHECK_ANGLES, QTM_OPT_DENSE_BLOCKS,
+                   QTM_OPT_GREEDY_PLAN, QtmError)
 
 __all__ = ["Circuit", "Multi", "QtmError", "precision_code", "lib_path",
            "QTM_C64", "QTM_C128", "QTM_PATH_AUTO", "QTM_PATH_PLAIN", "QTM_PATH_FUSED"]
@@ -141,8 +142,9 @@ class Circuit:
         _lib.check(_lib.load().qtm_jit_compile(self._h, precision_code(precision)))
 
     def autotune(self, batch: int, precision=QTM_C64, cache: bool = True, stream=None) -> dict:
-        """Search tile size, contiguous low qubits and generic / specialised
-        sweep kernels for (batch, precision); installs the fastest candidate
+        """Search tile size, contiguous low qubits, generic / specialised
+        sweep kernels and the sweep plan of the specialised ones (zero-skip
+        or greedy) for (batch, precision); installs the fastest candidate
         that reproduces the complex128 per-gate result.  Returns the JSON
         report (candidates with timings and errors)."""
         lib = _lib.load()

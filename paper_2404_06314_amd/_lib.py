@@ -28,6 +28,7 @@ QTM_OPT_PATH, QTM_OPT_TILE_QUBITS, QTM_OPT_LOW_QUBITS, QTM_OPT_RENORM, QTM_OPT_T
 QTM_OPT_JIT = 5
 QTM_OPT_CHECK_ANGLES = 6
 QTM_OPT_DENSE_BLOCKS = 7
+QTM_OPT_GREEDY_PLAN = 8
 
 # every exported function of include/qtm.h: name -> (restype, argtypes)
 _P = ctypes.c_void_p

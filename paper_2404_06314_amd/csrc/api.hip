@@ -160,10 +160,13 @@ struct qtm_circuit_s {
   bool uploaded = false;
   DevCircuit dev;
   std::vector<void *> owned;
-  std::map<std::pair<int, int>, DevPlan> plans;
-  std::map<std::pair<int, int>, HostPlan> hplans;
+  // plans by (kt, klo, zero_skip): the specialised kernels skip all-zero
+  // tiles and take plans chosen for that (QTM_OPT_JIT), the compiled ones not
+  std::map<std::tuple<int, int, int>, DevPlan> plans;
+  std::map<std::tuple<int, int, int>, HostPlan> hplans;
   int jit = 0;  // QTM_OPT_JIT
-  std::map<std::tuple<int, int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision, renorm)
+  int greedy_plan = 0;  // QTM_OPT_GREEDY_PLAN
+  std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision, renorm, zero_skip)
   DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm, part_pauli;
   DevBuf jac_state, jac_G, jac_gw, jac_out, chk, rn;
   // shared-weight dense-block forward (QTM_OPT_DENSE_BLOCKS)
@@ -258,6 +261,10 @@ int ensure_device(qtm_circuit_t c) {
   return QTM_OK;
 }
 
+// Whether the fused plans of this handle are chosen for kernels that skip
+// all-zero tiles (the specialised ones), see QTM_OPT_GREEDY_PLAN.
+int zero_skip_plan(const qtm_circuit_s *c) { return c->jit && !c->greedy_plan ? 1 : 0; }
+
 int default_kt(const qtm_circuit_s *c, int precision) {
   int kt = c->tile_qubits > 0 ? c->tile_qubits : (precision == QTM_C128 ? 11 : 12);
   kt = std::min(kt, kMaxTileQubits);
@@ -271,11 +278,12 @@ int get_host_plan(qtm_circuit_t c, int precision, const HostPlan **out) {
     return fail(QTM_ERR_UNSUPPORTED, "controlled rotations run on the per-gate path only");
   const int kt = default_kt(c, precision);
   const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
-  auto key = std::make_pair(kt, klo);
+  const int zs = zero_skip_plan(c);
+  auto key = std::make_tuple(kt, klo, zs);
   auto it = c->hplans.find(key);
   if (it == c->hplans.end()) {
     HostPlan hp;
-    std::string why = build_host_plan(c->desc, kt, klo, hp);
+    std::string why = build_host_plan(c->desc, kt, klo, hp, zs != 0);
     if (!why.empty()) return fail(QTM_ERR_UNSUPPORTED, "internal planner error: " + why);
     it = c->hplans.emplace(key, std::move(hp)).first;
   }
@@ -288,7 +296,7 @@ int get_plan(qtm_circuit_t c, int precision, DevPlan **out) {
   int rc = get_host_plan(c, precision, &hpp);
   if (rc) return rc;
   const HostPlan &hp = *hpp;
-  auto key = std::make_pair(hp.kt, hp.klo);
+  auto key = std::make_tuple(hp.kt, hp.klo, hp.zero_skip);
   auto it = c->plans.find(key);
   if (it != c->plans.end()) {
     *out = &it->second;
@@ -346,7 +354,7 @@ int get_jit(qtm_circuit_t c, int precision, bool load, const JitSweeps **out) {
   const HostPlan *hp = nullptr;
   int rc = get_host_plan(c, precision, &hp);
   if (rc) return rc;
-  const auto key = std::make_tuple(hp->kt, hp->klo, precision, c->renorm);
+  const auto key = std::make_tuple(hp->kt, hp->klo, precision, c->renorm, hp->zero_skip);
   auto it = c->jits.find(key);
   if (it == c->jits.end()) {
     std::unique_ptr<JitSweeps> js(new JitSweeps());
@@ -716,6 +724,9 @@ int qtm_set_option(qtm_circuit_t c, int32_t option, int64_t value) {
     case QTM_OPT_JIT:
       c->jit = value ? 1 : 0;
       return QTM_OK;
+    case QTM_OPT_GREEDY_PLAN:
+      c->greedy_plan = value ? 1 : 0;
+      return QTM_OK;
     case QTM_OPT_CHECK_ANGLES:
       c->check_angles = value ? 1 : 0;
       return QTM_OK;
@@ -789,14 +800,15 @@ int qtm_forward_noalloc(qtm_circuit_t c, int32_t batch, int32_t precision, const
     // the plan key as get_host_plan forms it; nothing is planned here
     const int kt = default_kt(c, precision);
     const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
-    auto it = c->plans.find(std::make_pair(kt, klo));
+    const int zs = zero_skip_plan(c);
+    auto it = c->plans.find(std::make_tuple(kt, klo, zs));
     if (it == c->plans.end())
       return fail(QTM_ERR_STATE, "the circuit's plan for this tile configuration is not on the device: "
                                  "call qtm_forward once first");
     p = &it->second;
     // specialised kernels only if already compiled and loaded here; else the compiled ones
     if (c->jit) {
-      auto jt = c->jits.find(std::make_tuple(kt, klo, (int)precision, c->renorm));
+      auto jt = c->jits.find(std::make_tuple(kt, klo, (int)precision, c->renorm, zs));
       if (jt != c->jits.end() && jt->second->loaded && jt->second->device == dev) js = jt->second.get();
     }
   }
@@ -961,7 +973,7 @@ int qtm_plan_json(qtm_circuit_t c, int32_t precision, char *buf, size_t len, siz
     return fail(QTM_ERR_UNSUPPORTED, "controlled rotations run on the per-gate path only");
   const int kt = default_kt(c, precision);
   const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
-  Plan plan = make_plan(c->desc, kt, klo);
+  Plan plan = make_plan(c->desc, kt, klo, zero_skip_plan(c) != 0);
   std::string why = check_plan(c->desc, plan);
   std::string js = plan_json(c->desc, plan);
   if (!why.empty()) {
@@ -1030,7 +1042,7 @@ int qtm_jit_info(qtm_circuit_t c, int32_t precision, int32_t dir, int32_t sweep,
   const HostPlan *hp = nullptr;
   int rc = get_host_plan(c, precision, &hp);
   if (rc) return rc;
-  auto it = c->jits.find(std::make_tuple(hp->kt, hp->klo, (int)precision, c->renorm));
+  auto it = c->jits.find(std::make_tuple(hp->kt, hp->klo, (int)precision, c->renorm, hp->zero_skip));
   if (it == c->jits.end() || !it->second->loaded) return fail(QTM_ERR_INVALID_ARG, "specialised kernels not loaded");
   if (sweep < 0 || sweep >= (int)it->second->k[dir].size()) return fail(QTM_ERR_INVALID_ARG, "sweep out of range");
   *vgprs = it->second->k[dir][sweep].vgprs;

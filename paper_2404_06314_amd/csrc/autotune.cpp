@@ -1,6 +1,7 @@
 // Autotuner for the fused path: searches the tile size (kt), the number of
 // contiguous low qubits in a tile (klo), generic vs specialised sweep
-// kernels and, for complex64 layered CZ-chain circuits, the shared-weight
+// kernels (with the plan chosen for skipping zero tiles or the greedy plan)
+// and, for complex64 layered CZ-chain circuits, the shared-weight
 // dense-block forward (QTM_OPT_DENSE_BLOCKS) for one (circuit, batch,
 // precision) on the current device.
 //
@@ -36,7 +37,7 @@ namespace qtm {
 namespace {
 
 struct Cand {
-  int kt, klo, jit, dense = 0;
+  int kt, klo, jit, dense = 0, greedy = 0;
   bool ok = false;
   double ms = 0.0;
   double err_z = 0.0, err_g = 0.0;
@@ -64,7 +65,7 @@ std::string cache_path() {
 }
 
 // The cache is a flat JSON array of {"key": ..., "tile": .., "klo": .., "jit": .., "ms": ..}.
-bool cache_lookup(const std::string &key, int &kt, int &klo, int &jit, int &dense) {
+bool cache_lookup(const std::string &key, int &kt, int &klo, int &jit, int &dense, int &greedy) {
   std::ifstream f(cache_path());
   if (!f) return false;
   std::stringstream ss;
@@ -82,10 +83,11 @@ bool cache_lookup(const std::string &key, int &kt, int &klo, int &jit, int &dens
     return true;
   };
   if (!num("dense", dense)) dense = 0;
+  if (!num("greedy", greedy)) greedy = 0;
   return num("tile", kt) && num("klo", klo) && num("jit", jit);
 }
 
-void cache_store(const std::string &key, int kt, int klo, int jit, int dense, double ms) {
+void cache_store(const std::string &key, int kt, int klo, int jit, int dense, int greedy, double ms) {
   static std::mutex mu;
   std::lock_guard<std::mutex> g(mu);
   const std::string path = cache_path();
@@ -108,8 +110,10 @@ void cache_store(const std::string &key, int kt, int klo, int jit, int dense, do
     i = j + 1;
   }
   char buf[512];
-  snprintf(buf, sizeof buf, "{\"key\": \"%s\", \"tile\": %d, \"klo\": %d, \"jit\": %d, \"dense\": %d, \"ms\": %.4f}",
-           key.c_str(), kt, klo, jit, dense, ms);
+  snprintf(buf, sizeof buf,
+           "{\"key\": \"%s\", \"tile\": %d, \"klo\": %d, \"jit\": %d, \"dense\": %d, \"greedy\": %d, "
+           "\"ms\": %.4f}",
+           key.c_str(), kt, klo, jit, dense, greedy, ms);
   entries.push_back(buf);
   // create missing parent directories
   for (size_t k = 1; k < path.size(); ++k)
@@ -151,15 +155,16 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
   const std::string key = keybuf;
   std::ostringstream rep;
   rep << "{\"key\": \"" << key << "\"";
-  int kt = 0, klo = 0, jit = 0, dense = 0;
-  if (use_cache && cache_lookup(key, kt, klo, jit, dense) &&
+  int kt = 0, klo = 0, jit = 0, dense = 0, greedy = 0;
+  if (use_cache && cache_lookup(key, kt, klo, jit, dense, greedy) &&
       (!dense || qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, 1) == QTM_OK)) {
     qtm_set_option(c, QTM_OPT_PATH, QTM_PATH_FUSED);
     qtm_set_option(c, QTM_OPT_TILE_QUBITS, kt);
     qtm_set_option(c, QTM_OPT_LOW_QUBITS, klo);
     qtm_set_option(c, QTM_OPT_JIT, jit);
+    qtm_set_option(c, QTM_OPT_GREEDY_PLAN, greedy);
     rep << ", \"cached\": true, \"tile\": " << kt << ", \"klo\": " << klo << ", \"jit\": " << jit
-        << ", \"dense\": " << dense << "}";
+        << ", \"dense\": " << dense << ", \"greedy\": " << greedy << "}";
     report = rep.str();
     return QTM_OK;
   }
@@ -207,6 +212,7 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
   qtm_set_option(c, QTM_OPT_PATH, QTM_PATH_PLAIN);
   qtm_set_option(c, QTM_OPT_JIT, 0);
   qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, 0);
+  qtm_set_option(c, QTM_OPT_GREEDY_PLAN, 0);
   if ((rc = run(QTM_C128, &ref))) return rc;
   const double tol_z = precision == QTM_C128 ? 1e-12 : 1e-5;
   const double tol_g = precision == QTM_C128 ? 1e-10 : 1e-4;
@@ -228,6 +234,7 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
     qtm_set_option(c, QTM_OPT_TILE_QUBITS, cd.kt);
     qtm_set_option(c, QTM_OPT_LOW_QUBITS, cd.klo);
     qtm_set_option(c, QTM_OPT_JIT, cd.jit);
+    qtm_set_option(c, QTM_OPT_GREEDY_PLAN, cd.greedy);
     if (qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, cd.dense) != QTM_OK) return QTM_ERR_UNSUPPORTED;
     std::vector<double> got;
     int r = run(precision, &got);
@@ -272,16 +279,29 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
       if ((rc = measure(j))) break;
       cands.push_back(j);
     }
+    // the fastest specialised configuration with the greedy plan instead of
+    // the plan chosen for skipping zero tiles (the planner's cost estimate
+    // can misjudge a circuit)
+    {
+      const Cand *fj = nullptr;
+      for (const Cand &cd : cands)
+        if (cd.ok && cd.jit && (!fj || cd.ms < fj->ms)) fj = &cd;
+      if (!rc && fj) {
+        Cand g{fj->kt, fj->klo, 1, 0, 1};
+        if (!(rc = measure(g))) cands.push_back(g);
+      }
+    }
     // the shared-weight dense-block forward, with the backward of the
     // fastest candidate so far
     const Cand *f = nullptr;
     for (const Cand &cd : cands)
       if (cd.ok && (!f || cd.ms < f->ms)) f = &cd;
     if (!rc && f && precision == QTM_C64 && qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, 1) == QTM_OK) {
-      Cand k9{f->kt, f->klo, f->jit, 1};
+      Cand k9{f->kt, f->klo, f->jit, 1, f->greedy};
       if (!(rc = measure(k9))) cands.push_back(k9);
     }
     qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, 0);
+    qtm_set_option(c, QTM_OPT_GREEDY_PLAN, 0);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -304,9 +324,10 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
     const Cand &cd = cands[k];
     char b[256];
     snprintf(b, sizeof b,
-             "%s{\"tile\": %d, \"klo\": %d, \"jit\": %d, \"dense\": %d, \"ok\": %s, \"ms\": %.4f, "
-             "\"err_z\": %.3e, \"err_g\": %.3e}",
-             k ? ", " : "", cd.kt, cd.klo, cd.jit, cd.dense, cd.ok ? "true" : "false", cd.ms, cd.err_z, cd.err_g);
+             "%s{\"tile\": %d, \"klo\": %d, \"jit\": %d, \"dense\": %d, \"greedy\": %d, \"ok\": %s, "
+             "\"ms\": %.4f, \"err_z\": %.3e, \"err_g\": %.3e}",
+             k ? ", " : "", cd.kt, cd.klo, cd.jit, cd.dense, cd.greedy, cd.ok ? "true" : "false", cd.ms, cd.err_z,
+             cd.err_g);
     rep << b;
   }
   rep << "]";
@@ -315,6 +336,7 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
     qtm_set_option(c, QTM_OPT_TILE_QUBITS, 0);
     qtm_set_option(c, QTM_OPT_LOW_QUBITS, 0);
     qtm_set_option(c, QTM_OPT_JIT, 0);
+    qtm_set_option(c, QTM_OPT_GREEDY_PLAN, 0);
     rep << ", \"tile\": 0, \"klo\": 0, \"jit\": 0}";
     report = rep.str();
     return QTM_ERR_UNSUPPORTED;
@@ -324,10 +346,11 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
   qtm_set_option(c, QTM_OPT_LOW_QUBITS, win->klo);
   qtm_set_option(c, QTM_OPT_JIT, win->jit);
   qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, win->dense);
+  qtm_set_option(c, QTM_OPT_GREEDY_PLAN, win->greedy);
   rep << ", \"tile\": " << win->kt << ", \"klo\": " << win->klo << ", \"jit\": " << win->jit
-      << ", \"dense\": " << win->dense << ", \"ms\": " << win->ms << "}";
+      << ", \"dense\": " << win->dense << ", \"greedy\": " << win->greedy << ", \"ms\": " << win->ms << "}";
   report = rep.str();
-  if (use_cache) cache_store(key, win->kt, win->klo, win->jit, win->dense, win->ms);
+  if (use_cache) cache_store(key, win->kt, win->klo, win->jit, win->dense, win->greedy, win->ms);
   return QTM_OK;
 }
 

@@ -2,7 +2,9 @@
 #include "circuit.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
+#include <map>
 #include <set>
 #include <sstream>
 
@@ -312,9 +314,191 @@ std::vector<char> choose_set(Sched &S, const std::vector<char> &base, const std:
   return in;
 }
 
+// Tiles of the greedy planner: each sweep takes the klo low qubits plus the
+// kt - klo others that let the most ops run.
+std::vector<uint64_t> greedy_tiles(Sched S, int nq, int kt, int klo) {
+  std::vector<uint64_t> out;
+  std::vector<int> all_q(nq);
+  for (int q = 0; q < nq; ++q) all_q[q] = q;
+  size_t n_done = 0;
+  while (n_done < S.ops.size()) {
+    std::vector<char> base(nq, 0);
+    for (int q = 0; q < klo; ++q) base[q] = 1;
+    std::vector<char> T = choose_set(S, base, all_q, kt, nq, nullptr);
+    const size_t ran = S.run(T, nullptr, true, kMaxSweepBlocks).size();
+    if (ran == 0) break;
+    n_done += ran;
+    uint64_t m = 0;
+    for (int q = 0; q < nq; ++q)
+      if (T[q]) m |= (uint64_t)1 << q;
+    out.push_back(m);
+  }
+  return out;
+}
+
+// Estimated cost of one sweep for kernels that skip the tiles whose
+// amplitudes are all zero, in units of one fused block applied to the whole
+// state by the forward and the backward sweep together.  A full-state sweep
+// moves the state through HBM (kSweepIo block units), which the block work
+// hides only in part (kOverlap); a sweep over a fraction `live` of the tiles
+// costs that fraction, but at least a per-block latency (few tiles run their
+// blocks one after another); each sweep adds a launch.  The constants are
+// MI355X measurements of the complex64 sweeps at 20 qubits, batch 64: about
+// 44 us per block over the whole state (forward + backward), 530 us of
+// traffic per full-state sweep pair.
+double sweep_cost(double live, int blocks) {
+  constexpr double kSweepIo = 12.0, kOverlap = 0.3, kLatency = 0.03, kLaunch = 0.25;
+  const double b = blocks;
+  const double full = std::max(kSweepIo, b) + kOverlap * std::min(kSweepIo, b);
+  return std::max(live * full, kLatency * b) + kLaunch;
+}
+
+// Qubits a run of ops excites: until a qubit is the target of a
+// non-diagonal block or of a CNOT, every amplitude with its bit set is 0.
+uint64_t excited_by(const std::vector<FOp> &ops, const std::vector<int> &order) {
+  uint64_t ex = 0;
+  for (int i : order) {
+    const FOp &o = ops[i];
+    if ((o.kind == FK_BLOCK && !o.diagonal) || o.kind == FK_CNOT) ex |= (uint64_t)1 << o.target();
+  }
+  return ex;
+}
+
+// Fraction of the tiles a sweep with tile mask `tile` runs when the qubits
+// in `ex` are excited before it: those whose outer bits are 0 on every
+// unexcited outer qubit.
+double live_fraction(uint64_t ex, uint64_t tile, int nq, int kt) {
+  const uint64_t all = nq >= 64 ? ~(uint64_t)0 : (((uint64_t)1 << nq) - 1);
+  const int outer_ex = __builtin_popcountll(ex & ~tile & all);
+  return std::ldexp(1.0, outer_ex - (nq - kt));
+}
+
+int count_blocks(const std::vector<FOp> &ops, const std::vector<int> &order) {
+  int b = 0;
+  for (int i : order) b += ops[i].kind == FK_BLOCK ? 1 : 0;
+  return b;
+}
+
+double tiles_cost(Sched S, const std::vector<uint64_t> &tiles, int nq, int kt) {
+  double cost = 0.0;
+  uint64_t ex = 0;
+  for (uint64_t m : tiles) {
+    std::vector<char> T(nq, 0);
+    for (int q = 0; q < nq; ++q) T[q] = (m >> q) & 1;
+    const std::vector<int> order = S.run(T, nullptr, true, kMaxSweepBlocks);
+    cost += sweep_cost(live_fraction(ex, m, nq, kt), count_blocks(S.ops, order));
+    ex |= excited_by(S.ops, order);
+  }
+  return cost;
+}
+
+// Tile sequence for kernels that skip all-zero tiles: a beam search over
+// sweeps.  A sweep that leaves unexcited qubits outside its tile runs only a
+// fraction of the tiles, so fewer ops per sweep can cost less than the
+// greedy planner's maximal sweeps.  Candidates per step: the greedy tile,
+// and the greedy tile with one, or two, unexcited qubits kept out of it.
+// Returns the greedy sequence when the search finds nothing cheaper.
+std::vector<uint64_t> zero_aware_tiles(const Sched &S0, int nq, int kt, int klo) {
+  const std::vector<uint64_t> greedy = greedy_tiles(S0, nq, kt, klo);
+  if (nq <= kt) return greedy;
+  const double greedy_cost = tiles_cost(S0, greedy, nq, kt);
+  constexpr int kWidth = 8, kTopSingles = 5, kMaxDepth = 64;
+  constexpr double kPerBlockLeft = 1.2;  // ranking: estimated cost of the blocks not yet run
+  struct Node {
+    std::vector<int> left;
+    std::vector<char> done;
+    uint64_t ex = 0;
+    size_t n_done = 0;
+    int blocks_left = 0;
+    double cost = 0.0;
+    std::vector<uint64_t> tiles;
+  };
+  int total_blocks = 0;
+  for (const FOp &o : S0.ops) total_blocks += o.kind == FK_BLOCK ? 1 : 0;
+  std::vector<Node> frontier(1);
+  frontier[0].left = S0.left;
+  frontier[0].done = S0.done;
+  frontier[0].blocks_left = total_blocks;
+  std::vector<int> all_q(nq);
+  for (int q = 0; q < nq; ++q) all_q[q] = q;
+  double best_cost = greedy_cost;
+  std::vector<uint64_t> best = greedy;
+  for (int depth = 0; depth < kMaxDepth && !frontier.empty(); ++depth) {
+    std::map<std::vector<char>, Node> next;
+    for (const Node &nd : frontier) {
+      Sched S{S0.ops, S0.succ, nd.left, nd.done};
+      std::vector<char> base(nq, 0);
+      for (int q = 0; q < klo; ++q) base[q] = 1;
+      auto tile_without = [&](const std::vector<int> &out) {
+        std::vector<int> cands;
+        for (int q : all_q)
+          if (std::find(out.begin(), out.end(), q) == out.end()) cands.push_back(q);
+        return choose_set(S, base, cands, kt, nq, nullptr);
+      };
+      std::vector<std::vector<char>> tiles;
+      tiles.push_back(tile_without({}));
+      // unexcited qubits outside the low ones, by the ops the tile without
+      // each of them runs
+      std::vector<std::pair<long, int>> singles;
+      for (int q = klo; q < nq; ++q) {
+        if ((nd.ex >> q) & 1) continue;
+        std::vector<char> T = tile_without({q});
+        singles.push_back({-(long)S.run(T, nullptr, false, kMaxSweepBlocks).size(), q});
+        tiles.push_back(T);
+      }
+      std::sort(singles.begin(), singles.end());
+      const int ns = std::min((int)singles.size(), kTopSingles);
+      for (int i = 0; i < ns; ++i)
+        for (int j = i + 1; j < ns; ++j) tiles.push_back(tile_without({singles[i].second, singles[j].second}));
+      std::set<uint64_t> seen;
+      for (const std::vector<char> &T : tiles) {
+        uint64_t m = 0;
+        for (int q = 0; q < nq; ++q)
+          if (T[q]) m |= (uint64_t)1 << q;
+        if ((int)__builtin_popcountll(m) != kt || !seen.insert(m).second) continue;
+        Sched St{S0.ops, S0.succ, nd.left, nd.done};
+        const std::vector<int> order = St.run(T, nullptr, true, kMaxSweepBlocks);
+        if (order.empty()) continue;
+        const int nb = count_blocks(S0.ops, order);
+        Node c;
+        c.cost = nd.cost + sweep_cost(live_fraction(nd.ex, m, nq, kt), nb);
+        c.ex = nd.ex | excited_by(S0.ops, order);
+        c.n_done = nd.n_done + order.size();
+        c.blocks_left = nd.blocks_left - nb;
+        c.tiles = nd.tiles;
+        c.tiles.push_back(m);
+        if (c.n_done == S0.ops.size()) {
+          if (c.cost < best_cost - 1e-9) {
+            best_cost = c.cost;
+            best = c.tiles;
+          }
+          continue;
+        }
+        if (c.cost >= best_cost) continue;
+        c.left = std::move(St.left);
+        c.done = St.done;
+        auto it = next.find(St.done);
+        if (it == next.end()) next.emplace(std::move(St.done), std::move(c));
+        else if (c.cost < it->second.cost) it->second = std::move(c);
+      }
+    }
+    std::vector<Node> nf;
+    nf.reserve(next.size());
+    for (auto &kv : next) nf.push_back(std::move(kv.second));
+    std::sort(nf.begin(), nf.end(), [&](const Node &a, const Node &b) {
+      const double ka = a.cost + kPerBlockLeft * a.blocks_left, kb = b.cost + kPerBlockLeft * b.blocks_left;
+      if (ka != kb) return ka < kb;
+      return a.tiles < b.tiles;
+    });
+    if ((int)nf.size() > kWidth) nf.resize(kWidth);
+    frontier = std::move(nf);
+  }
+  return best;
+}
+
 }  // namespace
 
-Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo) {
+Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo, bool zero_skip) {
   Plan p;
   p.n = c.n;
   p.kt = kt;
@@ -335,17 +519,14 @@ Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo) {
     for (int i : preds[j]) succ[i].push_back((int)j);
   }
   Sched S{p.ops, succ, left, std::vector<char>(p.ops.size(), 0)};
-  size_t n_done = 0;
-  std::vector<int> all_q(c.n);
-  for (int q = 0; q < c.n; ++q) all_q[q] = q;
-  while (n_done < p.ops.size()) {
-    // tile: the klo low qubits plus the best kt - klo others
-    std::vector<char> base(c.n, 0);
-    for (int q = 0; q < p.klo; ++q) base[q] = 1;
-    std::vector<char> T = choose_set(S, base, all_q, kt, c.n, nullptr);
+  // tiles: the klo low qubits plus kt - klo others per sweep
+  const std::vector<uint64_t> tiles =
+      zero_skip ? zero_aware_tiles(S, c.n, kt, p.klo) : greedy_tiles(S, c.n, kt, p.klo);
+  for (uint64_t tm : tiles) {
+    std::vector<char> T(c.n, 0);
+    for (int q = 0; q < c.n; ++q) T[q] = (tm >> q) & 1;
     std::vector<int> order = S.run(T, nullptr, true, kMaxSweepBlocks);
-    if (order.empty()) break;  // cannot happen: the earliest ready op's target gets picked
-    n_done += order.size();
+    if (order.empty()) break;  // cannot happen: every tile of the sequence runs ops
     Sweep sw;
     for (int q = 0; q < c.n; ++q)
       if (T[q]) sw.tile.push_back(q);
@@ -687,14 +868,15 @@ Program encode_program(const CircuitDesc &c, const Plan &p) {
   return pr;
 }
 
-std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostPlan &out) {
-  Plan plan = make_plan(c, kt, klo);
+std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostPlan &out, bool zero_skip) {
+  Plan plan = make_plan(c, kt, klo, zero_skip);
   std::string why = check_plan(c, plan);
   if (!why.empty()) return why;
   HostPlan &h = out;
   h.prog = encode_program(c, plan);
   h.kt = kt;
   h.klo = klo;
+  h.zero_skip = zero_skip ? 1 : 0;
   h.n_blocks = plan.n_blocks;
   h.n_gslots = plan.n_gslots;
   h.max_gslots = h.prog.max_gslots_per_sweep;

@@ -126,7 +126,10 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
                        int32_t n_obs, CircuitDesc &out, std::string &err);
 
 // Plan the fused path for tile size kt (<= n) with klo contiguous low qubits.
-Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo);
+// zero_skip: plan for kernels that skip all-zero tiles (the sweeps' tiles
+// are chosen by an estimated cost that counts only the tiles that run);
+// otherwise each sweep takes the tile that runs the most ops.
+Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo, bool zero_skip = false);
 
 // Check the plan's invariants (each gate scheduled once, dependency order,
 // stage/tile membership).  Returns "" when valid.
@@ -156,6 +159,7 @@ Program encode_program(const CircuitDesc &c, const Plan &p);
 // occurrence -> gradient slot map and the two sign tables.
 struct HostPlan {
   int32_t kt = 0, klo = 0, n_blocks = 0, n_gslots = 0, max_gslots = 0, n_sweeps = 0;
+  int32_t zero_skip = 0;  // planned for kernels that skip all-zero tiles
   Program prog;
   std::vector<int32_t> blk;        // per block: [q, ng, (type, src, idx, widx, occ) x ng]
   std::vector<int32_t> blk_off;    // block -> offset in blk
@@ -165,6 +169,7 @@ struct HostPlan {
 };
 
 // Plan, check and encode.  Returns "" or the planner's error.
-std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostPlan &out);
+std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostPlan &out,
+                            bool zero_skip = false);
 
 }  // namespace qtm

@@ -98,13 +98,15 @@ void exercise(const Spec &s, const std::string &name, bool all_tiles) {
   if (d.has_crot() || d.n < kMinTileQubits) return;
   const int kmax = std::min(d.n, kMaxTileQubits);
   for (int kt = all_tiles ? kMinTileQubits : kmax; kt <= kmax; ++kt)
-    for (int klo = 0; klo <= std::min(kt, 7); klo += (all_tiles ? 1 : 3)) {
-      const std::string tag = name + " kt=" + std::to_string(kt) + " klo=" + std::to_string(klo);
-      Plan p = make_plan(d, kt, klo);
+    for (int klo = 0; klo <= std::min(kt, 7); klo += (all_tiles ? 1 : 3))
+      for (int zs = 0; zs < 2; ++zs) {
+      const std::string tag = name + " kt=" + std::to_string(kt) + " klo=" + std::to_string(klo) +
+                              " zero_skip=" + std::to_string(zs);
+      Plan p = make_plan(d, kt, klo, zs != 0);
       check(check_plan(d, p).empty(), tag + ": check_plan");
       check(!plan_json(d, p).empty(), tag + ": plan_json");
       HostPlan hp;
-      const std::string why = build_host_plan(d, kt, klo, hp);
+      const std::string why = build_host_plan(d, kt, klo, hp, zs != 0);
       check(why.empty(), tag + ": build_host_plan: " + why);
       if (!why.empty()) continue;
       for (int dbl = 0; dbl < 2; ++dbl) {

@@ -163,3 +163,18 @@ def test_c128_tile12(jit, n, L, ent, klo):
     got = run_gpu(circ, wl.inputs, wl.weights, wl.grad_out, "c128", qcirc=c)
     assert c.plan("c128")["kt"] == 12
     assert_parity(got, oracle_ref(wl), "c128", f"c128 tile 12 n={n} jit={jit}")
+
+
+@pytest.mark.parametrize("klo,greedy", [(4, 0), (3, 0), (5, 1)])
+def test_c3_sweep_plans(klo, greedy):
+    """The n=20 workload through the specialised sweeps with the plan chosen
+    for skipping all-zero tiles (the default with QTM_OPT_JIT; 3 and 4 low
+    qubits) and with the greedy plan (QTM_OPT_GREEDY_PLAN), against the oracle
+    fixture."""
+    import paper_2404_06314_amd as q
+    d = np.load(os.path.join(GOLDEN, "oracle_c3_b64.npz"), allow_pickle=False)
+    wl = W.config_workload("c3")
+    c = jit_circuit(wl.circuit, 12, klo)
+    c.set_option(q.QTM_OPT_GREEDY_PLAN, greedy)
+    got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, "c64", qcirc=c)
+    assert_parity(got, (d["expvals"], d["grad_w"], d["grad_x"]), "c64", f"jit c3 t12l{klo} greedy={greedy}")

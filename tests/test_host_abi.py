@@ -156,12 +156,15 @@ def _plan_gate_order(plan):
     return order
 
 
-def _check_plan(qtm, circ, precision="c64", tile=None, klo=None, batch=2, seed=0):
+def _check_plan(qtm, circ, precision="c64", tile=None, klo=None, batch=2, seed=0, zero_skip=False):
     c = qtm.Circuit.from_workload(circ)
     if tile:
         c.set_option(qtm.QTM_OPT_TILE_QUBITS, tile)
     if klo:
         c.set_option(qtm.QTM_OPT_LOW_QUBITS, klo)
+    if zero_skip:
+        # plans for the specialised kernels, which skip all-zero tiles
+        c.set_option(qtm.QTM_OPT_JIT, 1)
     plan = c.plan(precision)
     assert "error" not in plan
     order = _plan_gate_order(plan)
@@ -181,24 +184,76 @@ def _check_plan(qtm, circ, precision="c64", tile=None, klo=None, batch=2, seed=0
     return plan
 
 
+@pytest.mark.parametrize("zero_skip", [False, True])
 @pytest.mark.parametrize("name", ["c1", "c2"])
-def test_plan_reorders_only_commuting_gates(qtm, name):
-    _check_plan(qtm, W.config_workload(name).circuit)
+def test_plan_reorders_only_commuting_gates(qtm, name, zero_skip):
+    _check_plan(qtm, W.config_workload(name).circuit, zero_skip=zero_skip)
 
 
+@pytest.mark.parametrize("zero_skip", [False, True])
 @pytest.mark.parametrize("n,L,ent,tile,klo", [(10, 3, "ring", 6, 3), (9, 2, "ladder", 5, 2),
                                               (11, 2, "ring", 7, 5), (8, 4, "ladder", 4, 4)])
-def test_plan_multi_sweep_small(qtm, n, L, ent, tile, klo):
-    plan = _check_plan(qtm, W.layered_circuit(n, L, ent), tile=tile, klo=klo)
+def test_plan_multi_sweep_small(qtm, n, L, ent, tile, klo, zero_skip):
+    plan = _check_plan(qtm, W.layered_circuit(n, L, ent), tile=tile, klo=klo, zero_skip=zero_skip)
     assert len(plan["sweeps"]) >= 2
 
 
-def test_plan_random_circuits(qtm):
+@pytest.mark.parametrize("zero_skip", [False, True])
+def test_plan_random_circuits(qtm, zero_skip):
     rng = np.random.default_rng(5)
     for n in (4, 5, 7, 9):
         for _ in range(4):
             circ = W.random_circuit(rng, n, 40)
-            _check_plan(qtm, circ, tile=4 if n > 4 else None, klo=2, seed=n)
+            _check_plan(qtm, circ, tile=4 if n > 4 else None, klo=2, seed=n, zero_skip=zero_skip)
+
+
+def _live_blocks(plan, n):
+    """Per sweep, the fraction of the tiles the specialised kernels run: those
+    whose outer bits are 0 on every outer qubit not excited before the sweep."""
+    out, ex = [], 0
+    for sw, ex_after in zip(plan["sweeps"], plan["excited"]):
+        tile = sum(1 << q for q in sw["tile"])
+        outer_ex = bin(ex & ~tile & ((1 << n) - 1)).count("1")
+        out.append(2.0 ** (outer_ex - (n - plan["kt"])))
+        ex = ex_after
+    return out
+
+
+@pytest.mark.parametrize("klo", [4, 5])
+def test_zero_skip_plan_for_the_n20_ladder(qtm, klo):
+    """With the specialised kernels on, the n = 20, 8-layer CZ-ladder circuit
+    is planned for skipping all-zero tiles: it runs fewer blocks over the
+    whole state and fewer tile-weighted blocks than the greedy plan, still
+    schedules every gate once in an order the oracle agrees with, and
+    QTM_OPT_GREEDY_PLAN restores the greedy plan."""
+    import bench
+    circ = W.config_workload("c3").circuit
+    plans = {}
+    for mode in ("greedy", "zero", "forced"):
+        c = qtm.Circuit.from_workload(circ)
+        c.set_option(qtm.QTM_OPT_TILE_QUBITS, 12)
+        c.set_option(qtm.QTM_OPT_LOW_QUBITS, klo)
+        if mode != "greedy":
+            c.set_option(qtm.QTM_OPT_JIT, 1)
+        if mode == "forced":
+            c.set_option(qtm.QTM_OPT_GREEDY_PLAN, 1)
+        plans[mode] = c.plan("c64")
+    g, z = plans["greedy"], plans["zero"]
+    assert [s["tile"] for s in plans["forced"]["sweeps"]] == [s["tile"] for s in g["sweeps"]]
+    assert [s["tile"] for s in z["sweeps"]] != [s["tile"] for s in g["sweeps"]]
+    order = _plan_gate_order(z)
+    assert sorted(order) == list(range(circ.n_gates))
+    stats = {}
+    for name, p in (("greedy", g), ("zero", z)):
+        blocks = bench._sweep_block_ops(p, 0, False)
+        live = _live_blocks(p, circ.n)
+        stats[name] = (sum(b for b, f in zip(blocks, live) if f == 1.0), sum(b * f for b, f in zip(blocks, live)))
+    assert stats["zero"][0] < stats["greedy"][0], stats
+    assert stats["zero"][1] < stats["greedy"][1], stats
+    # the 36 blocks that depend on qubit 19's first gate (its light cone in
+    # the ladder) are the least any plan must run over the whole state
+    if klo == 4:
+        assert stats["zero"][0] <= 36, stats
 
 
 def test_plan_sizes_for_configs(qtm):

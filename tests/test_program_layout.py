@@ -134,9 +134,10 @@ def check_program(plan, n, circ=None):
                             assert np.array_equal(direct, rec_sign), "diag sign decomposition"
 
 
-@pytest.mark.parametrize("name,tile,klo", [("c1", 0, 0), ("c2", 0, 0), ("c3", 0, 0),
-                                           ("c3", 10, 4), ("c5", 0, 0)])
-def test_program_layout_configs(name, tile, klo):
+@pytest.mark.parametrize("name,tile,klo,zero_skip", [("c1", 0, 0, 0), ("c2", 0, 0, 0), ("c3", 0, 0, 0),
+                                                     ("c3", 10, 4, 0), ("c5", 0, 0, 0), ("c2", 0, 0, 1),
+                                                     ("c3", 12, 4, 1), ("c3", 12, 3, 1)])
+def test_program_layout_configs(name, tile, klo, zero_skip):
     import paper_2404_06314_amd as q
     wl = W.config_workload(name)
     c = q.Circuit.from_workload(wl.circuit)
@@ -144,6 +145,8 @@ def test_program_layout_configs(name, tile, klo):
         c.set_option(q.QTM_OPT_TILE_QUBITS, tile)
     if klo:
         c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
+    if zero_skip:
+        c.set_option(q.QTM_OPT_JIT, 1)
     if name == "c5":
         pytest.skip("n = 26 emulation is too large for the CPU suite; covered by c3 layouts")
     check_program(c.plan("c64"), wl.circuit.n, wl.circuit)
