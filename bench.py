@@ -213,6 +213,46 @@ def cpu_baselines(wl, threads: int, samples: int, samples_1: int):
     return allc
 
 
+def bench_jacobian(args, c, wl, prec, x, w, G, state, tuned):
+    """Full Jacobian (B, M, |Theta|): the forward once, then one adjoint pass
+    per observable.  Timed against one forward and one backward (VJP) pass of
+    the same configuration: the ratio to M backward passes says what sharing
+    psi across the M bras could at most save."""
+    import torch
+    import workloads as W
+
+    def timed(fn, reps):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    M = wl.circuit.n_obs
+    fwd_ms = timed(lambda: c.forward(x, w, prec, state=state), args.steps)
+
+    def vjp():
+        c.forward(x, w, prec, state=state)
+        c.backward(x, w, G, prec, state=state)
+
+    step_ms = timed(vjp, args.steps)
+    bwd_ms = step_ms - fwd_ms
+    jac_ms = timed(lambda: c.jacobian(x, w, prec), max(1, args.steps // 4))
+    log(f"jacobian: {jac_ms:.3f} ms; forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms, "
+        f"M = {M}: {jac_ms / (M * bwd_ms):.3f} of M backward passes")
+    out = {"metric": "full Jacobian (B, M, |Theta|) ms per batch", "value": round(jac_ms, 3),
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": prec, "data": "synthetic",
+           "config": {"workload": W.WORKLOAD_NAMES[args.config], "batch": wl.batch, "observables": M,
+                      "autotuned": tuned is not None},
+           "forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
+           "ratio_to_M_backward": round(jac_ms / (M * bwd_ms), 4),
+           "ratio_to_forward_plus_M_backward": round(jac_ms / (fwd_ms + M * bwd_ms), 4)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +285,9 @@ def main():
     ap.add_argument("--paper-sweep", default="", choices=["", "fig1", "fig2", "tab1", "all"],
                     help="time the paper's benchmark shapes (Eq. (7) ansatz with input scaling) "
                          "instead of the default workload; one JSON line per shape")
+    ap.add_argument("--jacobian", action="store_true",
+                    help="time the full Jacobian (qtm_jacobian) of the workload against one forward "
+                         "and one backward pass; one JSON line")
     ap.add_argument("--digest", default="",
                     help="print the digest of the sources of this kernel (traffic records refer to it)")
     args = ap.parse_args()
@@ -306,6 +349,8 @@ def main():
     G = torch.as_tensor(wl.grad_out, device=dev)
     B = wl.batch
     state = c.alloc_state(B, prec)
+    if args.jacobian:
+        return bench_jacobian(args, c, wl, prec, x, w, G, state, tuned)
     log(f"workload {circ.name}: n={circ.n} gates={circ.n_gates} B={B} precision={prec} "
         f"path={args.path}")
 

@@ -562,9 +562,12 @@ int check_angles(qtm_circuit_t c, int32_t B, const double *x, const double *w, h
 // prepped: no forward has run on c since the one that filled psi, so mats
 // and coef may still hold its matrices (checked against the plan, batch and
 // precision here).
+// psi_in: the final states, if not in psi (the fused path reads them there
+// and leaves psi overwritten; the per-gate path works in psi, so they are
+// copied there first)
 int run_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
-                 const double *weights, const double *grad_expvals, void *psi, double *grad_weights,
-                 double *grad_inputs, bool prepped, hipStream_t s) {
+                 const double *weights, const double *grad_expvals, void *psi, const void *psi_in,
+                 double *grad_weights, double *grad_inputs, bool prepped, hipStream_t s) {
   const DevCircuit &d = c->dev;
   const size_t sbytes = ((size_t)batch << c->desc.n) * elem_bytes(precision);
   int rc;
@@ -599,16 +602,18 @@ int run_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
     }
     e = precision == QTM_C64
             ? fused_backward<float>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
-                                    (double *)c->coef.p, reuse, psi, c->lam.p, (double *)c->part_grad.p,
+                                    (double *)c->coef.p, reuse, psi, psi_in, c->lam.p, (double *)c->part_grad.p,
                                     (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
                                     grad_inputs, s, c->timer.get(), js, rn)
             : fused_backward<double>(d, *p, batch, inputs, weights, grad_expvals, c->mats.p,
-                                     (double *)c->coef.p, reuse, psi, c->lam.p, (double *)c->part_grad.p,
+                                     (double *)c->coef.p, reuse, psi, psi_in, c->lam.p, (double *)c->part_grad.p,
                                      (double *)c->part_norm.p, (double *)c->gocc.p, grad_weights,
                                      grad_inputs, s, c->timer.get(), js, rn);
   } else {
     if ((rc = c->cs.ensure((size_t)batch * std::max(d.n_occ, 1) * sizeof(double2)))) return rc;
     if ((rc = c->part.ensure(plain_part_doubles(d, batch) * sizeof(double)))) return rc;
+    if (psi_in && (e = hipMemcpyAsync(psi, psi_in, sbytes, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return hip_fail(e, "state copy");
     // the per-gate backward reuses the forward's partial-sum buffer
     c->norm_part = nullptr;
     e = launch_half_angles(d, batch, inputs, weights, (double2 *)c->cs.p, s);
@@ -885,8 +890,8 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
     if ((rc = do_forward(c, batch, precision, inputs, weights, (double *)c->gocc.p, psi, true, s)))
       return rc;
   }
-  return run_backward(c, batch, precision, inputs, weights, grad_expvals, psi, grad_weights, grad_inputs,
-                      prepped, s);
+  return run_backward(c, batch, precision, inputs, weights, grad_expvals, psi, nullptr, grad_weights,
+                      grad_inputs, prepped, s);
 }
 
 int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
@@ -910,15 +915,14 @@ int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double
       (rc = c->jac_out.ensure((size_t)batch * M * sizeof(double))))
     return rc;
   double *out = expvals ? expvals : (double *)c->jac_out.p;
-  if ((rc = do_forward(c, batch, precision, inputs, weights, out, c->state_ws.p, true, s))) return rc;
-  hipError_t e = hipMemcpyAsync(c->jac_state.p, c->state_ws.p, sbytes, hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return hip_fail(e, "jacobian state copy");
+  // the forward leaves the final states in jac_state; every adjoint pass
+  // reads them there and works in state_ws (no copies between the passes)
+  if ((rc = do_forward(c, batch, precision, inputs, weights, out, c->jac_state.p, true, s))) return rc;
+  hipError_t e;
   for (int m = 0; m < M; ++m) {
-    if (m > 0 && (e = hipMemcpyAsync(c->state_ws.p, c->jac_state.p, sbytes, hipMemcpyDeviceToDevice, s)))
-      return hip_fail(e, "jacobian state copy");
     if ((e = launch_onehot((double *)c->jac_G.p, batch, M, m, s))) return hip_fail(e, "jacobian seed");
     if ((rc = run_backward(c, batch, precision, inputs, weights, (double *)c->jac_G.p, c->state_ws.p,
-                           (double *)c->jac_gw.p, nullptr, true, s)))
+                           c->jac_state.p, (double *)c->jac_gw.p, nullptr, true, s)))
       return rc;
     if ((e = launch_scatter_jac(d, batch, (double *)c->gocc.p, inputs, weights, m, jac_weights,
                                   jac_inputs, s)))

@@ -199,8 +199,8 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *ma
 
 template <typename R, int KT>
 static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const double *G, void *mats,
-                          void *psi, void *lam, double *part_grad, double *part_norm, hipStream_t s,
-                          SweepTimer *tm, const JitSweeps *js, const Renorm &rn) {
+                          void *psi, const void *psi_in, void *lam, double *part_grad, double *part_norm,
+                          hipStream_t s, SweepTimer *tm, const JitSweeps *js, const Renorm &rn) {
   const int nwg = fused_wg_per_sample(d.n, KT);
   const size_t lds = bwd_lds<R, KT>(p.max_gslots);
   hipError_t e = allow_lds(k_fused_bwd<R, KT>, lds);
@@ -212,6 +212,7 @@ static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const do
     a.sweep_off = p.sweep_off_bwd[sw];
     a.n = d.n;
     a.psi = psi;
+    a.psi_in = sw == 0 ? psi_in : nullptr;
     a.lam = lam;
     a.mats = mats;
     a.n_blocks = p.n_blocks;
@@ -285,16 +286,17 @@ hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const dou
 template <typename R>
 hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                           const double *w, const double *G, void *mats, double *coef, bool prepped,
-                          void *state, void *lam, double *part_grad, double *part_norm,
-                          double *gocc, double *gw, double *gx, hipStream_t s, SweepTimer *tm,
-                          const JitSweeps *js, const Renorm &rn) {
+                          void *state, const void *state_in, void *lam, double *part_grad,
+                          double *part_norm, double *gocc, double *gw, double *gx, hipStream_t s,
+                          SweepTimer *tm, const JitSweeps *js, const Renorm &rn) {
   // prepped: mats and coef still hold what the forward computed from the
   // same angles for this plan and batch
   hipError_t e = prepped ? hipSuccess : prep<R>(d, p, B, x, w, mats, coef, s);
   if (e != hipSuccess) return e;
   // bra term of observables with X or Y factors, added in the first sweep
-  if ((e = launch_pauli_seed<R>(d, B, state, lam, G, false, s)) != hipSuccess) return e;
-#define BWD_CALL(K) e = run_bwd<R, K>(d, p, B, G, mats, state, lam, part_grad, part_norm, s, tm, js, rn)
+  if ((e = launch_pauli_seed<R>(d, B, state_in ? state_in : state, lam, G, false, s)) != hipSuccess) return e;
+#define BWD_CALL(K) \
+  e = run_bwd<R, K>(d, p, B, G, mats, state, state_in, lam, part_grad, part_norm, s, tm, js, rn)
   QTM_KT_DISPATCH(p.kt, BWD_CALL)
 #undef BWD_CALL
   if (e != hipSuccess) return e;
@@ -317,12 +319,12 @@ template hipError_t fused_forward<double>(const DevCircuit &, const DevPlan &, i
                                           bool, hipStream_t, SweepTimer *, const JitSweeps *, const Renorm &);
 template hipError_t fused_backward<float>(const DevCircuit &, const DevPlan &, int, const double *,
                                           const double *, const double *, void *, double *, bool,
-                                          void *, void *, double *, double *, double *, double *,
+                                          void *, const void *, void *, double *, double *, double *, double *,
                                           double *, hipStream_t, SweepTimer *, const JitSweeps *,
                                           const Renorm &);
 template hipError_t fused_backward<double>(const DevCircuit &, const DevPlan &, int, const double *,
                                            const double *, const double *, void *, double *, bool,
-                                           void *, void *, double *, double *, double *, double *,
+                                           void *, const void *, void *, double *, double *, double *, double *,
                                            double *, hipStream_t, SweepTimer *, const JitSweeps *,
                                            const Renorm &);
 

@@ -110,7 +110,9 @@ size_t fused_rn_doubles(const DevCircuit &d, const DevPlan &p, int B);
 // js: kernels specialised for this plan (nullptr: the compiled sweep kernels).
 // The forward's prep also writes the derivative coefficients when coef is
 // not NULL; the backward skips its prep when `prepped` (mats and coef hold
-// what a forward computed from the same angles, plan and batch).
+// what a forward computed from the same angles, plan and batch).  The
+// backward reads the final states from state_in when it is not NULL (else
+// from state) and leaves intermediate states in state.
 template <typename R>
 hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                          const double *w, void *mats, double *coef, void *state, double *part_obs,
@@ -119,8 +121,8 @@ hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const dou
 template <typename R>
 hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const double *x,
                           const double *w, const double *G, void *mats, double *coef, bool prepped,
-                          void *state, void *lam, double *part_grad, double *part_norm,
-                          double *gocc, double *gw, double *gx, hipStream_t s, SweepTimer *tm,
-                          const JitSweeps *js, const Renorm &rn);
+                          void *state, const void *state_in, void *lam, double *part_grad,
+                          double *part_norm, double *gocc, double *gw, double *gx, hipStream_t s,
+                          SweepTimer *tm, const JitSweeps *js, const Renorm &rn);
 
 }  // namespace qtm

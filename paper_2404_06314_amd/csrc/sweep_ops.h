@@ -560,6 +560,9 @@ struct BwdArgs {
   // rn_period sweeps before it (each sweep's drift undone)
   double *rn_rec = nullptr;
   int rn_i = 0, rn_period = 0, rn_rows = 0;
+  // first sweep: psi is read from here instead of from psi (NULL: from psi);
+  // the sweep still writes psi (one state buffer read, another written)
+  const void *psi_in = nullptr;
 };
 
 // Sum over a workgroup of NT threads (a power of two) in FP64, in a fixed
