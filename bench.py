@@ -337,6 +337,7 @@ def main():
         c.set_option(q.QTM_OPT_RENORM, args.renorm)
     tuned = None
     if args.autotune and args.path == "fused":
+        os.environ.setdefault("QTM_AUTOTUNE_LOG", "1")  # progress: one line per candidate
         t0 = time.perf_counter()
         tuned = c.autotune(wl.batch, prec, cache=False)
         args.jit = tuned["jit"]

@@ -320,7 +320,9 @@ int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *la
  * circuit's gates and observables, batch, precision and GPU architecture.
  * report (may be NULL): JSON summary of the candidates (truncated to len - 1
  * bytes); *needed = its full length + 1.  Allocates device memory for the
- * trial inputs and one state, synchronises `stream`, takes seconds.
+ * trial inputs and one state, synchronises `stream`, takes seconds (minutes
+ * at 26 qubits); with QTM_AUTOTUNE_LOG=1 in the environment it prints one
+ * line per candidate to stderr as each finishes.
  * QTM_ERR_UNSUPPORTED if no candidate passed (options reset to defaults). */
 int qtm_autotune(qtm_circuit_t c, int32_t batch, int32_t precision, void *stream, int32_t flags,
                  char *report, size_t len, size_t *needed);

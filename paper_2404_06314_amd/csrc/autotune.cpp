@@ -229,7 +229,10 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
     }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QTM_ERR_HIP;
-  auto measure = [&](Cand &cd) -> int {
+  // QTM_AUTOTUNE_LOG=1: one line per candidate on stderr as it finishes
+  const char *lg = getenv("QTM_AUTOTUNE_LOG");
+  const bool log = lg && *lg && *lg != '0';
+  auto measure_one = [&](Cand &cd) -> int {
     qtm_set_option(c, QTM_OPT_PATH, QTM_PATH_FUSED);
     qtm_set_option(c, QTM_OPT_TILE_QUBITS, cd.kt);
     qtm_set_option(c, QTM_OPT_LOW_QUBITS, cd.klo);
@@ -260,6 +263,14 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
     (void)hipEventElapsedTime(&tot, e0, e1);
     cd.ms = tot / reps;
     return QTM_OK;
+  };
+  auto measure = [&](Cand &cd) -> int {
+    const int r = measure_one(cd);
+    if (log)
+      fprintf(stderr, "autotune: tile %d klo %d jit %d greedy %d dense %d: %s %.4f ms (err z %.2e, g %.2e)\n",
+              cd.kt, cd.klo, cd.jit, cd.greedy, cd.dense, r ? "error" : cd.ok ? "ok" : "rejected", cd.ms,
+              cd.err_z, cd.err_g);
+    return r;
   };
   for (Cand &cd : cands)
     if ((rc = measure(cd))) break;

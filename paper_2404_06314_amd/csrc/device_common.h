@@ -173,27 +173,52 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// FP64 sums of three per-thread values a, b, c over each row of 16 lanes.
-// The first two steps transpose while they reduce (a lane passes on two
-// values, then one, instead of three), so on return each lane holds one of
-// its row's sums, chosen by lane & 3: 0 -> a, 1 -> c, 2 -> b, 3 -> 0.
-__device__ __forceinline__ double row_sum3_d(double a, double b, double c) {
-  const unsigned l = __lane_id();
-  const bool odd = (l & 1u) != 0, hi = (l & 2u) != 0;
-  const double s0 = odd ? a : c, k0 = odd ? c : a;
-  const double s1 = odd ? b : 0.0, k1 = odd ? 0.0 : b;
-  const double u0 = k0 + dpp_perm_d<0xb1>(s0);  // quad_perm [1,0,3,2]: a (even) / c (odd) pair sums
-  const double u1 = k1 + dpp_perm_d<0xb1>(s1);  //                      b (even) / 0 (odd)
-  const double s2 = hi ? u0 : u1, k2 = hi ? u1 : u0;
-  double r = k2 + dpp_perm_d<0x4e>(s2);         // quad_perm [2,3,0,1]: quad sums
-  r += dpp_perm_d<0x124>(r);                    // row_ror:4
-  r += dpp_perm_d<0x128>(r);                    // row_ror:8
+// Exchange of 64-bit values between halves (32) or rows (16) of a wave with
+// the gfx950 lane swaps, applied to both 32-bit words: swap32 trades lanes
+// 32-63 of x for lanes 0-31 of y; swap16 trades the odd rows (16 lanes) of x
+// for the even rows of y.
+__device__ __forceinline__ void swap32_d(double &x, double &y) {
+  const unsigned long long ux = __builtin_bit_cast(unsigned long long, x);
+  const unsigned long long uy = __builtin_bit_cast(unsigned long long, y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ux, (unsigned)uy, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ux >> 32), (unsigned)(uy >> 32), false, false);
+  x = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
+  y = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ void swap16_d(double &x, double &y) {
+  const unsigned long long ux = __builtin_bit_cast(unsigned long long, x);
+  const unsigned long long uy = __builtin_bit_cast(unsigned long long, y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ux, (unsigned)uy, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ux >> 32), (unsigned)(uy >> 32), false, false);
+  x = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
+  y = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+
+// FP64 sums of three per-thread values a, b, c over the 64 lanes of a wave.
+// The two swap steps transpose while they reduce (each lane adds pairs of
+// halves, then of rows, of different values), so one row reduction finishes
+// all three: on return every lane of row 0 (lanes 0-15) holds the sum of a,
+// row 1 the sum of c, row 2 the sum of b, row 3 zero.
+__device__ __forceinline__ double wave_sum3_d(double a, double b, double c) {
+  // rows of 16 lanes written [r0, r1, r2, r3]; A0 = a(r0) + a(r2), A1 =
+  // a(r1) + a(r3), likewise B0, B1 of b and C0, C1 of c
+  double z = 0.0;
+  swap32_d(a, b);                 // a: [a(r0), a(r1), b(r0), b(r1)], b: [a(r2), a(r3), b(r2), b(r3)]
+  swap32_d(c, z);                 // c: [c(r0), c(r1), 0, 0], z: [c(r2), c(r3), 0, 0]
+  double ab = a + b, cz = c + z;  // ab: [A0, A1, B0, B1], cz: [C0, C1, 0, 0]
+  swap16_d(ab, cz);               // ab: [A0, C0, B0, 0], cz: [A1, C1, B1, 0]
+  double r = ab + cz;             // [a, c, b, 0] summed over the rows, per lane of a row
+  r += dpp_perm_d<0xb1>(r);       // quad_perm [1,0,3,2]
+  r += dpp_perm_d<0x4e>(r);       // quad_perm [2,3,0,1]
+  r += dpp_perm_d<0x124>(r);      // row_ror:4
+  r += dpp_perm_d<0x128>(r);      // row_ror:8
   return r;
 }
-// Component (0 = a, 1 = b, 2 = c) that row_sum3_d leaves in lane l (l & 3 < 3).
-__device__ __forceinline__ int row_sum3_comp(unsigned l) {
-  const unsigned q = l & 3u;
-  return q == 0u ? 0 : q == 1u ? 2 : 1;
+// Component (0 = a, 1 = b, 2 = c) that wave_sum3_d leaves in the lanes of
+// row (lane >> 4) < 3.
+__device__ __forceinline__ int wave_sum3_comp(unsigned lane) {
+  const unsigned row = lane >> 4;
+  return row == 0u ? 0 : row == 1u ? 2 : 1;
 }
 
 __device__ __forceinline__ int parity_u64(uint64_t v) { return __popcll(v) & 1; }
