@@ -194,32 +194,36 @@ __device__ __forceinline__ void swap16_d(double &x, double &y) {
   y = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
 }
 
-// FP64 sums of three per-thread values a, b, c over the 64 lanes of a wave.
-// The two swap steps transpose while they reduce (each lane adds pairs of
-// halves, then of rows, of different values), so one row reduction finishes
-// all three: on return every lane of row 0 (lanes 0-15) holds the sum of a,
-// row 1 the sum of c, row 2 the sum of b, row 3 zero.
-__device__ __forceinline__ double wave_sum3_d(double a, double b, double c) {
+// FP64 sums of four per-thread values a, b, c, d over the 64 lanes of a
+// wave.  The two swap steps transpose while they reduce (each lane adds
+// pairs of halves, then of rows, of different values), so one row reduction
+// finishes all four: on return every lane of row 0 (lanes 0-15) holds the
+// sum of a, row 1 the sum of c, row 2 the sum of b, row 3 the sum of d.
+__device__ __forceinline__ double wave_sum4_d(double a, double b, double c, double d) {
   // rows of 16 lanes written [r0, r1, r2, r3]; A0 = a(r0) + a(r2), A1 =
-  // a(r1) + a(r3), likewise B0, B1 of b and C0, C1 of c
-  double z = 0.0;
+  // a(r1) + a(r3), likewise B, C, D
   swap32_d(a, b);                 // a: [a(r0), a(r1), b(r0), b(r1)], b: [a(r2), a(r3), b(r2), b(r3)]
-  swap32_d(c, z);                 // c: [c(r0), c(r1), 0, 0], z: [c(r2), c(r3), 0, 0]
-  double ab = a + b, cz = c + z;  // ab: [A0, A1, B0, B1], cz: [C0, C1, 0, 0]
-  swap16_d(ab, cz);               // ab: [A0, C0, B0, 0], cz: [A1, C1, B1, 0]
-  double r = ab + cz;             // [a, c, b, 0] summed over the rows, per lane of a row
+  swap32_d(c, d);                 // c: [c(r0), c(r1), d(r0), d(r1)], d: [c(r2), c(r3), d(r2), d(r3)]
+  double ab = a + b, cd = c + d;  // ab: [A0, A1, B0, B1], cd: [C0, C1, D0, D1]
+  swap16_d(ab, cd);               // ab: [A0, C0, B0, D0], cd: [A1, C1, B1, D1]
+  double r = ab + cd;             // [a, c, b, d] summed over the rows, per lane of a row
   r += dpp_perm_d<0xb1>(r);       // quad_perm [1,0,3,2]
   r += dpp_perm_d<0x4e>(r);       // quad_perm [2,3,0,1]
   r += dpp_perm_d<0x124>(r);      // row_ror:4
   r += dpp_perm_d<0x128>(r);      // row_ror:8
   return r;
 }
-// Component (0 = a, 1 = b, 2 = c) that wave_sum3_d leaves in the lanes of
-// row (lane >> 4) < 3.
-__device__ __forceinline__ int wave_sum3_comp(unsigned lane) {
+// Which of wave_sum4_d's values (0 = a, 1 = b, 2 = c, 3 = d) the lanes of
+// row (lane >> 4) hold.
+__device__ __forceinline__ int wave_sum4_comp(unsigned lane) {
   const unsigned row = lane >> 4;
-  return row == 0u ? 0 : row == 1u ? 2 : 1;
+  return row == 0u ? 0 : row == 1u ? 2 : row == 2u ? 1 : 3;
 }
+// Three values: rows 0-2 hold the sums of a, c, b (row 3: zero).
+__device__ __forceinline__ double wave_sum3_d(double a, double b, double c) {
+  return wave_sum4_d(a, b, c, 0.0);
+}
+__device__ __forceinline__ int wave_sum3_comp(unsigned lane) { return wave_sum4_comp(lane); }
 
 __device__ __forceinline__ int parity_u64(uint64_t v) { return __popcll(v) & 1; }
 
