@@ -155,9 +155,10 @@ static hipError_t launch_sweep(K kernel, const JitSweeps *js, int dir, int sw, i
 }
 
 template <typename R, int KT>
-static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *mats, void *state,
-                          double *part_obs, double *out, bool store_final, hipStream_t s,
-                          SweepTimer *tm, const JitSweeps *js, const Renorm &rn) {
+static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, const double *x, const double *w,
+                          void *mats, double *coef, void *state, double *part_obs, double *out,
+                          bool store_final, hipStream_t s, SweepTimer *tm, const JitSweeps *js,
+                          const Renorm &rn) {
   const int nwg = fused_wg_per_sample(d.n, KT);
   const size_t lds = fwd_lds<R, KT>(d.n_obs);
   hipError_t e = allow_lds(k_fused_fwd<R, KT>, lds);
@@ -180,6 +181,16 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *ma
     a.obs_sgn = p.obs_sgn_f;
     a.part_obs = part_obs;
     a.out = out;
+    if (js && js->loaded && js->direct_prep) {
+      a.blk = p.blk;
+      a.blk_off = p.blk_off;
+      a.x = x;
+      a.w = w;
+      a.n_in = d.n_inputs;
+      a.n_occ = d.n_occ;
+      a.mats_out = mats;
+      a.coef = coef;
+    }
     if (rn.period > 0) {
       // sweep sw rescales when it is a positive multiple of the period; the
       // sweep before it records its end norm
@@ -200,7 +211,8 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, void *ma
 template <typename R, int KT>
 static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const double *G, void *mats,
                           void *psi, const void *psi_in, void *lam, double *part_grad, double *part_norm,
-                          hipStream_t s, SweepTimer *tm, const JitSweeps *js, const Renorm &rn) {
+                          const double *coef, double *gocc, hipStream_t s, SweepTimer *tm, const JitSweeps *js,
+                          const Renorm &rn) {
   const int nwg = fused_wg_per_sample(d.n, KT);
   const size_t lds = bwd_lds<R, KT>(p.max_gslots);
   hipError_t e = allow_lds(k_fused_bwd<R, KT>, lds);
@@ -213,6 +225,9 @@ static hipError_t run_bwd(const DevCircuit &d, const DevPlan &p, int B, const do
     a.n = d.n;
     a.psi = psi;
     a.psi_in = sw == 0 ? psi_in : nullptr;
+    a.coef = coef;
+    a.gocc = gocc;
+    a.n_occ = d.n_occ;
     a.lam = lam;
     a.mats = mats;
     a.n_blocks = p.n_blocks;
@@ -272,9 +287,11 @@ hipError_t fused_forward(const DevCircuit &d, const DevPlan &p, int B, const dou
                          const double *w, void *mats, double *coef, void *state, double *part_obs,
                          double *out, bool store_final, hipStream_t s, SweepTimer *tm,
                          const JitSweeps *js, const Renorm &rn) {
-  hipError_t e = prep<R>(d, p, B, x, w, mats, coef, s);
+  // (a specialised forward that prepares the matrices itself needs no prep launch)
+  hipError_t e = js && js->loaded && js->direct_prep ? hipSuccess : prep<R>(d, p, B, x, w, mats, coef, s);
   if (e != hipSuccess) return e;
-#define FWD_CALL(K) e = run_fwd<R, K>(d, p, B, mats, state, part_obs, out, store_final, s, tm, js, rn)
+#define FWD_CALL(K) \
+  e = run_fwd<R, K>(d, p, B, x, w, mats, coef, state, part_obs, out, store_final, s, tm, js, rn)
   QTM_KT_DISPATCH(p.kt, FWD_CALL)
 #undef FWD_CALL
   if (e != hipSuccess) return e;
@@ -296,11 +313,13 @@ hipError_t fused_backward(const DevCircuit &d, const DevPlan &p, int B, const do
   // bra term of observables with X or Y factors, added in the first sweep
   if ((e = launch_pauli_seed<R>(d, B, state_in ? state_in : state, lam, G, false, s)) != hipSuccess) return e;
 #define BWD_CALL(K) \
-  e = run_bwd<R, K>(d, p, B, G, mats, state, state_in, lam, part_grad, part_norm, s, tm, js, rn)
+  e = run_bwd<R, K>(d, p, B, G, mats, state, state_in, lam, part_grad, part_norm, coef, gocc, s, tm, js, rn)
   QTM_KT_DISPATCH(p.kt, BWD_CALL)
 #undef BWD_CALL
   if (e != hipSuccess) return e;
-  if (d.n_occ > 0 && p.n_gslots > 0) {
+  // (a specialised one-sweep backward over single-tile samples has written
+  // the per-rotation gradients itself)
+  if (d.n_occ > 0 && p.n_gslots > 0 && !(js && js->loaded && js->direct_grad)) {
     const int nwg = fused_wg_per_sample(d.n, p.kt);
     k_fused_grad_slot<<<dim3(p.n_gslots, B), 64, 0, s>>>(
         part_grad, part_norm, coef, p.gs_ptr, p.gs_occ, d.n_occ, p.n_gslots, nwg,

@@ -76,6 +76,8 @@ struct JitSweeps {
   std::vector<int32_t> gs_rows;  // per gradient slot: partial rows its sweep writes
   int32_t *gs_rows_dev = nullptr;
   bool direct_obs = false;      // the last forward sweep writes <Z_m> itself
+  bool direct_grad = false;     // the backward writes the per-rotation gradients itself
+  bool direct_prep = false;     // the forward prepares the gate matrices itself
   std::string name[2];          // kernel name per direction
   int device = -1;
   bool loaded = false;

@@ -263,33 +263,33 @@ __global__ void k_plain_grad_final(const double *__restrict__ part, int B, int n
 // order), with the chain-rule factor of a scaled angle w[j] * x[b][i]:
 // grad_w[j] = sum_b sum_{k in occ(w_j)} gocc[b][k] * (x[b][fac_k] or 1);
 // grad_x[b][i] = sum_{k in occ(x_i)} gocc[b][k] * (w[fac_k] or 1).
-// dL/dw_j = sum over the batch and over the occurrences of weight j: one
-// workgroup per weight, samples over the threads, fixed-order sums.
-__global__ void __launch_bounds__(256) k_scatter_w(const double *__restrict__ gocc, int B, int n_occ,
-                                                   const int32_t *__restrict__ w_ptr,
-                                                   const int32_t *__restrict__ w_list,
-                                                   const int32_t *__restrict__ w_fac,
-                                                   const double *__restrict__ x, int n_in,
-                                                   double *__restrict__ gw) {
-  __shared__ double sh[4];
-  const int j = blockIdx.x;
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < B; b += blockDim.x)
-    for (int e = w_ptr[j]; e < w_ptr[j + 1]; ++e) {
-      const int f = w_fac[e];
-      const double g = gocc[(int64_t)b * n_occ + w_list[e]];
-      acc += f < 0 ? g : g * x[(int64_t)b * n_in + f];
-    }
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) gw[j] = acc;
-}
-
-// dL/dx[b][i] = sum over the occurrences of input i (per sample).
-__global__ void k_scatter_x(const double *__restrict__ gocc, int B, int n_occ,
-                            const int32_t *__restrict__ x_ptr, const int32_t *__restrict__ x_list,
-                            const int32_t *__restrict__ x_fac, const double *__restrict__ w,
-                            int n_in, double *__restrict__ gx) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One launch: blocks [0, n_w) one per weight (samples over the threads,
+// fixed-order block sum), the blocks after them one thread per (sample,
+// input).
+__global__ void __launch_bounds__(256) k_scatter(const double *__restrict__ gocc, int B, int n_occ, int n_w,
+                                                 const int32_t *__restrict__ w_ptr,
+                                                 const int32_t *__restrict__ w_list,
+                                                 const int32_t *__restrict__ w_fac,
+                                                 const int32_t *__restrict__ x_ptr,
+                                                 const int32_t *__restrict__ x_list,
+                                                 const int32_t *__restrict__ x_fac, const double *__restrict__ x,
+                                                 const double *__restrict__ w, int n_in, double *__restrict__ gw,
+                                                 double *__restrict__ gx) {
+  if ((int)blockIdx.x < n_w) {
+    __shared__ double sh[4];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < B; b += blockDim.x)
+      for (int e = w_ptr[j]; e < w_ptr[j + 1]; ++e) {
+        const int f = w_fac[e];
+        const double g = gocc[(int64_t)b * n_occ + w_list[e]];
+        acc += f < 0 ? g : g * x[(int64_t)b * n_in + f];
+      }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) gw[j] = acc;
+    return;
+  }
+  const int64_t i = (int64_t)(blockIdx.x - n_w) * blockDim.x + threadIdx.x;
   if (i >= (int64_t)B * n_in) return;
   const int b = (int)(i / n_in), k = (int)(i % n_in);
   double acc = 0.0;
@@ -595,15 +595,13 @@ hipError_t launch_obs_final(const double *part, int B, int nblk, int M, double *
 
 hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, const double *x,
                           const double *w, double *gw, double *gx, hipStream_t s) {
-  if (d.n_weights > 0) {
-    k_scatter_w<<<d.n_weights, red_threads(B), 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, d.w_fac,
-                                                       x, d.n_inputs, gw);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (gx && d.n_inputs > 0)
-    k_scatter_x<<<nb((int64_t)B * d.n_inputs), kThreads, 0, s>>>(gocc, B, d.n_occ, d.x_ptr, d.x_list,
-                                                                d.x_fac, w, d.n_inputs, gx);
+  const unsigned threads = red_threads(B);
+  const int n_w = d.n_weights > 0 ? d.n_weights : 0;
+  const int64_t nx = gx && d.n_inputs > 0 ? (int64_t)B * d.n_inputs : 0;
+  const int64_t blocks = n_w + (nx + threads - 1) / threads;
+  if (blocks == 0) return hipSuccess;
+  k_scatter<<<(unsigned)blocks, threads, 0, s>>>(gocc, B, d.n_occ, n_w, d.w_ptr, d.w_list, d.w_fac, d.x_ptr,
+                                                d.x_list, d.x_fac, x, w, nx ? d.n_inputs : 0, gw, gx);
   return hipGetLastError();
 }
 

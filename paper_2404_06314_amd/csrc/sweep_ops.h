@@ -529,6 +529,15 @@ struct FwdArgs {
   const double *rn_prev = nullptr;
   int rn_prev_n = 0;
   double *rn_out = nullptr;
+  // specialised forward of a one-sweep plan over single-tile samples with a
+  // thread per block: the kernel prepares its sample's gate matrices itself
+  // (as k_fused_prep does) and writes them to mats_out, and the derivative
+  // coefficients to coef[B][n_occ][3] when coef is not NULL
+  const int32_t *blk = nullptr, *blk_off = nullptr;
+  const double *x = nullptr, *w = nullptr;
+  int n_in = 0, n_occ = 0;
+  void *mats_out = nullptr;
+  double *coef = nullptr;
 };
 
 
@@ -563,6 +572,12 @@ struct BwdArgs {
   // first sweep: psi is read from here instead of from psi (NULL: from psi);
   // the sweep still writes psi (one state buffer read, another written)
   const void *psi_in = nullptr;
+  // specialised backward of a one-sweep plan over single-tile samples: the
+  // per-rotation gradients gocc[B][n_occ] from the derivative coefficients
+  // coef[B][n_occ][3] (see k_fused_grad_slot)
+  const double *coef = nullptr;
+  double *gocc = nullptr;
+  int n_occ = 0;
 };
 
 // Sum over a workgroup of NT threads (a power of two) in FP64, in a fixed
