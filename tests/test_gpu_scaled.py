@@ -53,6 +53,23 @@ def test_random_scaled_circuits(precision, path):
             assert_parity(got, _ref(wl), precision, f"random scaled n{n} rep{rep} path{path}")
 
 
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+@pytest.mark.parametrize("n,d", [(10, 3), (12, 3), (12, 6)])
+def test_jit_single_tile_samples(precision, n, d):
+    """One sweep with a workgroup per sample (tile = n): the specialised
+    forward prepares its sample's gate matrices and derivative coefficients
+    (weight-scaled input angles included) and the backward writes the
+    per-rotation gradients, without the prep and slot-reduction launches."""
+    import paper_2404_06314_amd as q
+    wl = W.paper_workload(n, d, 6, seed=700 + 10 * n + d)
+    c = q.Circuit.from_workload(wl.circuit)
+    c.set_option(q.QTM_OPT_JIT, 1)
+    c.set_option(q.QTM_OPT_TILE_QUBITS, n)
+    assert len(c.plan(precision)["sweeps"]) == 1
+    got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, precision, qcirc=c)
+    assert_parity(got, _ref(wl), precision, f"paper n{n} d{d} jit single tile {precision}")
+
+
 def test_jit_sweeps():
     import paper_2404_06314_amd as q
     wl = W.paper_workload(14, 3, 8, seed=23)
@@ -62,13 +79,20 @@ def test_jit_sweeps():
     assert_parity(got, _ref(wl), "c64", "paper n14 d3 jit")
 
 
-@pytest.mark.parametrize("precision", ["c64", "c128"])
-def test_jacobian(precision):
+@pytest.mark.parametrize("precision,jit", [("c64", False), ("c128", False), ("c64", True), ("c128", True)])
+def test_jacobian(precision, jit):
+    """The Jacobian of the paper's ansatz (10 qubits, depth 2); with the
+    specialised sweeps the plan is one sweep over single-tile samples, whose
+    kernels prepare the gates and write the per-rotation gradients
+    themselves."""
     import torch
     import paper_2404_06314_amd as q
     from gpu_helpers import FLOOR_G_C128, TOL_G_C128, TOL_Z_C128
     wl = W.paper_workload(10, 2, 4, seed=31)
     c = q.Circuit.from_workload(wl.circuit)
+    if jit:
+        c.set_option(q.QTM_OPT_JIT, 1)
+        assert len(c.plan(precision)["sweeps"]) == 1
     xt = torch.as_tensor(wl.inputs, dtype=torch.float64, device="cuda:0")
     wt = torch.as_tensor(wl.weights, dtype=torch.float64, device="cuda:0")
     ev, jw, jx = c.jacobian(xt, wt, precision)
