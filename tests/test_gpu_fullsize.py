@@ -159,9 +159,10 @@ def test_c5_specialised_tile_loop(precision, tile, klo):
     c.set_option(q.QTM_OPT_LOW_QUBITS, klo)
     got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, precision, qcirc=c)
     assert_parity(got, ref, precision, f"c5 specialised {precision} kt{tile}")
-    if precision == "c64":
-        # the complex128 kernels of two sweeps spill a few hundred bytes at
-        # this size (double-precision amplitudes take twice the registers)
-        for direction in (0, 1):
-            for s in range(len(c.plan(precision)["sweeps"])):
-                assert c.jit_info(precision, direction, s)[1] <= 64
+    # no sweep kernel spills registers to scratch memory (the complex128
+    # backward kernels use up to ~350 of the 512 registers their one
+    # workgroup per compute unit allows)
+    for direction in (0, 1):
+        for s in range(len(c.plan(precision)["sweeps"])):
+            vg, sc = c.jit_info(precision, direction, s)
+            assert sc <= 64, (precision, direction, s, vg, sc)
