@@ -181,7 +181,7 @@ static hipError_t run_fwd(const DevCircuit &d, const DevPlan &p, int B, const do
     a.obs_sgn = p.obs_sgn_f;
     a.part_obs = part_obs;
     a.out = out;
-    if (js && js->loaded && js->direct_prep) {
+    if (sw == 0 && js && js->loaded && js->direct_prep) {
       a.blk = p.blk;
       a.blk_off = p.blk_off;
       a.x = x;

@@ -529,10 +529,10 @@ struct FwdArgs {
   const double *rn_prev = nullptr;
   int rn_prev_n = 0;
   double *rn_out = nullptr;
-  // specialised forward of a one-sweep plan over single-tile samples with a
-  // thread per block: the kernel prepares its sample's gate matrices itself
-  // (as k_fused_prep does) and writes them to mats_out, and the derivative
-  // coefficients to coef[B][n_occ][3] when coef is not NULL
+  // specialised first forward sweep with one workgroup per sample and a
+  // thread per fused block: the kernel prepares its sample's gate matrices
+  // itself (as k_fused_prep does) and writes them to mats_out, and the
+  // derivative coefficients to coef[B][n_occ][3] when coef is not NULL
   const int32_t *blk = nullptr, *blk_off = nullptr;
   const double *x = nullptr, *w = nullptr;
   int n_in = 0, n_occ = 0;
