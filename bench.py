@@ -275,6 +275,9 @@ def main():
     ap.add_argument("--greedy-plan", type=int, default=0, choices=[0, 1],
                     help="1: the greedy sweep plan for the specialised kernels (QTM_OPT_GREEDY_PLAN) "
                          "instead of the plan chosen for skipping zero tiles; implies --autotune 0")
+    ap.add_argument("--plan-io", type=int, default=12,
+                    help="HBM weight of a full-state sweep in the zero-skip planner's cost estimate "
+                         "(QTM_OPT_PLAN_IO, 1..64); other than 12 implies --autotune 0")
     ap.add_argument("--renorm", type=int, default=0,
                     help="periodic renormalisation every R sweeps (QTM_OPT_RENORM); implies --autotune 0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -331,6 +334,9 @@ def main():
     if args.greedy_plan:
         args.autotune = 0
         c.set_option(q.QTM_OPT_GREEDY_PLAN, 1)
+    if args.plan_io != 12:
+        args.autotune = 0
+        c.set_option(q.QTM_OPT_PLAN_IO, args.plan_io)
     if args.dense or args.renorm:
         args.autotune = 0
         c.set_option(q.QTM_OPT_DENSE_BLOCKS, args.dense)
@@ -342,8 +348,10 @@ def main():
         tuned = c.autotune(wl.batch, prec, cache=False)
         args.jit = tuned["jit"]
         args.greedy_plan = tuned.get("greedy", 0)
+        args.plan_io = tuned.get("io", 12)
         log(f"autotune ({time.perf_counter() - t0:.1f} s): tile {tuned['tile']} klo {tuned['klo']} "
-            f"jit {tuned['jit']} greedy plan {args.greedy_plan} ({len(tuned['candidates'])} candidates)")
+            f"jit {tuned['jit']} greedy plan {args.greedy_plan} plan io {args.plan_io} "
+            f"({len(tuned['candidates'])} candidates)")
     dev = torch.device("cuda:0")
     x = torch.as_tensor(wl.inputs, device=dev)
     w = torch.as_tensor(wl.weights, device=dev)
@@ -481,7 +489,7 @@ def main():
                    "observables": circ.n_obs, "precision": prec, "path": args.path,
                    "specialised_kernels": bool(args.jit and args.path == "fused"),
                    "tile_qubits": plan_kt, "low_qubits": plan_klo,
-                   "sweep_plan": "greedy" if (args.greedy_plan or not args.jit) else "zero-skip",
+                   "sweep_plan": "greedy" if (args.greedy_plan or not args.jit) else f"zero-skip, io {args.plan_io}",
                    "autotuned": tuned is not None, "dense_blocks": bool(args.dense),
                    "renorm_period": args.renorm},
         "roofline": roof,

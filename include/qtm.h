@@ -116,7 +116,13 @@ enum {
                               gate holds |0>): a search over tile sequences by an estimated cost
                               that counts only the tiles that run; the generic kernels take the
                               greedy plan.  1: the greedy plan (each sweep runs the most ops a
-                              tile allows) for both.  Results agree within rounding either way. */
+                              tile allows) for both.  Results agree within rounding either way. */,
+  QTM_OPT_PLAN_IO = 9      /* fused path, the zero-skip planning of QTM_OPT_GREEDY_PLAN = 0: the HBM
+                              traffic of a sweep over the whole state, forward and backward, in
+                              units of one fused block applied to the whole state, as the planner's
+                              cost estimate weighs it against the block work (1..64, default 12;
+                              larger values favour fewer, fuller sweeps).  The autotuner tries 8
+                              and 16 beside the default.  Results agree within rounding. */
 };
 
 /* One gate.  Rotations (RX, RY, RZ): q0 = qubit, src = QTM_SRC_INPUT or

@@ -166,6 +166,7 @@ struct qtm_circuit_s {
   std::map<std::tuple<int, int, int>, HostPlan> hplans;
   int jit = 0;  // QTM_OPT_JIT
   int greedy_plan = 0;  // QTM_OPT_GREEDY_PLAN
+  int plan_io = 12;     // QTM_OPT_PLAN_IO
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision, renorm, zero_skip)
   DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm, part_pauli;
   DevBuf jac_state, jac_G, jac_gw, jac_out, chk, rn;
@@ -261,9 +262,10 @@ int ensure_device(qtm_circuit_t c) {
   return QTM_OK;
 }
 
-// Whether the fused plans of this handle are chosen for kernels that skip
-// all-zero tiles (the specialised ones), see QTM_OPT_GREEDY_PLAN.
-int zero_skip_plan(const qtm_circuit_s *c) { return c->jit && !c->greedy_plan ? 1 : 0; }
+// How the fused plans of this handle are chosen: 0 greedy, > 0 for kernels
+// that skip all-zero tiles (the specialised ones) with that traffic weight,
+// see QTM_OPT_GREEDY_PLAN and QTM_OPT_PLAN_IO.
+int zero_skip_plan(const qtm_circuit_s *c) { return c->jit && !c->greedy_plan ? c->plan_io : 0; }
 
 int default_kt(const qtm_circuit_s *c, int precision) {
   int kt = c->tile_qubits > 0 ? c->tile_qubits : (precision == QTM_C128 ? 11 : 12);
@@ -283,7 +285,7 @@ int get_host_plan(qtm_circuit_t c, int precision, const HostPlan **out) {
   auto it = c->hplans.find(key);
   if (it == c->hplans.end()) {
     HostPlan hp;
-    std::string why = build_host_plan(c->desc, kt, klo, hp, zs != 0);
+    std::string why = build_host_plan(c->desc, kt, klo, hp, zs);
     if (!why.empty()) return fail(QTM_ERR_UNSUPPORTED, "internal planner error: " + why);
     it = c->hplans.emplace(key, std::move(hp)).first;
   }
@@ -732,6 +734,10 @@ int qtm_set_option(qtm_circuit_t c, int32_t option, int64_t value) {
     case QTM_OPT_GREEDY_PLAN:
       c->greedy_plan = value ? 1 : 0;
       return QTM_OK;
+    case QTM_OPT_PLAN_IO:
+      if (value < 1 || value > 64) return fail(QTM_ERR_INVALID_ARG, "QTM_OPT_PLAN_IO must be in 1..64");
+      c->plan_io = (int)value;
+      return QTM_OK;
     case QTM_OPT_CHECK_ANGLES:
       c->check_angles = value ? 1 : 0;
       return QTM_OK;
@@ -977,7 +983,7 @@ int qtm_plan_json(qtm_circuit_t c, int32_t precision, char *buf, size_t len, siz
     return fail(QTM_ERR_UNSUPPORTED, "controlled rotations run on the per-gate path only");
   const int kt = default_kt(c, precision);
   const int klo = std::min(c->low_qubits > 0 ? c->low_qubits : 5, kt);
-  Plan plan = make_plan(c->desc, kt, klo, zero_skip_plan(c) != 0);
+  Plan plan = make_plan(c->desc, kt, klo, zero_skip_plan(c));
   std::string why = check_plan(c->desc, plan);
   std::string js = plan_json(c->desc, plan);
   if (!why.empty()) {

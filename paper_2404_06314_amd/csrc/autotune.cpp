@@ -37,7 +37,7 @@ namespace qtm {
 namespace {
 
 struct Cand {
-  int kt, klo, jit, dense = 0, greedy = 0;
+  int kt, klo, jit, dense = 0, greedy = 0, io = 12;
   bool ok = false;
   double ms = 0.0;
   double err_z = 0.0, err_g = 0.0;
@@ -65,7 +65,7 @@ std::string cache_path() {
 }
 
 // The cache is a flat JSON array of {"key": ..., "tile": .., "klo": .., "jit": .., "ms": ..}.
-bool cache_lookup(const std::string &key, int &kt, int &klo, int &jit, int &dense, int &greedy) {
+bool cache_lookup(const std::string &key, int &kt, int &klo, int &jit, int &dense, int &greedy, int &io) {
   std::ifstream f(cache_path());
   if (!f) return false;
   std::stringstream ss;
@@ -84,10 +84,11 @@ bool cache_lookup(const std::string &key, int &kt, int &klo, int &jit, int &dens
   };
   if (!num("dense", dense)) dense = 0;
   if (!num("greedy", greedy)) greedy = 0;
+  if (!num("io", io)) io = 12;
   return num("tile", kt) && num("klo", klo) && num("jit", jit);
 }
 
-void cache_store(const std::string &key, int kt, int klo, int jit, int dense, int greedy, double ms) {
+void cache_store(const std::string &key, int kt, int klo, int jit, int dense, int greedy, int io, double ms) {
   static std::mutex mu;
   std::lock_guard<std::mutex> g(mu);
   const std::string path = cache_path();
@@ -112,8 +113,8 @@ void cache_store(const std::string &key, int kt, int klo, int jit, int dense, in
   char buf[512];
   snprintf(buf, sizeof buf,
            "{\"key\": \"%s\", \"tile\": %d, \"klo\": %d, \"jit\": %d, \"dense\": %d, \"greedy\": %d, "
-           "\"ms\": %.4f}",
-           key.c_str(), kt, klo, jit, dense, greedy, ms);
+           "\"io\": %d, \"ms\": %.4f}",
+           key.c_str(), kt, klo, jit, dense, greedy, io, ms);
   entries.push_back(buf);
   // create missing parent directories
   for (size_t k = 1; k < path.size(); ++k)
@@ -155,16 +156,17 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
   const std::string key = keybuf;
   std::ostringstream rep;
   rep << "{\"key\": \"" << key << "\"";
-  int kt = 0, klo = 0, jit = 0, dense = 0, greedy = 0;
-  if (use_cache && cache_lookup(key, kt, klo, jit, dense, greedy) &&
+  int kt = 0, klo = 0, jit = 0, dense = 0, greedy = 0, io = 12;
+  if (use_cache && cache_lookup(key, kt, klo, jit, dense, greedy, io) &&
       (!dense || qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, 1) == QTM_OK)) {
     qtm_set_option(c, QTM_OPT_PATH, QTM_PATH_FUSED);
     qtm_set_option(c, QTM_OPT_TILE_QUBITS, kt);
     qtm_set_option(c, QTM_OPT_LOW_QUBITS, klo);
     qtm_set_option(c, QTM_OPT_JIT, jit);
     qtm_set_option(c, QTM_OPT_GREEDY_PLAN, greedy);
+    qtm_set_option(c, QTM_OPT_PLAN_IO, io);
     rep << ", \"cached\": true, \"tile\": " << kt << ", \"klo\": " << klo << ", \"jit\": " << jit
-        << ", \"dense\": " << dense << ", \"greedy\": " << greedy << "}";
+        << ", \"dense\": " << dense << ", \"greedy\": " << greedy << ", \"io\": " << io << "}";
     report = rep.str();
     return QTM_OK;
   }
@@ -213,6 +215,7 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
   qtm_set_option(c, QTM_OPT_JIT, 0);
   qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, 0);
   qtm_set_option(c, QTM_OPT_GREEDY_PLAN, 0);
+  qtm_set_option(c, QTM_OPT_PLAN_IO, 12);
   if ((rc = run(QTM_C128, &ref))) return rc;
   const double tol_z = precision == QTM_C128 ? 1e-12 : 1e-5;
   const double tol_g = precision == QTM_C128 ? 1e-10 : 1e-4;
@@ -238,6 +241,7 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
     qtm_set_option(c, QTM_OPT_LOW_QUBITS, cd.klo);
     qtm_set_option(c, QTM_OPT_JIT, cd.jit);
     qtm_set_option(c, QTM_OPT_GREEDY_PLAN, cd.greedy);
+    qtm_set_option(c, QTM_OPT_PLAN_IO, cd.io);
     if (qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, cd.dense) != QTM_OK) return QTM_ERR_UNSUPPORTED;
     std::vector<double> got;
     int r = run(precision, &got);
@@ -267,8 +271,8 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
   auto measure = [&](Cand &cd) -> int {
     const int r = measure_one(cd);
     if (log)
-      fprintf(stderr, "autotune: tile %d klo %d jit %d greedy %d dense %d: %s %.4f ms (err z %.2e, g %.2e)\n",
-              cd.kt, cd.klo, cd.jit, cd.greedy, cd.dense, r ? "error" : cd.ok ? "ok" : "rejected", cd.ms,
+      fprintf(stderr, "autotune: tile %d klo %d jit %d greedy %d io %d dense %d: %s %.4f ms (err z %.2e, g %.2e)\n",
+              cd.kt, cd.klo, cd.jit, cd.greedy, cd.io, cd.dense, r ? "error" : cd.ok ? "ok" : "rejected", cd.ms,
               cd.err_z, cd.err_g);
     return r;
   };
@@ -290,16 +294,21 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
       if ((rc = measure(j))) break;
       cands.push_back(j);
     }
-    // the fastest specialised configuration with the greedy plan instead of
-    // the plan chosen for skipping zero tiles (the planner's cost estimate
-    // can misjudge a circuit)
+    // the fastest specialised configuration with the greedy plan, and with
+    // zero-skip plans that weigh a full-state sweep's traffic at 8 and 16
+    // blocks instead of 12 (the planner's cost estimate can misjudge a
+    // circuit or a machine)
     {
       const Cand *fj = nullptr;
       for (const Cand &cd : cands)
         if (cd.ok && cd.jit && (!fj || cd.ms < fj->ms)) fj = &cd;
-      if (!rc && fj) {
-        Cand g{fj->kt, fj->klo, 1, 0, 1};
-        if (!(rc = measure(g))) cands.push_back(g);
+      if (fj) {
+        const int fkt = fj->kt, fklo = fj->klo;
+        for (const Cand &v : {Cand{fkt, fklo, 1, 0, 1}, Cand{fkt, fklo, 1, 0, 0, 8}, Cand{fkt, fklo, 1, 0, 0, 16}}) {
+          Cand g = v;
+          if (rc || (rc = measure(g))) break;
+          cands.push_back(g);
+        }
       }
     }
     // the shared-weight dense-block forward, with the backward of the
@@ -308,11 +317,12 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
     for (const Cand &cd : cands)
       if (cd.ok && (!f || cd.ms < f->ms)) f = &cd;
     if (!rc && f && precision == QTM_C64 && qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, 1) == QTM_OK) {
-      Cand k9{f->kt, f->klo, f->jit, 1, f->greedy};
+      Cand k9{f->kt, f->klo, f->jit, 1, f->greedy, f->io};
       if (!(rc = measure(k9))) cands.push_back(k9);
     }
     qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, 0);
     qtm_set_option(c, QTM_OPT_GREEDY_PLAN, 0);
+    qtm_set_option(c, QTM_OPT_PLAN_IO, 12);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -335,10 +345,10 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
     const Cand &cd = cands[k];
     char b[256];
     snprintf(b, sizeof b,
-             "%s{\"tile\": %d, \"klo\": %d, \"jit\": %d, \"dense\": %d, \"greedy\": %d, \"ok\": %s, "
-             "\"ms\": %.4f, \"err_z\": %.3e, \"err_g\": %.3e}",
-             k ? ", " : "", cd.kt, cd.klo, cd.jit, cd.dense, cd.greedy, cd.ok ? "true" : "false", cd.ms, cd.err_z,
-             cd.err_g);
+             "%s{\"tile\": %d, \"klo\": %d, \"jit\": %d, \"dense\": %d, \"greedy\": %d, \"io\": %d, "
+             "\"ok\": %s, \"ms\": %.4f, \"err_z\": %.3e, \"err_g\": %.3e}",
+             k ? ", " : "", cd.kt, cd.klo, cd.jit, cd.dense, cd.greedy, cd.io, cd.ok ? "true" : "false", cd.ms,
+             cd.err_z, cd.err_g);
     rep << b;
   }
   rep << "]";
@@ -348,6 +358,7 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
     qtm_set_option(c, QTM_OPT_LOW_QUBITS, 0);
     qtm_set_option(c, QTM_OPT_JIT, 0);
     qtm_set_option(c, QTM_OPT_GREEDY_PLAN, 0);
+    qtm_set_option(c, QTM_OPT_PLAN_IO, 12);
     rep << ", \"tile\": 0, \"klo\": 0, \"jit\": 0}";
     report = rep.str();
     return QTM_ERR_UNSUPPORTED;
@@ -358,10 +369,12 @@ int autotune(qtm_circuit_t c, const TuneInfo &info, int32_t batch, int32_t preci
   qtm_set_option(c, QTM_OPT_JIT, win->jit);
   qtm_set_option(c, QTM_OPT_DENSE_BLOCKS, win->dense);
   qtm_set_option(c, QTM_OPT_GREEDY_PLAN, win->greedy);
+  qtm_set_option(c, QTM_OPT_PLAN_IO, win->io);
   rep << ", \"tile\": " << win->kt << ", \"klo\": " << win->klo << ", \"jit\": " << win->jit
-      << ", \"dense\": " << win->dense << ", \"greedy\": " << win->greedy << ", \"ms\": " << win->ms << "}";
+      << ", \"dense\": " << win->dense << ", \"greedy\": " << win->greedy << ", \"io\": " << win->io
+      << ", \"ms\": " << win->ms << "}";
   report = rep.str();
-  if (use_cache) cache_store(key, win->kt, win->klo, win->jit, win->dense, win->greedy, win->ms);
+  if (use_cache) cache_store(key, win->kt, win->klo, win->jit, win->dense, win->greedy, win->io, win->ms);
   return QTM_OK;
 }
 

@@ -345,11 +345,12 @@ std::vector<uint64_t> greedy_tiles(Sched S, int nq, int kt, int klo) {
 // blocks one after another); each sweep adds a launch.  The constants are
 // MI355X measurements of the complex64 sweeps at 20 qubits, batch 64: about
 // 44 us per block over the whole state (forward + backward), 530 us of
-// traffic per full-state sweep pair.
-double sweep_cost(double live, int blocks) {
-  constexpr double kSweepIo = 12.0, kOverlap = 0.3, kLatency = 0.03, kLaunch = 0.25;
+// traffic per full-state sweep pair (io = 12, the default of
+// QTM_OPT_PLAN_IO, which the autotuner varies).
+double sweep_cost(double live, int blocks, double io) {
+  constexpr double kOverlap = 0.3, kLatency = 0.03, kLaunch = 0.25;
   const double b = blocks;
-  const double full = std::max(kSweepIo, b) + kOverlap * std::min(kSweepIo, b);
+  const double full = std::max(io, b) + kOverlap * std::min(io, b);
   return std::max(live * full, kLatency * b) + kLaunch;
 }
 
@@ -379,14 +380,14 @@ int count_blocks(const std::vector<FOp> &ops, const std::vector<int> &order) {
   return b;
 }
 
-double tiles_cost(Sched S, const std::vector<uint64_t> &tiles, int nq, int kt) {
+double tiles_cost(Sched S, const std::vector<uint64_t> &tiles, int nq, int kt, double io) {
   double cost = 0.0;
   uint64_t ex = 0;
   for (uint64_t m : tiles) {
     std::vector<char> T(nq, 0);
     for (int q = 0; q < nq; ++q) T[q] = (m >> q) & 1;
     const std::vector<int> order = S.run(T, nullptr, true, kMaxSweepBlocks);
-    cost += sweep_cost(live_fraction(ex, m, nq, kt), count_blocks(S.ops, order));
+    cost += sweep_cost(live_fraction(ex, m, nq, kt), count_blocks(S.ops, order), io);
     ex |= excited_by(S.ops, order);
   }
   return cost;
@@ -398,10 +399,10 @@ double tiles_cost(Sched S, const std::vector<uint64_t> &tiles, int nq, int kt) {
 // greedy planner's maximal sweeps.  Candidates per step: the greedy tile,
 // and the greedy tile with one, or two, unexcited qubits kept out of it.
 // Returns the greedy sequence when the search finds nothing cheaper.
-std::vector<uint64_t> zero_aware_tiles(const Sched &S0, int nq, int kt, int klo) {
+std::vector<uint64_t> zero_aware_tiles(const Sched &S0, int nq, int kt, int klo, double io) {
   const std::vector<uint64_t> greedy = greedy_tiles(S0, nq, kt, klo);
   if (nq <= kt) return greedy;
-  const double greedy_cost = tiles_cost(S0, greedy, nq, kt);
+  const double greedy_cost = tiles_cost(S0, greedy, nq, kt, io);
   constexpr int kWidth = 8, kTopSingles = 5, kMaxDepth = 64;
   constexpr double kPerBlockLeft = 1.2;  // ranking: estimated cost of the blocks not yet run
   struct Node {
@@ -461,7 +462,7 @@ std::vector<uint64_t> zero_aware_tiles(const Sched &S0, int nq, int kt, int klo)
         if (order.empty()) continue;
         const int nb = count_blocks(S0.ops, order);
         Node c;
-        c.cost = nd.cost + sweep_cost(live_fraction(nd.ex, m, nq, kt), nb);
+        c.cost = nd.cost + sweep_cost(live_fraction(nd.ex, m, nq, kt), nb, io);
         c.ex = nd.ex | excited_by(S0.ops, order);
         c.n_done = nd.n_done + order.size();
         c.blocks_left = nd.blocks_left - nb;
@@ -498,7 +499,7 @@ std::vector<uint64_t> zero_aware_tiles(const Sched &S0, int nq, int kt, int klo)
 
 }  // namespace
 
-Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo, bool zero_skip) {
+Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo, int32_t zero_skip) {
   Plan p;
   p.n = c.n;
   p.kt = kt;
@@ -521,7 +522,7 @@ Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo, bool zero_skip) {
   Sched S{p.ops, succ, left, std::vector<char>(p.ops.size(), 0)};
   // tiles: the klo low qubits plus kt - klo others per sweep
   const std::vector<uint64_t> tiles =
-      zero_skip ? zero_aware_tiles(S, c.n, kt, p.klo) : greedy_tiles(S, c.n, kt, p.klo);
+      zero_skip > 0 ? zero_aware_tiles(S, c.n, kt, p.klo, zero_skip) : greedy_tiles(S, c.n, kt, p.klo);
   for (uint64_t tm : tiles) {
     std::vector<char> T(c.n, 0);
     for (int q = 0; q < c.n; ++q) T[q] = (tm >> q) & 1;
@@ -868,7 +869,7 @@ Program encode_program(const CircuitDesc &c, const Plan &p) {
   return pr;
 }
 
-std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostPlan &out, bool zero_skip) {
+std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostPlan &out, int32_t zero_skip) {
   Plan plan = make_plan(c, kt, klo, zero_skip);
   std::string why = check_plan(c, plan);
   if (!why.empty()) return why;
@@ -876,7 +877,7 @@ std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostP
   h.prog = encode_program(c, plan);
   h.kt = kt;
   h.klo = klo;
-  h.zero_skip = zero_skip ? 1 : 0;
+  h.zero_skip = zero_skip;
   h.n_blocks = plan.n_blocks;
   h.n_gslots = plan.n_gslots;
   h.max_gslots = h.prog.max_gslots_per_sweep;

@@ -126,10 +126,12 @@ int validate_and_build(int32_t n, const Gate *gates, int32_t n_gates, int32_t n_
                        int32_t n_obs, CircuitDesc &out, std::string &err);
 
 // Plan the fused path for tile size kt (<= n) with klo contiguous low qubits.
-// zero_skip: plan for kernels that skip all-zero tiles (the sweeps' tiles
-// are chosen by an estimated cost that counts only the tiles that run);
-// otherwise each sweep takes the tile that runs the most ops.
-Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo, bool zero_skip = false);
+// zero_skip > 0: plan for kernels that skip all-zero tiles (the sweeps'
+// tiles are chosen by an estimated cost that counts only the tiles that
+// run, with zero_skip the HBM traffic of a full-state sweep pair in units of
+// one fused block applied to the whole state); 0: each sweep takes the tile
+// that runs the most ops.
+Plan make_plan(const CircuitDesc &c, int32_t kt, int32_t klo, int32_t zero_skip = 0);
 
 // Check the plan's invariants (each gate scheduled once, dependency order,
 // stage/tile membership).  Returns "" when valid.
@@ -159,7 +161,7 @@ Program encode_program(const CircuitDesc &c, const Plan &p);
 // occurrence -> gradient slot map and the two sign tables.
 struct HostPlan {
   int32_t kt = 0, klo = 0, n_blocks = 0, n_gslots = 0, max_gslots = 0, n_sweeps = 0;
-  int32_t zero_skip = 0;  // planned for kernels that skip all-zero tiles
+  int32_t zero_skip = 0;  // > 0: planned for kernels that skip all-zero tiles (make_plan)
   Program prog;
   std::vector<int32_t> blk;        // per block: [q, ng, (type, src, idx, widx, occ) x ng]
   std::vector<int32_t> blk_off;    // block -> offset in blk
@@ -170,6 +172,6 @@ struct HostPlan {
 
 // Plan, check and encode.  Returns "" or the planner's error.
 std::string build_host_plan(const CircuitDesc &c, int32_t kt, int32_t klo, HostPlan &out,
-                            bool zero_skip = false);
+                            int32_t zero_skip = 0);
 
 }  // namespace qtm

@@ -99,14 +99,14 @@ void exercise(const Spec &s, const std::string &name, bool all_tiles) {
   const int kmax = std::min(d.n, kMaxTileQubits);
   for (int kt = all_tiles ? kMinTileQubits : kmax; kt <= kmax; ++kt)
     for (int klo = 0; klo <= std::min(kt, 7); klo += (all_tiles ? 1 : 3))
-      for (int zs = 0; zs < 2; ++zs) {
+      for (int zs : {0, 12}) {
       const std::string tag = name + " kt=" + std::to_string(kt) + " klo=" + std::to_string(klo) +
                               " zero_skip=" + std::to_string(zs);
-      Plan p = make_plan(d, kt, klo, zs != 0);
+      Plan p = make_plan(d, kt, klo, zs);
       check(check_plan(d, p).empty(), tag + ": check_plan");
       check(!plan_json(d, p).empty(), tag + ": plan_json");
       HostPlan hp;
-      const std::string why = build_host_plan(d, kt, klo, hp, zs != 0);
+      const std::string why = build_host_plan(d, kt, klo, hp, zs);
       check(why.empty(), tag + ": build_host_plan: " + why);
       if (!why.empty()) continue;
       for (int dbl = 0; dbl < 2; ++dbl) {

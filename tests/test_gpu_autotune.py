@@ -24,16 +24,18 @@ def test_autotune_installs_fastest_passing_candidate(tmp_path, monkeypatch, prec
     fastest = min(x["ms"] for x in ok)
     near = [x for x in ok if x["ms"] <= fastest * 1.03]
     best = max(near, key=lambda x: (x["klo"], x["tile"], -x["ms"]))
-    assert (rep["tile"], rep["klo"], rep["jit"], rep["greedy"]) == \
-        (best["tile"], best["klo"], best["jit"], best["greedy"])
+    assert (rep["tile"], rep["klo"], rep["jit"], rep["greedy"], rep["io"]) == \
+        (best["tile"], best["klo"], best["jit"], best["greedy"], best["io"])
     assert any(x["jit"] == 1 for x in rep["candidates"])
-    # the fastest specialised configuration is also timed with the greedy plan
+    # the fastest specialised configuration is also timed with the greedy
+    # plan and with the zero-skip planner's other traffic weights
     assert any(x["jit"] == 1 and x["greedy"] == 1 for x in rep["candidates"])
+    assert {8, 16} <= {x["io"] for x in rep["candidates"] if x["jit"] == 1}
     rng = np.random.default_rng(7)
     wl = W.random_workload(rng, circ, B)
     got = run_gpu(circ, wl.inputs, wl.weights, wl.grad_out, precision, qcirc=c)
     assert_parity(got, oracle.vjp(circ, wl.inputs, wl.weights, wl.grad_out), precision, "tuned")
     c2 = q.Circuit.from_workload(circ)
     rep2 = c2.autotune(B, precision)
-    assert rep2["cached"] and (rep2["tile"], rep2["klo"], rep2["jit"], rep2["greedy"]) == \
-        (best["tile"], best["klo"], best["jit"], best["greedy"])
+    assert rep2["cached"] and (rep2["tile"], rep2["klo"], rep2["jit"], rep2["greedy"], rep2["io"]) == \
+        (best["tile"], best["klo"], best["jit"], best["greedy"], best["io"])

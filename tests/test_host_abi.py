@@ -336,3 +336,27 @@ def test_missing_library_raises_instead_of_falling_back(qtm, monkeypatch, tmp_pa
     wl = W.config_workload("c1")
     with pytest.raises(ImportError):
         qtm.Circuit.from_workload(wl.circuit)
+
+
+def test_plan_io_option(qtm):
+    """QTM_OPT_PLAN_IO (the weight of a full-state sweep's HBM traffic in the
+    zero-skip planner's cost estimate) accepts 1..64; every weight gives a
+    plan that schedules each gate once, and at n = 20 a heavier weight gives
+    no more sweeps than a lighter one."""
+    import ctypes
+    circ = W.config_workload("c3").circuit
+    sweeps = {}
+    for io in (1, 8, 12, 16, 64):
+        c = qtm.Circuit.from_workload(circ)
+        c.set_option(qtm.QTM_OPT_TILE_QUBITS, 12)
+        c.set_option(qtm.QTM_OPT_LOW_QUBITS, 4)
+        c.set_option(qtm.QTM_OPT_JIT, 1)
+        c.set_option(qtm.QTM_OPT_PLAN_IO, io)
+        p = c.plan("c64")
+        assert sorted(_plan_gate_order(p)) == list(range(circ.n_gates))
+        sweeps[io] = len(p["sweeps"])
+    assert sweeps[16] <= sweeps[8] <= sweeps[1], sweeps
+    lib = qtm._lib.load()
+    c = qtm.Circuit.from_workload(circ)
+    for bad in (0, 65, -3):
+        assert lib.qtm_set_option(c.handle, qtm.QTM_OPT_PLAN_IO, bad) == qtm._lib.QTM_ERR_INVALID_ARG
