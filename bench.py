@@ -220,6 +220,7 @@ def bench_jacobian(args, c, wl, prec, x, w, G, state, tuned):
     psi across the M bras could at most save."""
     import torch
     import workloads as W
+    import paper_2404_06314_amd as q
 
     def timed(fn, reps):
         for _ in range(max(1, args.warmup)):
@@ -232,6 +233,8 @@ def bench_jacobian(args, c, wl, prec, x, w, G, state, tuned):
         return (time.perf_counter() - t0) * 1e3 / reps
 
     M = wl.circuit.n_obs
+    if args.jac_chunk:
+        c.set_option(q.QTM_OPT_JAC_CHUNK, args.jac_chunk)
     fwd_ms = timed(lambda: c.forward(x, w, prec, state=state), args.steps)
 
     def vjp():
@@ -246,7 +249,7 @@ def bench_jacobian(args, c, wl, prec, x, w, G, state, tuned):
     out = {"metric": "full Jacobian (B, M, |Theta|) ms per batch", "value": round(jac_ms, 3),
            "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": prec, "data": "synthetic",
            "config": {"workload": W.WORKLOAD_NAMES[args.config], "batch": wl.batch, "observables": M,
-                      "autotuned": tuned is not None},
+                      "observables_per_pass": args.jac_chunk or "auto", "autotuned": tuned is not None},
            "forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
            "ratio_to_M_backward": round(jac_ms / (M * bwd_ms), 4),
            "ratio_to_forward_plus_M_backward": round(jac_ms / (fwd_ms + M * bwd_ms), 4)}
@@ -291,6 +294,8 @@ def main():
     ap.add_argument("--jacobian", action="store_true",
                     help="time the full Jacobian (qtm_jacobian) of the workload against one forward "
                          "and one backward pass; one JSON line")
+    ap.add_argument("--jac-chunk", type=int, default=0,
+                    help="with --jacobian: observables per adjoint pass (0: the library's choice)")
     ap.add_argument("--digest", default="",
                     help="print the digest of the sources of this kernel (traffic records refer to it)")
     args = ap.parse_args()
@@ -574,8 +579,28 @@ def bench_paper_shapes(args):
                     "evals_per_s": round(B / ((tf + tb) / 1e3), 1),
                     "ms_step_graph": round(tg, 4), "evals_per_s_graph": round(B / (tg / 1e3), 1),
                     "dtype": prec, "specialised_kernels": bool(args.jit)}
+            msg = ""
+            if sw == "tab1":
+                # the paper's reverse gradient returns the full Jacobian
+                # (B, M, |Theta|): every observable in one adjoint pass (the
+                # default at these sizes) against one pass per observable
+                def jac_ms(k):
+                    c.set_option(q.QTM_OPT_JAC_CHUNK, k)
+                    for _ in range(max(args.warmup, 1)):
+                        c.jacobian(x, w, prec)
+                    torch.cuda.synchronize()
+                    ev[0].record()
+                    for _ in range(args.steps):
+                        c.jacobian(x, w, prec)
+                    ev[1].record()
+                    ev[1].synchronize()
+                    return ev[0].elapsed_time(ev[1]) / args.steps
+                tj, tj1 = jac_ms(0), jac_ms(1)
+                line["ms_jacobian"] = round(tj, 4)
+                line["ms_jacobian_one_observable_per_pass"] = round(tj1, 4)
+                msg = f"; Jacobian {tj:.3f} ms (one observable per pass: {tj1:.3f} ms)"
             print(json.dumps(line), flush=True)
-            log(f"{sw} n={n} d={d} M={M}: fwd {tf:.3f} ms, bwd {tb:.3f} ms; graph-launched step {tg:.3f} ms")
+            log(f"{sw} n={n} d={d} M={M}: fwd {tf:.3f} ms, bwd {tb:.3f} ms; graph-launched step {tg:.3f} ms{msg}")
             del graph
             c.close()
 

@@ -122,7 +122,12 @@ enum {
                               units of one fused block applied to the whole state, as the planner's
                               cost estimate weighs it against the block work (1..64, default 12;
                               larger values favour fewer, fuller sweeps).  The autotuner tries 8
-                              and 16 beside the default.  Results agree within rounding. */
+                              and 16 beside the default.  Results agree within rounding. */,
+  QTM_OPT_JAC_CHUNK = 10   /* qtm_jacobian: observables per adjoint pass, 1..65535 (capped at
+                              n_obs and at 65535 / batch rows).  0 (default): as many as keep one
+                              pass's copies of the final states within 64 MiB, so one per pass
+                              for batches whose states exceed that.  Results agree within
+                              rounding for every value. */
 };
 
 /* One gate.  Rotations (RX, RY, RZ): q0 = qubit, src = QTM_SRC_INPUT or
@@ -233,9 +238,15 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
                  double *grad_weights, double *grad_inputs, void *stream);
 
 /* Full Jacobian of the expectation values (the paper's (B, M, |Theta|)
- * result, Sec. II-A, Eq. (5)-(6)): forward once, then one adjoint backward
- * per observable m with the upstream gradient e_m, each restarted from a
- * saved copy of the final states (library workspace: two state buffers).
+ * result, Sec. II-A, Eq. (5)-(6)): forward once, then adjoint backward passes
+ * with one-hot upstream gradients e_m.  A pass takes k observables
+ * (QTM_OPT_JAC_CHUNK) over k x batch rows, row r being sample r mod batch
+ * with observable m0 + r / batch, and starts from k copies of the final
+ * states; with k = 1 it reads them in place.  Library workspace: the final
+ * states plus two buffers of k x batch states (and k copies of the inputs).
+ * Every row's gradient is computed by the same kernels as in a
+ * one-observable pass; a pass of k > 1 prepares its own gate matrices for
+ * the repeated input rows.
  *   expvals      dev [batch][n_obs] float64, overwritten; may be NULL
  *   jac_weights  dev [batch][n_obs][n_weights] float64: d<O_m>(sample b)/dw_j
  *                (per sample, not summed over the batch)

@@ -16,7 +16,7 @@ from ._lib import (QTM_C64, QTM_C128, QTM_CNOT, QTM_CZ, QTM_PATH_AUTO, QTM_PATH_
                    QTM_PATH_PLAIN, QTM_RX, QTM_RY, QTM_RZ, QTM_SRC_INPUT, QTM_SRC_NONE,
                    QTM_SRC_SCALED, QTM_SRC_WEIGHT, QTM_OPT_LOW_QUBITS, QTM_OPT_PATH, QTM_OPT_RENORM,
                    QTM_OPT_TILE_QUBITS, QTM_OPT_TIMING, QTM_OPT_JIT, QTM_OPT_CHECK_ANGLES, QTM_OPT_DENSE_BLOCKS,
-                   QTM_OPT_GREEDY_PLAN, QTM_OPT_PLAN_IO, QtmError)
+                   QTM_OPT_GREEDY_PLAN, QTM_OPT_PLAN_IO, QTM_OPT_JAC_CHUNK, QtmError)
 
 __all__ = ["Circuit", "Multi", "QtmError", "precision_code", "lib_path",
            "QTM_C64", "QTM_C128", "QTM_PATH_AUTO", "QTM_PATH_PLAIN", "QTM_PATH_FUSED"]

@@ -30,6 +30,7 @@ QTM_OPT_CHECK_ANGLES = 6
 QTM_OPT_DENSE_BLOCKS = 7
 QTM_OPT_GREEDY_PLAN = 8
 QTM_OPT_PLAN_IO = 9
+QTM_OPT_JAC_CHUNK = 10
 
 # every exported function of include/qtm.h: name -> (restype, argtypes)
 _P = ctypes.c_void_p

@@ -167,9 +167,10 @@ struct qtm_circuit_s {
   int jit = 0;  // QTM_OPT_JIT
   int greedy_plan = 0;  // QTM_OPT_GREEDY_PLAN
   int plan_io = 12;     // QTM_OPT_PLAN_IO
+  int jac_chunk = 0;    // QTM_OPT_JAC_CHUNK
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<JitSweeps>> jits;  // (kt, klo, precision, renorm, zero_skip)
   DevBuf cs, part, gocc, lam, state_ws, mats, coef, part_obs, part_grad, part_norm, part_pauli;
-  DevBuf jac_state, jac_G, jac_gw, jac_out, chk, rn;
+  DevBuf jac_state, jac_G, jac_gw, jac_out, jac_x, chk, rn;
   // shared-weight dense-block forward (QTM_OPT_DENSE_BLOCKS)
   int k9 = 0;
   K9Layout k9l;
@@ -190,7 +191,8 @@ struct qtm_circuit_s {
 
   std::vector<DevBuf *> bufs() {
     return {&cs, &part, &gocc, &lam, &state_ws, &mats, &coef, &part_obs, &part_grad, &part_norm,
-            &part_pauli, &jac_state, &jac_G, &jac_gw, &jac_out, &chk, &rn, &k9_tab, &k9_rx, &k9_part};
+            &part_pauli, &jac_state, &jac_G, &jac_gw, &jac_out, &jac_x, &chk, &rn, &k9_tab, &k9_rx,
+            &k9_part};
   }
   qtm_circuit_s() {
     for (DevBuf *b : bufs()) b->total = &ws_total;
@@ -738,6 +740,10 @@ int qtm_set_option(qtm_circuit_t c, int32_t option, int64_t value) {
       if (value < 1 || value > 64) return fail(QTM_ERR_INVALID_ARG, "QTM_OPT_PLAN_IO must be in 1..64");
       c->plan_io = (int)value;
       return QTM_OK;
+    case QTM_OPT_JAC_CHUNK:
+      if (value < 0 || value > 65535) return fail(QTM_ERR_INVALID_ARG, "QTM_OPT_JAC_CHUNK must be in 0..65535");
+      c->jac_chunk = (int)value;
+      return QTM_OK;
     case QTM_OPT_CHECK_ANGLES:
       c->check_angles = value ? 1 : 0;
       return QTM_OK;
@@ -900,6 +906,23 @@ int qtm_backward(qtm_circuit_t c, int32_t batch, int32_t precision, const double
                       grad_inputs, prepped, s);
 }
 
+namespace {
+// Observables per adjoint pass of qtm_jacobian: QTM_OPT_JAC_CHUNK, else as
+// many as keep one pass's repeated final states within kJacPassBytes (at
+// least one); the rows of a pass stay within a grid dimension.  A batch
+// whose states alone exceed that fills the GPU in a pass of its own, and
+// repeating its states would only add copies (n = 20, batch 64: 36.8 ms with
+// one observable per pass, 39.9 ms with two); small batches gain (n = 12,
+// batch 48, 32 observables: 0.24 ms in one pass, 1.43 ms in 32).
+constexpr size_t kJacPassBytes = (size_t)64 << 20;
+int jacobian_chunk(const qtm_circuit_s *c, int32_t batch, size_t sbytes) {
+  const int M = c->dev.n_obs;
+  int64_t k = c->jac_chunk > 0 ? c->jac_chunk : (int64_t)(kJacPassBytes / std::max<size_t>(sbytes, 1));
+  k = std::min<int64_t>(k, 65535 / batch);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(k, M));
+}
+}  // namespace
+
 int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double *inputs,
                  const double *weights, double *expvals, double *jac_weights, double *jac_inputs,
                  void *stream) {
@@ -915,23 +938,44 @@ int qtm_jacobian(qtm_circuit_t c, int32_t batch, int32_t precision, const double
   const DevCircuit &d = c->dev;
   const int M = d.n_obs;
   const size_t sbytes = ((size_t)batch << cd.n) * elem_bytes(precision);
-  if ((rc = c->state_ws.ensure(sbytes)) || (rc = c->jac_state.ensure(sbytes)) ||
-      (rc = c->jac_G.ensure((size_t)batch * M * sizeof(double))) ||
+  const int k = jacobian_chunk(c, batch, sbytes);
+  const size_t xbytes = (size_t)batch * cd.n_inputs * sizeof(double);
+  if ((rc = c->state_ws.ensure(sbytes * k)) || (rc = c->jac_state.ensure(sbytes)) ||
+      (rc = c->jac_G.ensure((size_t)batch * k * M * sizeof(double))) ||
       (rc = c->jac_gw.ensure((size_t)std::max(cd.n_weights, 1) * sizeof(double))) ||
-      (rc = c->jac_out.ensure((size_t)batch * M * sizeof(double))))
+      (rc = c->jac_out.ensure((size_t)batch * M * sizeof(double))) ||
+      (k > 1 && xbytes > 0 && (rc = c->jac_x.ensure(xbytes * k))))
     return rc;
   double *out = expvals ? expvals : (double *)c->jac_out.p;
-  // the forward leaves the final states in jac_state; every adjoint pass
-  // reads them there and works in state_ws (no copies between the passes)
+  // the forward leaves the final states in jac_state
   if ((rc = do_forward(c, batch, precision, inputs, weights, out, c->jac_state.p, true, s))) return rc;
   hipError_t e;
-  for (int m = 0; m < M; ++m) {
-    if ((e = launch_onehot((double *)c->jac_G.p, batch, M, m, s))) return hip_fail(e, "jacobian seed");
-    if ((rc = run_backward(c, batch, precision, inputs, weights, (double *)c->jac_G.p, c->state_ws.p,
-                           c->jac_state.p, (double *)c->jac_gw.p, nullptr, true, s)))
-      return rc;
-    if ((e = launch_scatter_jac(d, batch, (double *)c->gocc.p, inputs, weights, m, jac_weights,
-                                  jac_inputs, s)))
+  for (int m0 = 0; m0 < M; m0 += k) {
+    const int kk = std::min(k, M - m0), rows = kk * batch;
+    if ((e = launch_onehot((double *)c->jac_G.p, rows, batch, M, m0, s))) return hip_fail(e, "jacobian seed");
+    if (kk == 1) {
+      // one observable: the pass reads the final states in jac_state and
+      // works in state_ws (nothing copied)
+      if ((rc = run_backward(c, batch, precision, inputs, weights, (double *)c->jac_G.p, c->state_ws.p,
+                             c->jac_state.p, (double *)c->jac_gw.p, nullptr, true, s)))
+        return rc;
+    } else {
+      // kk observables in one pass over kk x batch rows: the final states and
+      // the input rows repeated kk times (row r is sample r mod batch); the
+      // pass prepares its own gate matrices for the repeated rows
+      if ((e = launch_replicate(c->state_ws.p, c->jac_state.p, sbytes, kk, s)))
+        return hip_fail(e, "jacobian state copies");
+      const double *xr = nullptr;
+      if (xbytes > 0) {
+        if ((e = launch_replicate(c->jac_x.p, inputs, xbytes, kk, s))) return hip_fail(e, "jacobian input copies");
+        xr = (const double *)c->jac_x.p;
+      }
+      if ((rc = run_backward(c, rows, precision, xr, weights, (double *)c->jac_G.p, c->state_ws.p, nullptr,
+                             (double *)c->jac_gw.p, nullptr, false, s)))
+        return rc;
+    }
+    if ((e = launch_scatter_jac(d, rows, batch, (double *)c->gocc.p, inputs, weights, m0, jac_weights,
+                                jac_inputs, s)))
       return hip_fail(e, "jacobian scatter");
   }
   return QTM_OK;

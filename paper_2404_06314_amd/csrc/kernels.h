@@ -79,9 +79,14 @@ int plain_norm_rows(int n, int B);
 hipError_t launch_norms(const double *part, int B, int rows, int M, double *out, hipStream_t s);
 hipError_t launch_first_nonfinite(const double *x, int64_t nx, const double *w, int64_t nw,
                                   unsigned long long *first, hipStream_t s);
-hipError_t launch_onehot(double *G, int B, int M, int m, hipStream_t s);
-hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, const double *x,
-                              const double *w, int m, double *jw, double *jx, hipStream_t s);
+// Jacobian passes over rows = k x B rows (row r: sample r mod B, observable
+// m0 + r / B): the one-hot upstream gradients, `copies` back-to-back copies of
+// a buffer (bytes a multiple of 8), and the rows' per-sample gradients
+// scattered into [B][M][n_weights] and [B][M][n_inputs].
+hipError_t launch_onehot(double *G, int rows, int B, int M, int m0, hipStream_t s);
+hipError_t launch_replicate(void *dst, const void *src, size_t bytes, int copies, hipStream_t s);
+hipError_t launch_scatter_jac(const DevCircuit &d, int rows, int B, const double *gocc, const double *x,
+                              const double *w, int m0, double *jw, double *jx, hipStream_t s);
 
 template <typename R>
 hipError_t plain_forward(const DevCircuit &d, const HostCircuitInfo &h, int B, const double2 *cs,

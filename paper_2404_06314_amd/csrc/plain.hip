@@ -301,26 +301,37 @@ __global__ void __launch_bounds__(256) k_scatter(const double *__restrict__ gocc
   gx[i] = acc;
 }
 
-// Upstream gradient selecting observable m for every sample.
-__global__ void k_onehot(double *__restrict__ G, int B, int M, int m) {
+// Upstream gradients of a Jacobian pass over `rows` = k x B rows: row r
+// (sample r mod B) selects observable m0 + r / B.
+__global__ void k_onehot(double *__restrict__ G, int rows, int B, int M, int m0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < (int64_t)B * M) G[i] = (int)(i % M) == m ? 1.0 : 0.0;
+  if (i < (int64_t)rows * M) G[i] = (int)(i % M) == m0 + (int)(i / M) / B ? 1.0 : 0.0;
 }
 
-// Row m of the Jacobian: per sample, every weight and input slot sums its
-// rotation occurrences (no sum over the batch).
-__global__ void k_scatter_jac(const double *__restrict__ gocc, int B, int n_occ,
+// `copies` back-to-back copies of n 8-byte words (a batch of states or of
+// input rows, repeated for the rows of a Jacobian pass).
+__global__ void k_replicate(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src, int64_t n,
+                            int copies) {
+  const int64_t total = n * copies, step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step) dst[i] = src[i % n];
+}
+
+// Rows of the Jacobian from a pass over `rows` = k x B rows (row r: sample
+// b = r mod B, observable m = m0 + r / B): per sample, every weight and input
+// slot sums its rotation occurrences (no sum over the batch).
+__global__ void k_scatter_jac(const double *__restrict__ gocc, int rows, int B, int n_occ,
                               const int32_t *__restrict__ w_ptr, const int32_t *__restrict__ w_list,
                               const int32_t *__restrict__ w_fac, int n_w,
                               const int32_t *__restrict__ x_ptr, const int32_t *__restrict__ x_list,
                               const int32_t *__restrict__ x_fac, int n_in,
-                              const double *__restrict__ x, const double *__restrict__ w, int m,
+                              const double *__restrict__ x, const double *__restrict__ w, int m0,
                               int M, double *__restrict__ jw, double *__restrict__ jx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int per = n_w + (jx ? n_in : 0);
-  if (i >= (int64_t)B * per) return;
-  const int b = (int)(i / per), j = (int)(i % per);
-  const double *g = gocc + (int64_t)b * n_occ;
+  if (i >= (int64_t)rows * per) return;
+  const int r = (int)(i / per), j = (int)(i % per);
+  const int b = r % B, m = m0 + r / B;
+  const double *g = gocc + (int64_t)r * n_occ;
   double acc = 0.0;
   if (j < n_w) {
     for (int e = w_ptr[j]; e < w_ptr[j + 1]; ++e) {
@@ -605,18 +616,26 @@ hipError_t launch_scatter(const DevCircuit &d, int B, const double *gocc, const 
   return hipGetLastError();
 }
 
-hipError_t launch_onehot(double *G, int B, int M, int m, hipStream_t s) {
-  k_onehot<<<nb((int64_t)B * M), kThreads, 0, s>>>(G, B, M, m);
+hipError_t launch_onehot(double *G, int rows, int B, int M, int m0, hipStream_t s) {
+  k_onehot<<<nb((int64_t)rows * M), kThreads, 0, s>>>(G, rows, B, M, m0);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_jac(const DevCircuit &d, int B, const double *gocc, const double *x,
-                              const double *w, int m, double *jw, double *jx, hipStream_t s) {
-  const int64_t work = (int64_t)B * (d.n_weights + (jx ? d.n_inputs : 0));
+hipError_t launch_replicate(void *dst, const void *src, size_t bytes, int copies, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / sizeof(uint64_t));
+  if (n == 0 || copies <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n * copies + kThreads - 1) / kThreads, 4096);
+  k_replicate<<<(int)blocks, kThreads, 0, s>>>((uint64_t *)dst, (const uint64_t *)src, n, copies);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_jac(const DevCircuit &d, int rows, int B, const double *gocc, const double *x,
+                              const double *w, int m0, double *jw, double *jx, hipStream_t s) {
+  const int64_t work = (int64_t)rows * (d.n_weights + (jx ? d.n_inputs : 0));
   if (work == 0) return hipSuccess;
-  k_scatter_jac<<<nb(work), kThreads, 0, s>>>(gocc, B, d.n_occ, d.w_ptr, d.w_list, d.w_fac,
+  k_scatter_jac<<<nb(work), kThreads, 0, s>>>(gocc, rows, B, d.n_occ, d.w_ptr, d.w_list, d.w_fac,
                                               d.n_weights, d.x_ptr, d.x_list, d.x_fac, d.n_inputs, x,
-                                              w, m, d.n_obs, jw, jx);
+                                              w, m0, d.n_obs, jw, jx);
   return hipGetLastError();
 }
 

@@ -71,3 +71,66 @@ def test_jacobian_contracts_to_vjp_n20():
     assert_grad_close(np.einsum("bm,bmj->j", G, jw), gw, 1e-4, "contracted J_w", 1e-6)
     for b in range(8):
         assert_grad_close(np.einsum("m,mj->j", G[b], jx[b]), gx[b], 1e-4, f"contracted J_x[{b}]", 1e-6)
+
+
+@pytest.mark.parametrize("mode", ["generic", "jit", "plain"])
+def test_jacobian_chunks(mode):
+    """Observables per adjoint pass (QTM_OPT_JAC_CHUNK) 1, 2, 4 and all 9 of
+    a layered 8-qubit circuit (ragged last passes): every chunking against the
+    oracle; the compiled kernels give the same bits for every chunking (the
+    specialised forward prepares its gate matrices in its own code, which a
+    pass of k > 1 does with the compiled preparation kernel instead)."""
+    import torch
+    import oracle
+    import paper_2404_06314_amd as q
+    rng = np.random.default_rng(91)
+    wl = W.random_workload(rng, W.layered_circuit(8, 3, "ring", extra_masks=(0xFF,)), 5)
+    assert wl.circuit.n_obs == 9
+    ref = oracle.jacobian(wl.circuit, wl.inputs, wl.weights)
+    xt = torch.as_tensor(wl.inputs, dtype=torch.float64, device="cuda:0")
+    wt = torch.as_tensor(wl.weights, dtype=torch.float64, device="cuda:0")
+    got = {}
+    for k in (1, 2, 4, 9):
+        c = q.Circuit.from_workload(wl.circuit)
+        if mode == "plain":
+            c.set_path(q.QTM_PATH_PLAIN)
+        if mode == "jit":
+            c.set_option(q.QTM_OPT_JIT, 1)
+        c.set_option(q.QTM_OPT_JAC_CHUNK, k)
+        ev, jw, jx = c.jacobian(xt, wt, "c64")
+        torch.cuda.synchronize()
+        got[k] = (ev.cpu().numpy(), jw.cpu().numpy(), jx.cpu().numpy())
+        check(got[k], ref, "c64", f"{mode} chunk {k}")
+    for k in (2, 4, 9):
+        for u, v in zip(got[1], got[k]):
+            if mode == "jit":
+                assert np.max(np.abs(u - v)) <= 1e-6 * max(1.0, float(np.max(np.abs(u)))), (mode, k)
+            else:
+                assert np.array_equal(u, v), (mode, k)
+
+
+def test_jacobian_chunks_n20():
+    """n=20 ladder (several sweeps over 256 tiles per sample), two samples:
+    7 observables per pass (passes of 14, 14 and 12 rows) give the same bits
+    as one observable per pass, and contract to the VJP."""
+    import torch
+    import paper_2404_06314_amd as q
+    from gpu_helpers import run_gpu
+    wl = W.config_workload("c3", batch=2)
+    xt = torch.as_tensor(wl.inputs, dtype=torch.float64, device="cuda:0")
+    wt = torch.as_tensor(wl.weights, dtype=torch.float64, device="cuda:0")
+    got = []
+    for k in (1, 7):
+        c = q.Circuit.from_workload(wl.circuit)
+        c.set_option(q.QTM_OPT_JAC_CHUNK, k)
+        ev, jw, jx = c.jacobian(xt, wt, "c64")
+        torch.cuda.synchronize()
+        got.append((ev.cpu().numpy(), jw.cpu().numpy(), jx.cpu().numpy()))
+    for u, v in zip(*got):
+        assert np.array_equal(u, v)
+    ev2, gw, gx = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, "c64")
+    G = wl.grad_out
+    jw, jx = got[1][1], got[1][2]
+    assert_grad_close(np.einsum("bm,bmj->j", G, jw), gw, 1e-4, "contracted J_w", 1e-6)
+    for b in range(2):
+        assert_grad_close(np.einsum("m,mj->j", G[b], jx[b]), gx[b], 1e-4, f"contracted J_x[{b}]", 1e-6)

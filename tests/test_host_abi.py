@@ -360,3 +360,15 @@ def test_plan_io_option(qtm):
     c = qtm.Circuit.from_workload(circ)
     for bad in (0, 65, -3):
         assert lib.qtm_set_option(c.handle, qtm.QTM_OPT_PLAN_IO, bad) == qtm._lib.QTM_ERR_INVALID_ARG
+
+
+def test_jac_chunk_option(qtm):
+    """QTM_OPT_JAC_CHUNK (observables per adjoint pass of qtm_jacobian)
+    accepts 0 (automatic) to 65535 and refuses anything else."""
+    circ = W.config_workload("c1").circuit
+    lib = qtm._lib.load()
+    c = qtm.Circuit.from_workload(circ)
+    for good in (0, 1, 7, 65535):
+        assert lib.qtm_set_option(c.handle, qtm.QTM_OPT_JAC_CHUNK, good) == 0
+    for bad in (-1, 65536):
+        assert lib.qtm_set_option(c.handle, qtm.QTM_OPT_JAC_CHUNK, bad) == qtm._lib.QTM_ERR_INVALID_ARG
