@@ -55,18 +55,22 @@ def kernel_digest(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str, workload: str):
+def recorded_traffic(kernel: str, workload: str, plan: str = ""):
     """HBM bytes per launch of `kernel` on `workload` from the counter summaries
     in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a device copy), or None
-    when none was recorded for the current kernel sources."""
+    when none was recorded for the current kernel sources and, for kernels
+    whose sweeps depend on the sweep plan, for this plan ("io12": zero-skip
+    planning with traffic weight 12, "greedy")."""
     import glob
     digest = kernel_digest(kernel)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
         with open(path) as fh:
             for line in fh:
                 f = line.split()
-                if len(f) == 6 and f[0] == "traffic_bytes_per_launch" and f[1] == kernel \
-                        and f[2] == workload and f[4] == "sources" and f[5] == digest:
+                if len(f) < 6 or f[0] != "traffic_bytes_per_launch" or f[1] != kernel or f[2] != workload \
+                        or f[4] != "sources" or f[5] != digest:
+                    continue
+                if (f[6:] == ["plan", plan]) if plan else len(f) == 6:
                     return int(f[3])
     return None
 
@@ -412,6 +416,9 @@ def main():
         ms_tot, launches = res[kind]
         use_jit = args.jit and args.path == "fused"
         dense_fwd = kind == 0 and args.dense and prec == "c64"
+        # the specialised kernels' sweeps, and so their traffic, depend on the
+        # sweep plan; the compiled ones always take the greedy plan
+        plan_tag = ("greedy" if args.greedy_plan else f"io{args.plan_io}") if use_jit and not dense_fwd else ""
         avg_s = ms_tot / launches / 1e3
         if dense_fwd:
             # one pass per (layer, block of 4 qubits): the state read and
@@ -456,7 +463,7 @@ def main():
             gflop_step / S / (VALU_F32_PEAK_TFLOPS * 1e12)
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "traffic": recorded_traffic(name, W.WORKLOAD_NAMES[args.config]),
+                "traffic": recorded_traffic(name, W.WORKLOAD_NAMES[args.config], plan_tag),
                 "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
                 "bytes_per_launch": int(per_launch_bytes), "sweeps": S,
                 "mfma": {"achieved": round(tfs, 3), "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",

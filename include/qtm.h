@@ -326,13 +326,16 @@ int qtm_timing_read(qtm_circuit_t c, int32_t kind, double *total_ms, int64_t *la
 /* Tune the fused path of c for (batch, precision) on the current device:
  * tile qubits, contiguous low qubits, the compiled generic versus the
  * specialised sweep kernels (QTM_OPT_JIT), for the fastest specialised
- * configuration also the greedy sweep plan (QTM_OPT_GREEDY_PLAN), and for
+ * configuration also the greedy sweep plan (QTM_OPT_GREEDY_PLAN) and the
+ * zero-skip plans with traffic weights 8 and 16 (QTM_OPT_PLAN_IO), and for
  * complex64 layered CZ-chain circuits the dense-block forward
  * (QTM_OPT_DENSE_BLOCKS).  Every candidate must reproduce
  * the per-gate complex128 result on seeded synthetic inputs within the
  * precision's tolerances (<Z> 1e-5 absolute and gradients 1e-4 relative for
  * complex64; 1e-12 / 1e-10 for complex128) before it is timed; the fastest
- * is installed with qtm_set_option.  flags bit 0: read and update the JSON
+ * is installed with qtm_set_option (among the candidates within 3% of it:
+ * the most contiguous low qubits, then the larger tile, then the default
+ * sweep plan).  flags bit 0: read and update the JSON
  * cache ($QTM_AUTOTUNE_CACHE, else ~/.cache/qtm_autotune.json), keyed by the
  * circuit's gates and observables, batch, precision and GPU architecture.
  * report (may be NULL): JSON summary of the candidates (truncated to len - 1
