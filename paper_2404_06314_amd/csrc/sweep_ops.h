@@ -86,21 +86,14 @@ __device__ __forceinline__ void prep_block(const int32_t *__restrict__ r, const 
     if (e[1] == 3) return w[e[3]] * x[e[2]];
     return e[1] == 1 ? x[e[2]] : w[e[2]];
   };
-  MD U;
-  U.m[0][0] = {1, 0}; U.m[0][1] = {0, 0}; U.m[1][0] = {0, 0}; U.m[1][1] = {1, 0};
-  for (int g = 0; g < ng; ++g) U = md_mul(md_gate(r[2 + kBlkGate * g], ang(g)), U);
-  M2<R> o;
-  o.a = {(R)U.m[0][0].x, (R)U.m[0][0].y};
-  o.b = {(R)U.m[0][1].x, (R)U.m[0][1].y};
-  o.c = {(R)U.m[1][0].x, (R)U.m[1][0].y};
-  o.d = {(R)U.m[1][1].x, (R)U.m[1][1].y};
-  *mat = o;
-  if (!coef) return;
+  // From the last gate back to the first: when rotation g's coefficients
+  // are taken, A is the product of the gates after it, and at the end A is
+  // the block's unitary (one sine and cosine per gate).
   MD A;
   A.m[0][0] = {1, 0}; A.m[0][1] = {0, 0}; A.m[1][0] = {0, 0}; A.m[1][1] = {1, 0};
   for (int g = ng - 1; g >= 0; --g) {
     const int32_t *e = r + 2 + kBlkGate * g;
-    if (e[4] >= 0) {
+    if (coef && e[4] >= 0) {
       MD P = md_mul(md_mul(A, md_pauli(e[0])), md_adj(A));
       double *cf = coef + (int64_t)e[4] * 3;
       cf[0] = P.m[1][0].x;
@@ -109,6 +102,12 @@ __device__ __forceinline__ void prep_block(const int32_t *__restrict__ r, const 
     }
     A = md_mul(A, md_gate(e[0], ang(g)));
   }
+  M2<R> o;
+  o.a = {(R)A.m[0][0].x, (R)A.m[0][0].y};
+  o.b = {(R)A.m[0][1].x, (R)A.m[0][1].y};
+  o.c = {(R)A.m[1][0].x, (R)A.m[1][0].y};
+  o.d = {(R)A.m[1][1].x, (R)A.m[1][1].y};
+  *mat = o;
 }
 
 // ---------------------------------------------------------------------------
