@@ -41,7 +41,9 @@ struct JitSpec {
 // qtm_jit_fwd / qtm_jit_bwd with the tile configuration appended
 // (`_t<kt>l<klo>`, plus `_c128` for complex128), so that profiles tell
 // configurations apart.
-std::string jit_source(const JitSpec &sp, int dir, int sweep);
+// share = false: the backward keeps separate LDS tiles for psi and lambda
+// (the fallback for kernels that the shared form makes spill).
+std::string jit_source(const JitSpec &sp, int dir, int sweep, bool share = true);
 std::string jit_kernel_name(const JitSpec &sp, int dir);
 
 // Work of a specialised sweep restricted to the amplitudes that can be
@@ -61,7 +63,7 @@ struct SweepLive {
 SweepLive sweep_live(const JitSpec &sp, int dir, int sweep);
 
 // Static LDS bytes of that kernel.
-size_t jit_lds_bytes(const JitSpec &sp, int dir, int sweep);
+size_t jit_lds_bytes(const JitSpec &sp, int dir, int sweep, bool share = true);
 
 struct JitKernel {
   std::vector<char> code;  // code object
