@@ -77,8 +77,9 @@ def test_random_circuits(precision, seed):
 def test_c3_full_batch(precision):
     """n=20, 8 layers, CZ ladder, batch 64 against the oracle fixture; two
     runs give the same bits; the specialised kernels spill at most a few
-    registers (the backward kernels sit at the 256-register limit that two
-    workgroups per compute unit allow)."""
+    registers (the backward kernels are built for three workgroups per
+    compute unit, 168 registers, and rebuilt with two LDS tiles if they
+    would spill)."""
     path = os.path.join(GOLDEN, "oracle_c3_b64.npz")
     d = np.load(path, allow_pickle=False)
     ref = (d["expvals"], d["grad_w"], d["grad_x"])
