@@ -75,8 +75,11 @@ __global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) 
 // ---------------------------------------------------------------------------
 // backward sweep
 
+// (three workgroups per compute unit for the matrix-core kernels, which
+// pass psi and lambda through one LDS tile)
 template <typename R, int KT>
-__global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? 2 : 1) k_fused_bwd(BwdArgs a) {
+__global__ void __launch_bounds__(1 << (KT - kRegBits), sizeof(R) == 4 ? (KT - kRegBits >= 6 ? 3 : 2) : 1)
+    k_fused_bwd(BwdArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr bool FULL = true;
   constexpr int ntb = KT - kRegBits;
@@ -130,8 +133,10 @@ template <typename R, int KT>
 static size_t bwd_lds(int ngs) {
   constexpr int NT = 1 << (KT - kRegBits);
   constexpr int NW = (NT + 63) / 64;
+  // one tile for psi and lambda in turn in the matrix-core kernels, else two
+  constexpr int tiles = sizeof(R) == 4 && NT >= 64 ? 1 : 2;
   const size_t acc = (size_t)ngs * 3 * NW;
-  return (2 * sizeof(Cx<R>) << KT) + sizeof(M2<R>) * kMaxSweepBlocks + sizeof(double) * (2 * NW + acc);
+  return (tiles * sizeof(Cx<R>) << KT) + sizeof(M2<R>) * kMaxSweepBlocks + sizeof(double) * (2 * NW + acc);
 }
 
 template <typename K>

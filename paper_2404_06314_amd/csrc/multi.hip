@@ -172,7 +172,9 @@ __global__ void __launch_bounds__(kMultiNT, 2) k_multi_fwd(MultiStatic ms, Multi
   }
 }
 
-__global__ void __launch_bounds__(kMultiNT, 2) k_multi_bwd(MultiStatic ms, MultiIO io) {
+// (three workgroups per compute unit: psi and lambda pass through one LDS
+// tile in turn)
+__global__ void __launch_bounds__(kMultiNT, 3) k_multi_bwd(MultiStatic ms, MultiIO io) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_tk;
   using R = float;
@@ -187,7 +189,7 @@ __global__ void __launch_bounds__(kMultiNT, 2) k_multi_bwd(MultiStatic ms, Multi
     const cptr<int64_t> I = as_const(ms.items) + (int64_t)item * MI_WORDS;
     const int ntiles = (int)I[MI_NTILES], kt = (int)I[MI_KT];
     if (sweep > 0) multi_wait(done + item, sweep * ntiles, ms.ctr + 1);
-    if (kt < KT) zero_surplus(smem, kt, 2);
+    if (kt < KT) zero_surplus(smem, kt, 1);
     BwdArgs a;
     a.prog = ms.code + I[MI_CODE];
     a.thr = ms.thr + I[MI_THR];
@@ -290,7 +292,8 @@ size_t fwd_lds_bytes(int max_m) {
 }
 size_t bwd_lds_bytes(int max_gs) {
   constexpr int NW = (kMultiNT + 63) / 64;
-  return (2 * sizeof(Cx<float>) << kMultiKT) + sizeof(M2<float>) * kMaxSweepBlocks +
+  // one tile: psi and lambda pass through it in turn
+  return (sizeof(Cx<float>) << kMultiKT) + sizeof(M2<float>) * kMaxSweepBlocks +
          sizeof(double) * (size_t)(NW + (size_t)max_gs * 3 * NW);
 }
 
