@@ -136,10 +136,11 @@ def test_matrix_core_random_cz_heavy(seed):
 
 
 def test_c3_runner_up_configuration():
-    """The n=20 workload at tile 11 / 4 low qubits (specialised sweeps), the
-    autotuner's second choice, against the oracle fixture.  The configuration
-    the benchmark times (tile 12 / 5 low qubits) is the default one, which
-    test_c3_full_batch runs."""
+    """The n=20 workload at tile 11 / 4 low qubits (specialised sweeps), one
+    of the autotuner's candidates, against the oracle fixture.  The
+    configuration the benchmark times after tuning (tile 12 / 4 low qubits,
+    zero-skip plan) runs in test_c3_sweep_plans; the library's default tile
+    (12 / 5 low qubits) in test_c3_full_batch."""
     d = np.load(os.path.join(GOLDEN, "oracle_c3_b64.npz"), allow_pickle=False)
     wl = W.config_workload("c3")
     got = run_gpu(wl.circuit, wl.inputs, wl.weights, wl.grad_out, "c64",
