@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--renorm", type=int, default=0,
                     help="periodic renormalisation every R sweeps (QTM_OPT_RENORM); implies --autotune 0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain per-gate complex128 step timed beside the fused one")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--cpu-samples", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -473,6 +475,12 @@ def main():
         log(f"{name}: HBM {gbs / HBM_PEAK_GBS:.3f} of peak, matrix cores {tfs / MFMA_F32_PEAK_TFLOPS:.3f}, "
             f"serial issue floor {floor_s * 1e6:.1f} us ({floor_s / avg_s:.3f} of the launch)")
 
+    # the plain per-sample complex128 form (one launch per gate) beside the
+    # fused one: its step time, and how far the fused result is from it
+    plain = None
+    if args.path == "fused" and prec == "c64" and circ.n <= 20 and not args.no_plain:
+        plain = plain_c128_beside(c, circ, x, w, G, state, B, prec, q)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
@@ -507,7 +515,51 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if plain is not None:
+        out["plain_c128"] = plain
     print(json.dumps(out), flush=True)
+
+
+def plain_c128_beside(c, circ, x, w, G, state, B, prec, q, steps=2):
+    """One forward + VJP step of the plain per-gate complex128 kernels on the
+    same inputs (timed over `steps` after one warm-up), and the largest
+    differences of the fused result from it: absolute on <Z>, and per
+    gradient vector relative to that vector's largest entry."""
+    import torch
+    cp = q.Circuit.from_workload(circ)
+    cp.set_path(q.QTM_PATH_PLAIN)
+    st = cp.alloc_state(B, "c128")
+
+    def run(cc, p, s):
+        ev = cc.forward(x, w, p, state=s)
+        gw, gx = cc.backward(x, w, G, p, state=s)
+        return ev, gw, gx
+
+    ref = run(cp, "c128", st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run(cp, "c128", st)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    got = run(c, prec, state)
+    torch.cuda.synchronize()
+    ev_err = float((got[0] - ref[0]).abs().max())
+
+    def rel(a, b):
+        scale = float(b.abs().max()) if b.numel() else 0.0
+        return float((a - b).abs().max()) / scale if scale > 0 else 0.0
+
+    gx_err = max((rel(got[2][i], ref[2][i]) for i in range(B)), default=0.0) if got[2] is not None else None
+    out = {"ms_per_step": round(ms, 2), "value": round(B / (ms / 1e3), 2), "unit": "circuit evals/s",
+           "dtype": "c128", "path": "per-gate", "steps": steps,
+           "fused_c64_max_abs_err_expval": ev_err, "fused_c64_max_rel_err_grad_w": rel(got[1], ref[1]),
+           "fused_c64_max_rel_err_grad_x": gx_err}
+    log(f"plain complex128 per-gate form: {ms:.1f} ms/step; fused complex64 against it: "
+        f"<Z> {ev_err:.2e} abs, dL/dw {out['fused_c64_max_rel_err_grad_w']:.2e} rel, dL/dx {gx_err:.2e} rel")
+    del st
+    cp.close()
+    return out
 
 
 # The paper's benchmark shapes for its Eq. (7) ansatz (batch 48 throughout):
